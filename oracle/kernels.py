@@ -1,0 +1,108 @@
+"""Kernel entry functions K(x^i, y^j) of the operators the butterfly compresses.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Every entry is evaluated on demand from integer multi-indices, as section 2
+assumes (the operator tensor is never formed; any entry costs O(1)).  All
+arithmetic is FP64 / complex128.
+
+Index conventions (one per mode, 0-based):
+  target multi-index i in [0, n)^d, source multi-index j in [0, n)^d.
+
+Operators
+---------
+fourier    K = exp(-2 pi i x.k) with x = i/n (spatial target) and k = j - n/2
+           (integer frequency).  This is the uniform DFT of section 4.3 with
+           the roles of the two grids swapped and the sign flipped; the phase
+           x.k = (i.k)/n is reduced exactly in integers before the
+           exponential.
+helmholtz  K = exp(+i w rho)/rho, rho = |x - y|, x = i/n, y = j/n + (2,0,0):
+           two unit cubes whose centres are 2 apart along x1 (section 4.1,
+           with the offset along x1 and the +i w rho sign).
+radon      K = exp(2 pi i (x.k + sqrt(c1(x)^2 k1^2 + c2(x)^2 k2^2))), d = 2,
+           x = i/n, k = j - n/2, c1 = (a + b sin(2 pi x1) sin(2 pi x2))/den,
+           c2 = (a + b cos(2 pi x1) cos(2 pi x2))/den (equation for the 2-D
+           generalized Radon transform in section 4.2; the paper uses
+           a=2, b=1, den=16, the workloads here use den=3).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+FOURIER = 0
+HELMHOLTZ = 1
+RADON = 2
+
+KIND_NAMES = {FOURIER: "fourier", HELMHOLTZ: "helmholtz", RADON: "radon"}
+
+
+@dataclass(frozen=True)
+class Operator:
+    """A discretised oscillatory integral operator on an n^d x n^d grid."""
+
+    kind: int
+    d: int
+    n: int
+    omega: float = 0.0          # Helmholtz wavenumber (ignored otherwise)
+    radon_a: float = 2.0        # Radon speed constants (ignored otherwise)
+    radon_b: float = 1.0
+    radon_den: float = 3.0
+
+    def entries(self, ti: np.ndarray, sj: np.ndarray) -> np.ndarray:
+        """K(x^i, y^j) for broadcastable integer arrays of shape (..., d)."""
+        ti = np.asarray(ti, dtype=np.int64)
+        sj = np.asarray(sj, dtype=np.int64)
+        if self.kind == FOURIER:
+            return fourier_entries(self.n, ti, sj)
+        if self.kind == HELMHOLTZ:
+            return helmholtz_entries(self.n, self.omega, ti, sj)
+        if self.kind == RADON:
+            return radon_entries(self.n, ti, sj, self.radon_a, self.radon_b,
+                                 self.radon_den)
+        raise ValueError(f"unknown kernel kind {self.kind}")
+
+
+def helmholtz_omega(n: int) -> float:
+    """Wavenumber giving 4 points per wavelength on a grid of spacing 1/n.
+
+    Section 4.1 fixes 2 pi n / omega = 4, i.e. omega = pi n / 2; each unit
+    cube then spans n/4 wavelengths per direction.
+    """
+    return np.pi * n / 2.0
+
+
+def fourier_entries(n: int, ti: np.ndarray, sj: np.ndarray) -> np.ndarray:
+    # x.k = (i.k)/n with k = j - n/2; exp(-2 pi i x.k) depends on i.k mod n
+    # only, so the phase is reduced exactly in integer arithmetic.
+    k = sj - n // 2
+    p = np.sum(ti * k, axis=-1) % n
+    return np.exp(-2j * np.pi * (p.astype(np.float64) / n))
+
+
+def helmholtz_entries(n: int, omega: float, ti: np.ndarray,
+                      sj: np.ndarray) -> np.ndarray:
+    d = ti.shape[-1]
+    offset = np.zeros(d)
+    offset[0] = 2.0
+    diff = ti.astype(np.float64) / n - (sj.astype(np.float64) / n + offset)
+    rho = np.sqrt(np.sum(diff * diff, axis=-1))
+    return np.exp(1j * omega * rho) / rho
+
+
+def radon_entries(n: int, ti: np.ndarray, sj: np.ndarray, a: float, b: float,
+                  den: float) -> np.ndarray:
+    if ti.shape[-1] != 2:
+        raise ValueError("the Radon operator here is two-dimensional")
+    x = ti.astype(np.float64) / n
+    k = (sj - n // 2).astype(np.float64)
+    s1 = np.sin(2 * np.pi * x[..., 0])
+    s2 = np.sin(2 * np.pi * x[..., 1])
+    c1 = np.cos(2 * np.pi * x[..., 0])
+    c2 = np.cos(2 * np.pi * x[..., 1])
+    cc1 = (a + b * s1 * s2) / den
+    cc2 = (a + b * c1 * c2) / den
+    phase = np.sum(x * k, axis=-1) + np.sqrt(cc1 ** 2 * k[..., 0] ** 2 +
+                                             cc2 ** 2 * k[..., 1] ** 2)
+    return np.exp(2j * np.pi * phase)

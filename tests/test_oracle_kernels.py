@@ -1,0 +1,134 @@
+"""Pins of the oracle's kernel entries and dense reference routes.
+
+The operator definitions are fixed by the paper (sections 2, 4.1-4.3 and
+the workload definitions).  Each check here compares two independent routes
+to the same quantity, or a route to a closed form at special points.
+"""
+import numpy as np
+import pytest
+
+from oracle import dense, kernels
+from oracle.kernels import Operator
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def _rand(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("d,n", [(2, 8), (2, 16), (3, 8)])
+def test_fourier_fft_equals_brute(d, n):
+    op = Operator(kernels.FOURIER, d, n)
+    f = _rand((2,) + (n,) * d, 1)
+    np.testing.assert_allclose(dense.apply_fourier_fft(n, d, f),
+                               dense.apply_brute(op, f), rtol=0, atol=1e-10)
+    g = _rand((2,) + (n,) * d, 2)
+    np.testing.assert_allclose(dense.adjoint_fourier_fft(n, d, g),
+                               dense.adjoint_brute(op, g), rtol=0, atol=1e-10)
+
+
+def test_fourier_plane_waves():
+    # A unit impulse at frequency k0 gives the plane wave exp(-2 pi i x.k0);
+    # the conjugate plane wave at x_{i0} gives n^d times an impulse at i0.
+    n, d = 16, 2
+    j0 = (3, 13)
+    k0 = np.array(j0) - n // 2
+    f = np.zeros((n, n), complex)
+    f[j0] = 1.0
+    u = dense.apply_fourier_fft(n, d, f)[0]
+    i = dense.grid_indices(n, d).reshape(n, n, d)
+    expect = np.exp(-2j * np.pi * (i @ k0) / n)
+    np.testing.assert_allclose(u, expect, atol=1e-12)
+    i0 = np.array([5, 9])
+    k = dense.grid_indices(n, d) - n // 2
+    f2 = np.exp(2j * np.pi * (k @ i0) / n).reshape(n, n)
+    u2 = dense.apply_brute(Operator(kernels.FOURIER, d, n), f2)[0]
+    expect2 = np.zeros((n, n), complex)
+    expect2[tuple(i0)] = n ** d
+    np.testing.assert_allclose(u2, expect2, atol=1e-9)
+
+
+def test_fourier_phase_is_periodic_in_k():
+    # exp(-2 pi i (i.k)/n) is unchanged by k -> k + n e_m (integer reduction)
+    n = 32
+    ti = np.array([[7, 30]])
+    a = kernels.fourier_entries(n, ti, np.array([[1, 2]]))
+    b = kernels.fourier_entries(n, ti, np.array([[1 + n, 2]]))
+    np.testing.assert_allclose(a, b, atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_helmholtz_fft_convolution_equals_brute(n):
+    op = Operator(kernels.HELMHOLTZ, 3, n, omega=kernels.helmholtz_omega(n))
+    f = _rand((2, n, n, n), 3)
+    np.testing.assert_allclose(dense.apply_helmholtz_fft(op, f),
+                               dense.apply_brute(op, f), rtol=0, atol=1e-10)
+    g = _rand((2, n, n, n), 4)
+    np.testing.assert_allclose(dense.adjoint_helmholtz_fft(op, g),
+                               dense.adjoint_brute(op, g), rtol=0, atol=1e-10)
+
+
+def test_helmholtz_special_values():
+    # i = j = 0: rho = 2 exactly (the offset of the second cube).  With n = 8
+    # the wavenumber pi n / 2 = 4 pi makes omega rho = 8 pi, so K = 1/2.
+    n = 8
+    om = kernels.helmholtz_omega(n)
+    assert om == pytest.approx(4 * np.pi)
+    z = np.zeros((1, 3), np.int64)
+    assert kernels.helmholtz_entries(n, om, z, z)[0] == pytest.approx(0.5, abs=1e-14)
+    # i = (n, 0, 0)-ish geometry: target x1 = 0, source x1 = 2 + 4/8, rho = 2.5
+    ti = np.array([[0, 3, 5]])
+    sj = np.array([[4, 3, 5]])
+    val = kernels.helmholtz_entries(n, om, ti, sj)[0]
+    assert abs(val) == pytest.approx(1 / 2.5, abs=1e-14)
+    assert np.angle(val) == pytest.approx(np.angle(np.exp(1j * om * 2.5)), abs=1e-12)
+    # omega = 0 is the Newton potential 1/rho (real, positive)
+    v0 = kernels.helmholtz_entries(n, 0.0, ti, sj)[0]
+    assert v0.imag == 0.0 and v0.real == pytest.approx(0.4, abs=1e-15)
+
+
+def test_radon_special_points():
+    n = 16
+    z = np.zeros((1, 2), np.int64)
+    # at x = 0: c1 = 2/3, c2 = 1, so K(0, k) = exp(2 pi i sqrt(4/9 k1^2 + k2^2))
+    for k2 in (-5, 0, 3, 7):
+        sj = np.array([[n // 2, n // 2 + k2]])
+        assert kernels.radon_entries(n, z, sj, 2, 1, 3)[0] == pytest.approx(1.0, abs=1e-12)
+    for k1 in (-6, 3, 6):   # (2/3)|k1| is an integer when 3 divides k1
+        sj = np.array([[n // 2 + k1, n // 2]])
+        assert kernels.radon_entries(n, z, sj, 2, 1, 3)[0] == pytest.approx(1.0, abs=1e-12)
+    sj = np.array([[n // 2 + 1, n // 2]])
+    assert kernels.radon_entries(n, z, sj, 2, 1, 3)[0] == pytest.approx(
+        np.exp(2j * np.pi * 2 / 3), abs=1e-12)
+
+
+def test_radon_without_speed_terms_is_an_inverse_dft():
+    # with a = b = 0 both speeds vanish and K = exp(+2 pi i x.k): an inverse
+    # DFT of the input re-indexed by k mod n.
+    n, d = 16, 2
+    op = Operator(kernels.RADON, d, n, radon_a=0.0, radon_b=0.0)
+    f = _rand((1, n, n), 5)
+    expect = np.fft.ifftn(np.fft.ifftshift(f, axes=(1, 2)), axes=(1, 2)) * n ** d
+    np.testing.assert_allclose(dense.apply_brute(op, f), expect, atol=1e-10)
+
+
+@pytest.mark.parametrize("kind,d,n", [(kernels.FOURIER, 2, 8),
+                                      (kernels.HELMHOLTZ, 3, 4),
+                                      (kernels.RADON, 2, 8)])
+def test_dense_adjoint_identity(kind, d, n):
+    om = kernels.helmholtz_omega(n) if kind == kernels.HELMHOLTZ else 0.0
+    op = Operator(kind, d, n, omega=om)
+    f = _rand((1,) + (n,) * d, 6)
+    g = _rand((1,) + (n,) * d, 7)
+    lhs = np.vdot(g, dense.apply_brute(op, f))
+    rhs = np.vdot(dense.adjoint_brute(op, g), f)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_probe_error_metric_zero_for_exact_apply():
+    n, d = 8, 2
+    op = Operator(kernels.FOURIER, d, n)
+    err = dense.probe_error(op, lambda fe: dense.apply_fourier_fft(n, d, fe))
+    assert err < 1e-13
