@@ -1,0 +1,208 @@
+/*
+ * tb.h -- C ABI of the MI355X tensor butterfly library (libtb.so).
+ *
+ * The library builds and applies the tensor butterfly factorisation of a
+ * discretised d-dimensional oscillatory integral operator K with n^d target
+ * and n^d source points (Kielstra, Shi, Luo, Qian, Liu, "A Linear-complexity
+ * Tensor Butterfly Algorithm for Compressing High-dimensional Oscillatory
+ * Integral Operators", arXiv 2411.03029):
+ *
+ *   tb_construct      Algorithm 1 (construction) on the GPU: FP64 kernel
+ *                     entries at proxy indices, column interpolative
+ *                     decompositions (section 2.1) by FP64 Householder QR,
+ *                     nested over levels (section 3.2), and the middle-level
+ *                     cores K(tbar, sbar).
+ *   tb_apply          Algorithm 2 (contraction): u = K_BF f.
+ *   tb_apply_adjoint  the conjugate-transposed contraction: v = K_BF^H g.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Status:    every call returns a tb_status (TB_OK = 0) and never aborts;
+ *            tb_last_error() returns a thread-local message for the last
+ *            failure on the calling thread.
+ * Arrays:    f, u, g, v are caller-owned DEVICE pointers, contiguous, layout
+ *            (nrhs, n, ..., n) row-major (mode d fastest), complex values
+ *            interleaved (re, im).  Element type by tb_dtype below.  Input
+ *            and output must not overlap.
+ * Streams:   work is enqueued on the caller's HIP stream (hipStream_t passed
+ *            as void*, NULL = default stream) and the calls return without
+ *            synchronising, except where a call says otherwise.  A plan owns
+ *            its workspace: one stream at a time per plan.
+ * Ownership: a plan owns all device memory for factors, cores and
+ *            workspace; tb_destroy frees it.
+ * Indexing:  target multi-index i and source multi-index j in [0, n)^d.
+ *            Fourier: K = exp(-2 pi i x.k), x = i/n, k = j - n/2.
+ *            Helmholtz (d = 3): K = exp(+i omega rho)/rho, rho = |x - y|,
+ *              x = i/n, y = j/n + (2, 0, 0)  (two unit cubes, centres 2 apart).
+ *            Radon (d = 2): K = exp(2 pi i (x.k + sqrt(c1^2 k1^2 + c2^2 k2^2)))
+ *              with x = i/n, k = j - n/2, c1 = (a + b sin 2pi x1 sin 2pi x2)/den,
+ *              c2 = (a + b cos 2pi x1 cos 2pi x2)/den  (section 4.2).
+ */
+#ifndef TB_H
+#define TB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TB_OK = 0,
+  TB_ERR_INVALID_ARG = 1,  /* bad argument; nothing was launched            */
+  TB_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement   */
+  TB_ERR_OOM = 3,          /* device allocation failed or exceeded the cap   */
+  TB_ERR_HIP = 4,          /* a HIP runtime call failed (message attached)   */
+  TB_ERR_NUMERIC = 5,      /* an ID rank exceeded the allowed maximum        */
+  TB_ERR_IO = 6            /* plan file missing, truncated or corrupted      */
+} tb_status;
+
+typedef enum {
+  TB_KERNEL_FOURIER = 0,
+  TB_KERNEL_HELMHOLTZ = 1,
+  TB_KERNEL_RADON = 2
+} tb_kernel;
+
+/* Element type of the apply.  TB_C128: complex128 arrays, FP64 factors,
+ * cores and accumulation.  TB_C64: complex64 arrays, FP32 everything.
+ * TB_CBF16: complex64 arrays, BF16 cores, FP32 factors and accumulation. */
+typedef enum { TB_C128 = 0, TB_C64 = 1, TB_CBF16 = 2 } tb_dtype;
+
+#define TB_STORE_C128 (1u << TB_C128)
+#define TB_STORE_C64 (1u << TB_C64)
+#define TB_STORE_CBF16 (1u << TB_CBF16)
+
+typedef struct tb_plan_s* tb_plan;
+
+/* Construction options.  A zero-initialised struct (or NULL) gives the
+ * defaults listed per field. */
+typedef struct {
+  int leaf_size;        /* C_b, indices per leaf per mode; 0 -> 8            */
+  int lt_override;      /* 0 -> target middle level floor(L/2); v > 0 sets
+                           it to v - 1 (source middle level = L - that)     */
+  int proxy_pair;       /* samples of the paired mode per ID column; 0 -> 2;
+                           < 0 -> every index of the node                  */
+  int proxy_other;      /* samples of every other mode; 0 -> 2*leaf (d = 2)
+                           or 4 (d = 3); < 0 -> every index of the node     */
+  double id_tol_scale;  /* ID tolerance = id_tol_scale * tol; 0 -> 0.3      */
+  unsigned store_mask;  /* core precisions kept (TB_STORE_*); 0 -> C64      */
+  int max_rank;         /* > 0: an ID rank above it fails with
+                           TB_ERR_NUMERIC; 0 -> no limit                   */
+  size_t max_device_bytes; /* > 0: cap on the plan's device memory; a plan
+                              that needs more fails with TB_ERR_OOM         */
+  int radon_custom;     /* 1: use radon_a/b/den below; 0 -> a=2, b=1, den=3 */
+  double radon_a, radon_b, radon_den;
+} tb_options;
+
+/* Summary of a plan (tb_plan_info). */
+typedef struct {
+  int kind, d, leaf;
+  long long n;
+  int L, Lt, Ls;              /* levels; target / source middle levels      */
+  int r_min, r_max;           /* over all IDs                               */
+  long long n_ids;            /* number of IDs (source + target)            */
+  long long n_pairs;          /* middle-level (t, s) pairs                  */
+  long long factor_entries;   /* true-rank V, W, U, P entries               */
+  long long core_entries;     /* true-rank core entries, sum of R_T * R_S    */
+  long long core_rows;        /* sum over pairs of R_T                      */
+  long long core_cols;        /* sum over pairs of R_S                      */
+  long long apply_cmacs;      /* complex multiply-adds of one apply per RHS,
+                                 counted from the true ranks                */
+  double omega, tol, eps_id;
+  unsigned store_mask;
+  size_t device_bytes;        /* factor + core memory held by the plan      */
+  double construct_ms;        /* wall time of tb_construct (0 after load)   */
+} tb_plan_info_t;
+
+/* Build the factorisation on the GPU (Algorithm 1).
+ *   kind, d:  operator (Fourier d in {2,3}; Helmholtz d = 3; Radon d = 2).
+ *   n:        points per direction; n = leaf * 2^L with L >= 0.
+ *   omega:    Helmholtz wavenumber (> 0); ignored for Fourier and Radon.
+ *   tol:      requested relative accuracy in (0, 1); every ID runs at
+ *             id_tol_scale * tol (section 2.1 Frobenius criterion).
+ *   opt:      options or NULL.  hip_stream: stream for the GPU work.
+ *   out:      receives the plan.
+ * Synchronises with the device once per tree level (ranks are read back to
+ * size the next level).  Errors: TB_ERR_INVALID_ARG for a bad d/n/tol/omega,
+ * TB_ERR_UNSUPPORTED for a (kind, d) pair not built, TB_ERR_NUMERIC if an ID
+ * exceeds opt->max_rank, TB_ERR_OOM, TB_ERR_HIP. */
+tb_status tb_construct(tb_kernel kind, int d, long long n, double omega,
+                       double tol, const tb_options* opt, void* hip_stream,
+                       tb_plan* out);
+
+/* u = K_BF f (Algorithm 2): f and u hold nrhs >= 1 right-hand sides.
+ * io selects the element type (the plan must hold cores of that precision,
+ * see store_mask). */
+tb_status tb_apply(tb_plan p, const void* f, void* u, long long nrhs,
+                   tb_dtype io, void* hip_stream);
+
+/* v = K_BF^H g: the butterfly with every factor conjugate-transposed and
+ * the order reversed (not in the paper; the adjoint of Algorithm 2). */
+tb_status tb_apply_adjoint(tb_plan p, const void* g, void* v, long long nrhs,
+                           tb_dtype io, void* hip_stream);
+
+/* Fill *info.  Host only; no device work. */
+tb_status tb_plan_info(tb_plan p, tb_plan_info_t* info);
+
+/* Write / read the plan file (format below).  Save synchronises the device
+ * (cores are copied back); load synchronises once it has uploaded.  Load
+ * takes the cores from the file when it holds them, otherwise evaluates
+ * them on the GPU; recompute_cores = 1 always evaluates them on the GPU.
+ * opt supplies store_mask and max_device_bytes (NULL -> defaults). */
+tb_status tb_plan_save(tb_plan p, const char* path);
+tb_status tb_plan_load(const char* path, const tb_options* opt,
+                       int recompute_cores, void* hip_stream, tb_plan* out);
+
+/* Release a plan and everything it owns (NULL is ignored).  Synchronises
+ * the device before freeing. */
+void tb_destroy(tb_plan p);
+
+/* Kernel stages of the apply, for per-stage timing. */
+typedef enum {
+  TB_STAGE_SRC_LEAF = 0,      /* V: input blocks -> skeletons (forward)        */
+  TB_STAGE_SRC_TRANSFER,      /* W: level l-1 -> level l (forward)            */
+  TB_STAGE_CORE,              /* K(tbar, sbar) x F (forward)                  */
+  TB_STAGE_TGT_TRANSFER,      /* P^T, summed into the parents (forward)       */
+  TB_STAGE_TGT_LEAF,          /* U^T: skeletons -> output blocks (forward)    */
+  TB_STAGE_TGT_LEAF_ADJ,      /* conj(U) (adjoint)                            */
+  TB_STAGE_TGT_TRANSFER_ADJ,  /* conj(P) (adjoint)                            */
+  TB_STAGE_CORE_ADJ,          /* K(tbar, sbar)^H (adjoint)                    */
+  TB_STAGE_SRC_TRANSFER_ADJ,  /* W^H, summed into the parents (adjoint)       */
+  TB_STAGE_SRC_LEAF_ADJ,      /* V^H (adjoint)                                */
+  TB_NSTAGES
+} tb_stage;
+
+/* Per-stage timing.  While enabled, tb_apply and tb_apply_adjoint record a
+ * HIP event pair around every kernel they launch, on the caller's stream.
+ * tb_plan_stage_times waits for those events, adds their durations (ms) and
+ * launch counts per stage into ms[TB_NSTAGES] and launches[TB_NSTAGES]
+ * (either may be NULL) and clears the record.  Timing adds an event record
+ * per launch; leave it disabled for throughput runs. */
+tb_status tb_plan_set_timing(tb_plan p, int enable);
+tb_status tb_plan_stage_times(tb_plan p, double* ms, long long* launches);
+
+const char* tb_last_error(void);
+const char* tb_status_string(tb_status s);
+
+/* Plan file, version 1 (little endian, no padding between fields):
+ *   char[8]    "TBPLAN01"
+ *   int32[8]   kind, d, n, leaf, L, Lt, Ls, has_cores
+ *   float64[5] omega, tol, radon_a, radon_b, radon_den
+ *   source IDs, for l = 0..Lt, s (level Ls, flat), tau (level l, flat),
+ *     k = 0..d-1, nu = 0..2^(Lt-l)-1:   int32 r, int32 c, int32 skel[r],
+ *     complex128 X[r][c]
+ *   target IDs, for l = 0..Ls, t (level Lt), nu (level l), k, tau < 2^(Ls-l):
+ *     int32 r, int32 c, int32 skel[r], complex128 X[r][c]
+ *   cores if has_cores, for t, s: complex128 C[R_T][R_S] (row-major)
+ *   uint32 CRC-32 (IEEE) of all preceding bytes, uint32 0
+ * A multi-set (b_1..b_d) at level l has flat index sum_k b_k 2^(l(d-1-k)).
+ * skel holds global per-mode indices in pivot order; X (r x c) satisfies
+ * A ~= A(:, J) X for the sampled unfolding; its columns are the leaf's
+ * indices (l = 0) or the first child's skeleton then the second's. */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TB_H */

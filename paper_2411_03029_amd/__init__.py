@@ -1,0 +1,177 @@
+"""MI355X tensor butterfly: construct and apply compressed oscillatory
+integral operators (arXiv 2411.03029) through libtb.so.
+
+PyTorch supplies device memory and the current stream; every computation
+runs in the library's HIP kernels.
+
+    import paper_2411_03029_amd as tb
+    plan = tb.construct("helmholtz", d=3, n=64, tol=1e-4)
+    u = plan.apply(f)              # f: complex64 cuda tensor (nrhs, n, n, n)
+    v = plan.apply_adjoint(u)
+    u = tb.TBApply.apply(f, plan)  # autograd: backward = K^H grad
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+from . import _lib
+from ._lib import TBError
+
+KINDS = {"fourier": _lib.TB_KERNEL_FOURIER, "helmholtz": _lib.TB_KERNEL_HELMHOLTZ,
+         "radon": _lib.TB_KERNEL_RADON}
+DTYPES = {"c128": _lib.TB_C128, "c64": _lib.TB_C64, "cbf16": _lib.TB_CBF16}
+STORE = {"c128": _lib.TB_STORE_C128, "c64": _lib.TB_STORE_C64,
+         "cbf16": _lib.TB_STORE_CBF16}
+
+__all__ = ["construct", "load_plan", "Plan", "TBApply", "TBError",
+           "helmholtz_omega"]
+
+
+def helmholtz_omega(n: int) -> float:
+    """Wavenumber with 4 points per wavelength (2 pi n / omega = 4)."""
+    return math.pi * n / 2.0
+
+
+def _options(leaf=0, lt=None, proxy_pair=0, proxy_other=0, id_tol_scale=0.0,
+             store=("c64",), max_rank=0, max_device_bytes=0, radon=None):
+    o = _lib.TbOptions()
+    o.leaf_size = leaf
+    o.lt_override = 0 if lt is None else lt + 1
+    o.proxy_pair = proxy_pair
+    o.proxy_other = proxy_other
+    o.id_tol_scale = id_tol_scale
+    mask = 0
+    for s in store:
+        mask |= STORE[s]
+    o.store_mask = mask
+    o.max_rank = max_rank
+    o.max_device_bytes = max_device_bytes
+    if radon is not None:
+        o.radon_custom = 1
+        o.radon_a, o.radon_b, o.radon_den = radon
+    return o
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    if torch.cuda.is_available():
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(0)
+
+
+class Plan:
+    """A tensor butterfly factorisation held on the GPU by libtb."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.load().tb_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        info = _lib.TbPlanInfo()
+        _lib.check(_lib.load().tb_plan_info(self._h, ctypes.byref(info)))
+        return {name: getattr(info, name) for name, _ in info._fields_}
+
+    @property
+    def n(self) -> int:
+        return self.info()["n"]
+
+    @property
+    def d(self) -> int:
+        return self.info()["d"]
+
+    def _run(self, fn, x, out, dtype):
+        import torch
+        info = self.info()
+        n, d = info["n"], info["d"]
+        if not x.is_cuda:
+            raise ValueError("input must be a CUDA (HIP) tensor")
+        squeeze = x.dim() == d
+        xb = x.unsqueeze(0) if squeeze else x
+        if tuple(xb.shape[1:]) != (n,) * d:
+            raise ValueError(f"expected shape (nrhs, {n}^{d}), got {tuple(x.shape)}")
+        want = torch.complex128 if dtype == "c128" else torch.complex64
+        if xb.dtype != want:
+            raise TypeError(f"dtype {dtype} needs {want} input, got {xb.dtype}")
+        xb = xb.contiguous()
+        if out is None:
+            out = torch.empty_like(xb)
+        elif out.shape != xb.shape or out.dtype != want or not out.is_contiguous():
+            raise ValueError("out must be a contiguous tensor shaped like the input")
+        _lib.check(fn(self._h, ctypes.c_void_p(xb.data_ptr()),
+                      ctypes.c_void_p(out.data_ptr()), xb.shape[0], DTYPES[dtype],
+                      _stream_handle(None)))
+        return out.squeeze(0) if squeeze else out
+
+    def apply(self, f, out=None, dtype="c64"):
+        """u = K_BF f (Algorithm 2)."""
+        return self._run(_lib.load().tb_apply, f, out, dtype)
+
+    def apply_adjoint(self, g, out=None, dtype="c64"):
+        """v = K_BF^H g."""
+        return self._run(_lib.load().tb_apply_adjoint, g, out, dtype)
+
+    def set_timing(self, enable: bool = True) -> None:
+        """Record HIP events around every apply kernel (per-stage timing)."""
+        _lib.check(_lib.load().tb_plan_set_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self) -> dict:
+        """{stage: (total ms, launches)} recorded since the last call."""
+        ms = (ctypes.c_double * len(_lib.STAGES))()
+        cnt = (ctypes.c_longlong * len(_lib.STAGES))()
+        _lib.check(_lib.load().tb_plan_stage_times(self._h, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(_lib.STAGES)}
+
+    def save(self, path: str) -> None:
+        _lib.check(_lib.load().tb_plan_save(self._h, path.encode()))
+
+
+def construct(kind, d: int, n: int, tol: float, omega: float | None = None,
+              stream=None, **opts) -> Plan:
+    """Build the butterfly of operator ``kind`` on the GPU (Algorithm 1).
+
+    ``kind``: "fourier", "helmholtz" or "radon".  ``omega`` defaults to
+    4 points per wavelength for Helmholtz.  Options: leaf, lt, proxy_pair,
+    proxy_other, id_tol_scale, store (tuple of "c128"/"c64"/"cbf16"),
+    max_rank, max_device_bytes, radon=(a, b, den).
+    """
+    k = KINDS[kind] if isinstance(kind, str) else int(kind)
+    if omega is None:
+        omega = helmholtz_omega(n) if k == _lib.TB_KERNEL_HELMHOLTZ else 0.0
+    o = _options(**opts)
+    h = ctypes.c_void_p()
+    _lib.check(_lib.load().tb_construct(k, d, n, float(omega), float(tol), ctypes.byref(o),
+                                        _stream_handle(stream), ctypes.byref(h)))
+    return Plan(h)
+
+
+def load_plan(path: str, store=("c64",), recompute_cores: bool = False,
+              max_device_bytes: int = 0, stream=None) -> Plan:
+    """Load a plan file (format in include/tb.h)."""
+    o = _options(store=store, max_device_bytes=max_device_bytes)
+    h = ctypes.c_void_p()
+    _lib.check(_lib.load().tb_plan_load(path.encode(), ctypes.byref(o),
+                                        1 if recompute_cores else 0,
+                                        _stream_handle(stream), ctypes.byref(h)))
+    return Plan(h)
+
+
+def __getattr__(name):
+    if name == "TBApply":
+        from .autograd import TBApply
+        return TBApply
+    raise AttributeError(name)

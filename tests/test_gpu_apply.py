@@ -1,0 +1,142 @@
+"""GPU parity of the apply kernels (Algorithm 2 and its adjoint).
+
+The oracle builds a plan and writes it to a plan file; the library loads
+the file and applies it with its HIP kernels.  Both sides then contract the
+same factorisation, so the GPU result must match the oracle's apply element
+by element: FP64 to 1e-12 relative, FP32 to 2e-5 relative.  (FP32 bound:
+each output is a chain of about 2(L+1)d small contractions and one core dot
+product of at most a few thousand terms, each rounding at 2^-24 ~ 6e-8;
+sqrt(terms) growth gives ~1e-5 at worst.)
+"""
+import numpy as np
+import pytest
+
+from oracle import butterfly as bf
+from oracle import kernels, planio
+from oracle.kernels import Operator
+from paper_2411_03029_amd import inputs
+
+from .gpu_util import relerr, say, to_dev, to_host, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (kind, d, n, tol, leaf)  -- tiles span several blocks and levels
+    "fourier2_n32": (kernels.FOURIER, 2, 32, 1e-6, 8),
+    "fourier2_n64": (kernels.FOURIER, 2, 64, 1e-6, 8),
+    "fourier3_n16": (kernels.FOURIER, 3, 16, 1e-4, 4),
+    "helm3_n16": (kernels.HELMHOLTZ, 3, 16, 1e-4, 8),
+    "helm3_n32": (kernels.HELMHOLTZ, 3, 32, 1e-4, 8),
+    "radon2_n32": (kernels.RADON, 2, 32, 1e-3, 8),
+    "radon2_n64_leaf4": (kernels.RADON, 2, 64, 1e-2, 4),
+    "helm3_n8_single": (kernels.HELMHOLTZ, 3, 8, 1e-4, 8),   # L = 0
+}
+
+_PLANS = {}
+
+
+def oracle_plan(name):
+    if name not in _PLANS:
+        kind, d, n, tol, leaf = CASES[name]
+        om = kernels.helmholtz_omega(n) if kind == kernels.HELMHOLTZ else 0.0
+        _PLANS[name] = bf.construct(Operator(kind, d, n, omega=om), tol, leaf=leaf)
+    return _PLANS[name]
+
+
+def gpu_plan(name, tmp_path, store=("c128", "c64"), recompute=False):
+    import paper_2411_03029_amd as tb
+    path = str(tmp_path / f"{name}.tbplan")
+    planio.save_plan(oracle_plan(name), path)
+    return tb.load_plan(path, store=store, recompute_cores=recompute)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_matches_oracle_fp64(name, tmp_path):
+    torch = torch_gpu()
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path)
+    n, d = op.n, op.d
+    for nrhs in (1, 3):
+        f = inputs.rhs_batch(n, d, nrhs, config=90)
+        say(f"[gpu] apply fp64 {name} nrhs={nrhs}")
+        u = to_host(plan.apply(to_dev(f, torch.complex128), dtype="c128"))
+        torch.cuda.synchronize()
+        assert relerr(u, bf.apply(op, f)) <= 1e-12
+        say(f"[gpu] adjoint fp64 {name} nrhs={nrhs}")
+        v = to_host(plan.apply_adjoint(to_dev(f, torch.complex128), dtype="c128"))
+        torch.cuda.synchronize()
+        assert relerr(v, bf.apply_adjoint(op, f)) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_matches_oracle_fp32(name, tmp_path):
+    torch = torch_gpu()
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path)
+    n, d = op.n, op.d
+    for nrhs in (1, 5):
+        f = inputs.rhs_batch(n, d, nrhs, config=91)
+        say(f"[gpu] apply fp32 {name} nrhs={nrhs}")
+        u = to_host(plan.apply(to_dev(f, torch.complex64), dtype="c64"))
+        v = to_host(plan.apply_adjoint(to_dev(f, torch.complex64), dtype="c64"))
+        torch.cuda.synchronize()
+        assert relerr(u, bf.apply(op, f)) <= 2e-5
+        assert relerr(v, bf.apply_adjoint(op, f)) <= 2e-5
+        # every right-hand side individually
+        ue = bf.apply(op, f)
+        for q in range(nrhs):
+            assert relerr(u[q], ue[q]) <= 2e-5
+
+
+def test_single_input_shape_and_batched_rhs_consistency(tmp_path):
+    torch = torch_gpu()
+    name = "helm3_n32"
+    plan = gpu_plan(name, tmp_path)
+    f = inputs.rhs_batch(32, 3, 4, config=92)
+    say("[gpu] batched vs single rhs helm3_n32")
+    ub = to_host(plan.apply(to_dev(f, torch.complex128), dtype="c128"))
+    for q in range(4):
+        u1 = to_host(plan.apply(to_dev(f[q], torch.complex128), dtype="c128"))
+        np.testing.assert_allclose(u1, ub[q], rtol=0, atol=1e-13 * np.abs(ub).max())
+
+
+def test_core_evaluation_matches_oracle(tmp_path):
+    # cores recomputed on the GPU (FP64 entry evaluation at the oracle's
+    # skeletons) against the oracle's cores
+    torch_gpu()
+    from .planfile import PlanFile
+    for name in ("helm3_n32", "radon2_n32", "fourier2_n64"):
+        op = oracle_plan(name)
+        say(f"[gpu] core evaluation {name}")
+        plan = gpu_plan(name, tmp_path, store=("c128",), recompute=True)
+        out = str(tmp_path / f"{name}.gpu.tbplan")
+        plan.save(out)
+        pf = PlanFile(out)
+        worst = 0.0
+        for key, C in op.cores.items():
+            worst = max(worst, float(np.abs(pf.cores[key] - C).max() / np.abs(C).max()))
+        assert worst <= 1e-12, worst
+
+
+def test_deterministic(tmp_path):
+    torch = torch_gpu()
+    plan = gpu_plan("helm3_n32", tmp_path)
+    f = to_dev(inputs.rhs_batch(32, 3, 2, config=93), torch.complex64)
+    say("[gpu] determinism helm3_n32")
+    a = plan.apply(f)
+    b = plan.apply(f)
+    c = plan.apply_adjoint(a)
+    e = plan.apply_adjoint(b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(c, e)
+
+
+def test_dtype_without_cores_is_rejected(tmp_path):
+    torch = torch_gpu()
+    import paper_2411_03029_amd as tb
+    plan = gpu_plan("helm3_n16", tmp_path, store=("c64",))
+    f = to_dev(inputs.rhs_batch(16, 3, 1, config=94), torch.complex128)
+    with pytest.raises(tb.TBError):
+        plan.apply(f, dtype="c128")
+    with pytest.raises(ValueError):
+        plan.apply(to_dev(inputs.rhs_batch(8, 3, 1, config=94), torch.complex64))
