@@ -30,12 +30,10 @@
 namespace tb {
 
 constexpr int kThreads = 256;
-constexpr int kMaxPer = 32;     // fan-in outputs per thread (registers)
-constexpr int kCoreRows = 64;   // forward core: rows per workgroup
-constexpr int kCoreCols = 16;   // adjoint core: columns per workgroup
 
 struct StageArgs {
   int nb, nblk, lvl;              // blocks per mode, nb^d, fine level
+  int nsplit, chunk;              // slices of the first output mode
   int R[kMaxD], A[kMaxD];         // fine padded ranks, coarse block sizes
   long long mat_item_stride;
   long long mat_k_off[kMaxD];
@@ -46,7 +44,7 @@ struct StageArgs {
   long long cst[kMaxD];           // coarse item strides (entries)
   long long n, ndim;              // n and n^d (global arrays)
   int outer_level, outer_block;   // outer multi-set level and block size
-  int nrhs, Q;
+  int nrhs;
   int conj;
 };
 
@@ -132,37 +130,10 @@ __device__ __forceinline__ long long fine_base(const StageArgs& a, int fi, const
   return base * a.nrhs + q0;
 }
 
-// Loads the d matrices of (item, beta) into LDS, conjugated on request.
-template <class C, int D>
-__device__ void load_mats(const StageArgs& a, const C* mats, int item, const int* beta, C* sm,
-                          C** mk) {
-  int off = 0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    mk[k] = sm + off;
-    int cnt = a.R[k] * a.A[k];
-    const C* src = mats + (long long)item * a.mat_item_stride + a.mat_k_off[k] +
-                   (long long)beta[k] * cnt;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-      C v = src[i];
-      if (a.conj) v.y = -v.y;
-      mk[k][i] = v;
-    }
-    off += cnt;
-  }
-}
-
-template <int D>
-__device__ __forceinline__ int mats_lds(const StageArgs& a) {
-  int s = 0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) s += a.R[k] * a.A[k];
-  return s;
-}
-
 // --------------------------------------------------------------- fan-out --
 // fine(a_0..a_{D-1}, q) = sum_j prod_k M_k[a_k][j_k] coarse(j_0..j_{D-1}, q)
-template <class T, int D>
+// for a_0 in this workgroup's slice [lo, lo + na) of the first mode.
+template <class T, int D, int QT>
 __global__ void __launch_bounds__(kThreads)
     stage_fanout(StageArgs a, const typename CplxOf<T>::type* __restrict__ coarse,
                  typename CplxOf<T>::type* __restrict__ fine,
@@ -170,77 +141,124 @@ __global__ void __launch_bounds__(kThreads)
   using C = typename CplxOf<T>::type;
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
-  const int fi = blockIdx.x / a.nblk;
+  int bid = blockIdx.x;
+  const int split = bid % a.nsplit;
+  bid /= a.nsplit;
+  const int fi = bid / a.nblk;
   int beta[D];
-  unflatten_blk<D>(blockIdx.x % a.nblk, a.nb, beta);
-  const int q0 = blockIdx.y * a.Q;
-  const int Q = min(a.Q, a.nrhs - q0);
+  unflatten_blk<D>(bid % a.nblk, a.nb, beta);
+  const int lo = split * a.chunk;
+  const int na = min(a.R[0], lo + a.chunk) - lo;
+  const int q0 = blockIdx.y * QT;
+  const int Qa = min(QT, a.nrhs - q0);
+  const int A0 = a.A[0];
+  // matrices: rows lo..lo+na of M_0, then M_1.. M_{D-1}
+  const C* mbase = mats + (long long)fi * a.mat_item_stride;
+  C* m0 = sm;
   C* mk[D];
-  load_mats<C, D>(a, mats, fi, beta, sm, mk);
-  C* buf1 = sm + mats_lds<D>(a);
+  mk[0] = m0;
+  int off = na * A0;
+  {
+    const C* src = mbase + a.mat_k_off[0] + ((long long)beta[0] * a.R[0] + lo) * A0;
+    for (int i = threadIdx.x; i < na * A0; i += kThreads) {
+      C v = src[i];
+      if (a.conj) v.y = -v.y;
+      m0[i] = v;
+    }
+  }
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    mk[k] = sm + off;
+    const int cnt = a.R[k] * a.A[k];
+    const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * cnt;
+    for (int i = threadIdx.x; i < cnt; i += kThreads) {
+      C v = src[i];
+      if (a.conj) v.y = -v.y;
+      mk[k][i] = v;
+    }
+    off += cnt;
+  }
+  C* buf1 = sm + off;
   const int citem = a.coarse_global ? (fi >> (D * a.lvl)) : parent_of<D>(fi, a.lvl);
   CoarseAddr<D> ca;
   ca.init(a, citem, beta, q0);
   long long fs[D];
   const long long fb = fine_base<D>(a, fi, beta, q0, fs);
-  const int R0 = a.R[0], A0 = a.A[0];
   __syncthreads();
   if constexpr (D == 2) {
     const int A1 = a.A[1], R1 = a.R[1];
-    // buf1[a0][j1][q] = sum_j0 M0[a0][j0] coarse(j0, j1, q)
-    for (int idx = threadIdx.x; idx < R0 * A1 * Q; idx += blockDim.x) {
-      int q = idx % Q, t = idx / Q, j1 = t % A1, a0 = t / A1;
-      const C* src = coarse + ca.base + j1 * ca.stride[1] + q * ca.qstride;
+    for (int idx = threadIdx.x; idx < na * A1 * QT; idx += kThreads) {
+      const int q = idx % QT, t = idx / QT, j1 = t % A1, ai = t / A1;
       C acc = czero<C>();
-      for (int j0 = 0; j0 < A0; ++j0) acc = cfma(acc, mk[0][a0 * A0 + j0], src[j0 * ca.stride[0]]);
+      if (q < Qa) {
+        const C* src = coarse + ca.base + j1 * ca.stride[1] + q * ca.qstride;
+        const C* mr = m0 + ai * A0;
+        for (int j0 = 0; j0 < A0; ++j0) acc = cfma(acc, mr[j0], src[j0 * ca.stride[0]]);
+      }
       buf1[idx] = acc;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < R0 * R1 * Q; idx += blockDim.x) {
-      int q = idx % Q, t = idx / Q, a1 = t % R1, a0 = t / R1;
-      const C* src = buf1 + (a0 * A1) * Q + q;
+    for (int idx = threadIdx.x; idx < na * R1 * QT; idx += kThreads) {
+      const int q = idx % QT, t = idx / QT, a1 = t % R1, ai = t / R1;
+      if (q >= Qa) continue;
+      const C* src = buf1 + (ai * A1) * QT + q;
+      const C* mr = mk[1] + a1 * A1;
       C acc = czero<C>();
-      for (int j1 = 0; j1 < A1; ++j1) acc = cfma(acc, mk[1][a1 * A1 + j1], src[j1 * Q]);
-      fine[fb + a0 * fs[0] + a1 * fs[1] + q] = acc;
+      for (int j1 = 0; j1 < A1; ++j1) acc = cfma(acc, mr[j1], src[j1 * QT]);
+      fine[fb + (lo + ai) * fs[0] + a1 * fs[1] + q] = acc;
     }
   } else {
     const int A1 = a.A[1], A2 = a.A[2], R1 = a.R[1], R2 = a.R[2];
-    C* buf2 = buf1 + R0 * A1 * A2 * Q;
-    for (int idx = threadIdx.x; idx < R0 * A1 * A2 * Q; idx += blockDim.x) {
-      int q = idx % Q, t = idx / Q, j2 = t % A2;
+    C* buf2 = buf1 + na * A1 * A2 * QT;
+    for (int idx = threadIdx.x; idx < na * A1 * A2 * QT; idx += kThreads) {
+      const int q = idx % QT;
+      int t = idx / QT;
+      const int j2 = t % A2;
       t /= A2;
-      int j1 = t % A1, a0 = t / A1;
-      const C* src = coarse + ca.base + j1 * ca.stride[1] + j2 * ca.stride[2] + q * ca.qstride;
+      const int j1 = t % A1, ai = t / A1;
       C acc = czero<C>();
-      for (int j0 = 0; j0 < A0; ++j0) acc = cfma(acc, mk[0][a0 * A0 + j0], src[j0 * ca.stride[0]]);
+      if (q < Qa) {
+        const C* src = coarse + ca.base + j1 * ca.stride[1] + j2 * ca.stride[2] + q * ca.qstride;
+        const C* mr = m0 + ai * A0;
+        for (int j0 = 0; j0 < A0; ++j0) acc = cfma(acc, mr[j0], src[j0 * ca.stride[0]]);
+      }
       buf1[idx] = acc;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < R0 * R1 * A2 * Q; idx += blockDim.x) {
-      int q = idx % Q, t = idx / Q, j2 = t % A2;
+    for (int idx = threadIdx.x; idx < na * R1 * A2 * QT; idx += kThreads) {
+      const int q = idx % QT;
+      int t = idx / QT;
+      const int j2 = t % A2;
       t /= A2;
-      int a1 = t % R1, a0 = t / R1;
-      const C* src = buf1 + ((a0 * A1) * A2 + j2) * Q + q;
+      const int a1 = t % R1, ai = t / R1;
+      const C* src = buf1 + ((ai * A1) * A2 + j2) * QT + q;
+      const C* mr = mk[1] + a1 * A1;
       C acc = czero<C>();
-      for (int j1 = 0; j1 < A1; ++j1) acc = cfma(acc, mk[1][a1 * A1 + j1], src[j1 * A2 * Q]);
+      for (int j1 = 0; j1 < A1; ++j1) acc = cfma(acc, mr[j1], src[j1 * A2 * QT]);
       buf2[idx] = acc;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < R0 * R1 * R2 * Q; idx += blockDim.x) {
-      int q = idx % Q, t = idx / Q, a2 = t % R2;
+    for (int idx = threadIdx.x; idx < na * R1 * R2 * QT; idx += kThreads) {
+      const int q = idx % QT;
+      int t = idx / QT;
+      const int a2 = t % R2;
       t /= R2;
-      int a1 = t % R1, a0 = t / R1;
-      const C* src = buf2 + ((a0 * R1 + a1) * A2) * Q + q;
+      const int a1 = t % R1, ai = t / R1;
+      if (q >= Qa) continue;
+      const C* src = buf2 + ((ai * R1 + a1) * A2) * QT + q;
+      const C* mr = mk[2] + a2 * A2;
       C acc = czero<C>();
-      for (int j2 = 0; j2 < A2; ++j2) acc = cfma(acc, mk[2][a2 * A2 + j2], src[j2 * Q]);
-      fine[fb + a0 * fs[0] + a1 * fs[1] + a2 * fs[2] + q] = acc;
+      for (int j2 = 0; j2 < A2; ++j2) acc = cfma(acc, mr[j2], src[j2 * QT]);
+      fine[fb + (lo + ai) * fs[0] + a1 * fs[1] + a2 * fs[2] + q] = acc;
     }
   }
 }
 
 // ---------------------------------------------------------------- fan-in --
 // coarse(a_0..a_{D-1}, q) = sum_children sum_j prod_k M_k[j_k][a_k] fine_c(j, q)
-template <class T, int D>
+// for a_0 in this workgroup's slice [lo, lo + na) of the first coarse mode;
+// the outputs stay in registers (NPER per thread) across the children.
+template <class T, int D, int QT, int NPER>
 __global__ void __launch_bounds__(kThreads)
     stage_fanin(StageArgs a, const typename CplxOf<T>::type* __restrict__ fine,
                 typename CplxOf<T>::type* __restrict__ coarse,
@@ -248,83 +266,125 @@ __global__ void __launch_bounds__(kThreads)
   using C = typename CplxOf<T>::type;
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
-  const int ci = blockIdx.x / a.nblk;
+  int bid = blockIdx.x;
+  const int split = bid % a.nsplit;
+  bid /= a.nsplit;
+  const int ci = bid / a.nblk;
   int beta[D];
-  unflatten_blk<D>(blockIdx.x % a.nblk, a.nb, beta);
-  const int q0 = blockIdx.y * a.Q;
-  const int Q = min(a.Q, a.nrhs - q0);
+  unflatten_blk<D>(bid % a.nblk, a.nb, beta);
+  const int A0 = a.A[0], R0 = a.R[0];
+  const int lo = split * a.chunk;
+  const int na = min(A0, lo + a.chunk) - lo;
+  const int q0 = blockIdx.y * QT;
+  const int Qa = min(QT, a.nrhs - q0);
   const int nchild = a.coarse_global ? 1 : (1 << D);
-  C acc[kMaxPer];
+  int nout = na * QT;
 #pragma unroll
-  for (int i = 0; i < kMaxPer; ++i) acc[i] = czero<C>();
-  int nout = Q;
+  for (int k = 1; k < D; ++k) nout *= a.A[k];
+  C acc[NPER];
 #pragma unroll
-  for (int k = 0; k < D; ++k) nout *= a.A[k];
-  C* buf1 = sm + mats_lds<D>(a);
-  const int R0 = a.R[0], A0 = a.A[0];
+  for (int i = 0; i < NPER; ++i) acc[i] = czero<C>();
+  // LDS: m0 = M_0[:, lo..lo+na] (R0 x na), M_1.., buf1, buf2
+  C* m0 = sm;
+  C* mk[D];
+  mk[0] = m0;
+  int off = R0 * na;
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    mk[k] = sm + off;
+    off += a.R[k] * a.A[k];
+  }
+  C* buf1 = sm + off;
   for (int c = 0; c < nchild; ++c) {
     const int fi = a.coarse_global ? ci : child_of<D>(ci, a.lvl, c);
-    C* mk[D];
+    const C* mbase = mats + (long long)fi * a.mat_item_stride;
     __syncthreads();
-    load_mats<C, D>(a, mats, fi, beta, sm, mk);
+    {
+      const C* src = mbase + a.mat_k_off[0] + (long long)beta[0] * R0 * A0 + lo;
+      for (int i = threadIdx.x; i < R0 * na; i += kThreads) {
+        const int j0 = i / na, ai = i % na;
+        C v = src[j0 * A0 + ai];
+        if (a.conj) v.y = -v.y;
+        m0[i] = v;
+      }
+    }
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+      const int cnt = a.R[k] * a.A[k];
+      const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * cnt;
+      for (int i = threadIdx.x; i < cnt; i += kThreads) {
+        C v = src[i];
+        if (a.conj) v.y = -v.y;
+        mk[k][i] = v;
+      }
+    }
     long long fs[D];
     const long long fb = fine_base<D>(a, fi, beta, q0, fs);
     __syncthreads();
     if constexpr (D == 2) {
       const int R1 = a.R[1], A1 = a.A[1];
-      // buf1[a0][j1][q] = sum_j0 M0[j0][a0] fine(j0, j1, q)
-      for (int idx = threadIdx.x; idx < A0 * R1 * Q; idx += blockDim.x) {
-        int q = idx % Q, t = idx / Q, j1 = t % R1, a0 = t / R1;
-        const C* src = fine + fb + j1 * fs[1] + q;
+      for (int idx = threadIdx.x; idx < na * R1 * QT; idx += kThreads) {
+        const int q = idx % QT, t = idx / QT, j1 = t % R1, ai = t / R1;
         C s = czero<C>();
-        for (int j0 = 0; j0 < R0; ++j0) s = cfma(s, mk[0][j0 * A0 + a0], src[j0 * fs[0]]);
+        if (q < Qa) {
+          const C* src = fine + fb + j1 * fs[1] + q;
+          for (int j0 = 0; j0 < R0; ++j0) s = cfma(s, m0[j0 * na + ai], src[j0 * fs[0]]);
+        }
         buf1[idx] = s;
       }
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < kMaxPer; ++i) {
-        int idx = threadIdx.x + i * kThreads;
+      for (int i = 0; i < NPER; ++i) {
+        const int idx = threadIdx.x + i * kThreads;
         if (idx < nout) {
-          int q = idx % Q, t = idx / Q, a1 = t % A1, a0 = t / A1;
-          const C* src = buf1 + (a0 * R1) * Q + q;
+          const int q = idx % QT, t = idx / QT, a1 = t % A1, ai = t / A1;
+          const C* src = buf1 + (ai * R1) * QT + q;
           C s = acc[i];
-          for (int j1 = 0; j1 < R1; ++j1) s = cfma(s, mk[1][j1 * A1 + a1], src[j1 * Q]);
+          for (int j1 = 0; j1 < R1; ++j1) s = cfma(s, mk[1][j1 * A1 + a1], src[j1 * QT]);
           acc[i] = s;
         }
       }
     } else {
       const int R1 = a.R[1], R2 = a.R[2], A1 = a.A[1], A2 = a.A[2];
-      C* buf2 = buf1 + A0 * R1 * R2 * Q;
-      for (int idx = threadIdx.x; idx < A0 * R1 * R2 * Q; idx += blockDim.x) {
-        int q = idx % Q, t = idx / Q, j2 = t % R2;
+      C* buf2 = buf1 + na * R1 * R2 * QT;
+      for (int idx = threadIdx.x; idx < na * R1 * R2 * QT; idx += kThreads) {
+        const int q = idx % QT;
+        int t = idx / QT;
+        const int j2 = t % R2;
         t /= R2;
-        int j1 = t % R1, a0 = t / R1;
-        const C* src = fine + fb + j1 * fs[1] + j2 * fs[2] + q;
+        const int j1 = t % R1, ai = t / R1;
         C s = czero<C>();
-        for (int j0 = 0; j0 < R0; ++j0) s = cfma(s, mk[0][j0 * A0 + a0], src[j0 * fs[0]]);
+        if (q < Qa) {
+          const C* src = fine + fb + j1 * fs[1] + j2 * fs[2] + q;
+          for (int j0 = 0; j0 < R0; ++j0) s = cfma(s, m0[j0 * na + ai], src[j0 * fs[0]]);
+        }
         buf1[idx] = s;
       }
       __syncthreads();
-      for (int idx = threadIdx.x; idx < A0 * A1 * R2 * Q; idx += blockDim.x) {
-        int q = idx % Q, t = idx / Q, j2 = t % R2;
+      for (int idx = threadIdx.x; idx < na * A1 * R2 * QT; idx += kThreads) {
+        const int q = idx % QT;
+        int t = idx / QT;
+        const int j2 = t % R2;
         t /= R2;
-        int a1 = t % A1, a0 = t / A1;
-        const C* src = buf1 + ((a0 * R1) * R2 + j2) * Q + q;
+        const int a1 = t % A1, ai = t / A1;
+        const C* src = buf1 + ((ai * R1) * R2 + j2) * QT + q;
         C s = czero<C>();
-        for (int j1 = 0; j1 < R1; ++j1) s = cfma(s, mk[1][j1 * A1 + a1], src[j1 * R2 * Q]);
+        for (int j1 = 0; j1 < R1; ++j1) s = cfma(s, mk[1][j1 * A1 + a1], src[j1 * R2 * QT]);
         buf2[idx] = s;
       }
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < kMaxPer; ++i) {
-        int idx = threadIdx.x + i * kThreads;
+      for (int i = 0; i < NPER; ++i) {
+        const int idx = threadIdx.x + i * kThreads;
         if (idx < nout) {
-          int q = idx % Q, t = idx / Q, a2 = t % A2;
+          const int q = idx % QT;
+          int t = idx / QT;
+          const int a2 = t % A2;
           t /= A2;
-          int a1 = t % A1, a0 = t / A1;
-          const C* src = buf2 + ((a0 * A1 + a1) * R2) * Q + q;
+          const int a1 = t % A1, ai = t / A1;
+          const C* src = buf2 + ((ai * A1 + a1) * R2) * QT + q;
           C s = acc[i];
-          for (int j2 = 0; j2 < R2; ++j2) s = cfma(s, mk[2][j2 * A2 + a2], src[j2 * Q]);
+          for (int j2 = 0; j2 < R2; ++j2) s = cfma(s, mk[2][j2 * A2 + a2], src[j2 * QT]);
           acc[i] = s;
         }
       }
@@ -333,17 +393,21 @@ __global__ void __launch_bounds__(kThreads)
   CoarseAddr<D> ca;
   ca.init(a, ci, beta, q0);
 #pragma unroll
-  for (int i = 0; i < kMaxPer; ++i) {
-    int idx = threadIdx.x + i * kThreads;
+  for (int i = 0; i < NPER; ++i) {
+    const int idx = threadIdx.x + i * kThreads;
     if (idx < nout) {
-      int q = idx % Q, t = idx / Q;
-      long long off = ca.base + q * ca.qstride;
+      const int q = idx % QT;
+      if (q < Qa) {
+        int t = idx / QT;
+        long long o = ca.base + q * ca.qstride;
 #pragma unroll
-      for (int k = D - 1; k >= 0; --k) {
-        off += (long long)(t % a.A[k]) * ca.stride[k];
-        t /= a.A[k];
+        for (int k = D - 1; k >= 1; --k) {
+          o += (long long)(t % a.A[k]) * ca.stride[k];
+          t /= a.A[k];
+        }
+        o += (long long)(lo + t) * ca.stride[0];
+        coarse[o] = acc[i];
       }
-      coarse[off] = acc[i];
     }
   }
 }
@@ -353,7 +417,40 @@ struct CoreArgs {
   long long nS, nT;              // middle multi-sets per side
   long long Es, Et;              // entries per top-level item (source / target)
   int Rs[kMaxD], Rt[kMaxD];      // padded ranks of the top levels
-  int nrhs, Q;
+  int nrhs;
+};
+
+// 16-byte vector loads of the stored cores: VR consecutive rows per lane.
+template <class CS>
+struct CoreVec;
+template <>
+struct CoreVec<float2> {
+  static constexpr int VR = 2;
+  using V = float4;
+  __device__ static void get(const V& v, float2* c) {
+    c[0] = make_float2(v.x, v.y);
+    c[1] = make_float2(v.z, v.w);
+  }
+};
+template <>
+struct CoreVec<double2> {
+  static constexpr int VR = 1;
+  using V = double2;
+  __device__ static void get(const V& v, double2* c) { c[0] = v; }
+};
+template <>
+struct CoreVec<unsigned> {  // packed (bf16 re, bf16 im)
+  static constexpr int VR = 4;
+  using V = uint4;
+  __device__ static float2 one(unsigned u) {
+    return make_float2(bf16_to_f32((unsigned short)(u & 0xffff)), bf16_to_f32((unsigned short)(u >> 16)));
+  }
+  __device__ static void get(const V& v, float2* c) {
+    c[0] = one(v.x);
+    c[1] = one(v.y);
+    c[2] = one(v.z);
+    c[3] = one(v.w);
+  }
 };
 
 template <int D>
@@ -380,14 +477,19 @@ __device__ __forceinline__ bool is_padding(long long pos, const int* r, const in
   return pad;
 }
 
-// G_{t,s}(rows) = C_{t,s}(rows, :) F_{t,s}; one workgroup = 64 rows of one
-// pair, its four waves split the columns and reduce through LDS.
-template <class T, class CS, int D>
+constexpr int kUnroll = 8;
+
+// G_{t,s}(rows) = C_{t,s}(rows, :) F_{t,s}.  A workgroup owns 64 VR rows of
+// one pair (VR per lane, one 16-byte load per column); its four waves split
+// the columns, keep kUnroll column loads in flight and reduce through LDS.
+template <class T, class CS, int D, int QT>
 __global__ void __launch_bounds__(kThreads)
     core_fwd(CoreArgs a, const CS* __restrict__ cores, const long long* __restrict__ core_off,
              const int* __restrict__ meta, const int2* __restrict__ units,
              const typename CplxOf<T>::type* __restrict__ F, typename CplxOf<T>::type* __restrict__ G) {
   using C = typename CplxOf<T>::type;
+  using CV = CoreVec<CS>;
+  constexpr int VR = CV::VR;
   extern __shared__ unsigned char smem_raw[];
   C* x = reinterpret_cast<C*>(smem_raw);
   const int2 u = units[blockIdx.x];
@@ -402,69 +504,100 @@ __global__ void __launch_bounds__(kThreads)
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
-  const int q0 = blockIdx.y * a.Q;
-  const int Q = min(a.Q, a.nrhs - q0);
-  for (int idx = threadIdx.x; idx < RS * Q; idx += blockDim.x) {
-    int q = idx % Q, b = idx / Q;
-    x[idx] = F[(sitem * a.Es + padded_pos<D>(b, rs, a.Rs)) * a.nrhs + q0 + q];
+  const int q0 = blockIdx.y * QT;
+  const int Qa = min(QT, a.nrhs - q0);
+  for (int idx = threadIdx.x; idx < RS * QT; idx += kThreads) {
+    const int q = idx % QT, b = idx / QT;
+    x[idx] = q < Qa ? F[(sitem * a.Es + padded_pos<D>(b, rs, a.Rs)) * a.nrhs + q0 + q] : czero<C>();
   }
-  C* red = x + RS * Q;
+  C* red = x + RS * QT;
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int row = r0 + lane;
+  const int row = r0 + lane * VR;
   const int per = (RS + 3) / 4;
   const int j0 = w * per, j1 = min(RS, j0 + per);
-  constexpr int QM = 8;
-  C acc[QM];
+  C acc[VR][QT];
 #pragma unroll
-  for (int q = 0; q < QM; ++q) acc[q] = czero<C>();
+  for (int v = 0; v < VR; ++v)
+#pragma unroll
+    for (int q = 0; q < QT; ++q) acc[v][q] = czero<C>();
   if (row < RTp) {
-    const CS* col = cores + core_off[pair] + row;
-    for (int j = j0; j < j1; ++j) {
-      C c;
-      if constexpr (sizeof(CS) == 4) {   // packed bf16 pair
-        unsigned v = reinterpret_cast<const unsigned*>(col)[(long long)j * RTp];
-        c.x = bf16_to_f32((unsigned short)(v & 0xffff));
-        c.y = bf16_to_f32((unsigned short)(v >> 16));
-      } else {
-        CS v = col[(long long)j * RTp];
-        c.x = v.x;
-        c.y = v.y;
-      }
+    const typename CV::V* col =
+        reinterpret_cast<const typename CV::V*>(cores + core_off[pair] + row);
+    const long long cstride = RTp / VR;   // in vectors
+    int j = j0;
+    for (; j + kUnroll <= j1; j += kUnroll) {
+      typename CV::V vv[kUnroll];
 #pragma unroll
-      for (int q = 0; q < QM; ++q)
-        if (q < Q) acc[q] = cfma(acc[q], c, x[j * Q + q]);
+      for (int uu = 0; uu < kUnroll; ++uu) vv[uu] = col[(long long)(j + uu) * cstride];
+#pragma unroll
+      for (int uu = 0; uu < kUnroll; ++uu) {
+        C c[VR];
+        CV::get(vv[uu], c);
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+          const C xv = x[(j + uu) * QT + q];
+#pragma unroll
+          for (int v = 0; v < VR; ++v) acc[v][q] = cfma(acc[v][q], c[v], xv);
+        }
+      }
+    }
+    for (; j < j1; ++j) {
+      C c[VR];
+      CV::get(col[(long long)j * cstride], c);
+#pragma unroll
+      for (int q = 0; q < QT; ++q) {
+        const C xv = x[j * QT + q];
+#pragma unroll
+        for (int v = 0; v < VR; ++v) acc[v][q] = cfma(acc[v][q], c[v], xv);
+      }
     }
   }
 #pragma unroll
-  for (int q = 0; q < QM; ++q)
-    if (q < Q) red[(w * 64 + lane) * Q + q] = acc[q];
+  for (int v = 0; v < VR; ++v)
+#pragma unroll
+    for (int q = 0; q < QT; ++q) red[((w * 64 + lane) * VR + v) * QT + q] = acc[v][q];
   __syncthreads();
-  if (w == 0 && row < RT) {
-    long long pos = padded_pos<D>(row, rt, a.Rt);
-    for (int q = 0; q < Q; ++q) {
-      C v = red[lane * Q + q];
-      v = cadd(v, red[(64 + lane) * Q + q]);
-      v = cadd(v, red[(128 + lane) * Q + q]);
-      v = cadd(v, red[(192 + lane) * Q + q]);
-      G[(titem * a.Et + pos) * a.nrhs + q0 + q] = v;
+  if (w == 0) {
+#pragma unroll
+    for (int v = 0; v < VR; ++v) {
+      const int r = row + v;
+      if (r < RT) {
+        const long long pos = padded_pos<D>(r, rt, a.Rt);
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+          if (q < Qa) {
+            C sum = red[(lane * VR + v) * QT + q];
+            sum = cadd(sum, red[((64 + lane) * VR + v) * QT + q]);
+            sum = cadd(sum, red[((128 + lane) * VR + v) * QT + q]);
+            sum = cadd(sum, red[((192 + lane) * VR + v) * QT + q]);
+            G[(titem * a.Et + pos) * a.nrhs + q0 + q] = sum;
+          }
+        }
+      }
     }
   }
   if (r0 == 0) {  // padding of the output item is written as zeros
-    for (long long p = threadIdx.x; p < a.Et; p += blockDim.x)
+    for (long long p = threadIdx.x; p < a.Et; p += kThreads)
       if (is_padding<D>(p, rt, a.Rt))
-        for (int q = 0; q < Q; ++q) G[(titem * a.Et + p) * a.nrhs + q0 + q] = czero<C>();
+        for (int q = 0; q < Qa; ++q) G[(titem * a.Et + p) * a.nrhs + q0 + q] = czero<C>();
   }
 }
 
-// F_{t,s}(cols) = C_{t,s}(:, cols)^H G_{t,s}; one workgroup = 16 columns of
-// one pair, each wave reduces four columns across its lanes.
-template <class T, class CS, int D>
+constexpr int kAdjCols = 8;   // columns per wave in the adjoint core kernel
+
+// F_{t,s}(cols) = C_{t,s}(:, cols)^H G_{t,s}.  A workgroup owns 4 kAdjCols
+// columns of one pair; each wave takes kAdjCols of them, its lanes sweep the
+// rows (VR per lane per 16-byte load, kAdjCols loads in flight) and the
+// partial dot products are reduced across the wave at the end.
+template <class T, class CS, int D, int QT>
 __global__ void __launch_bounds__(kThreads)
     core_adj(CoreArgs a, const CS* __restrict__ cores, const long long* __restrict__ core_off,
              const int* __restrict__ meta, const int2* __restrict__ units,
              const typename CplxOf<T>::type* __restrict__ G, typename CplxOf<T>::type* __restrict__ F) {
   using C = typename CplxOf<T>::type;
+  using CV = CoreVec<CS>;
+  constexpr int VR = CV::VR;
   extern __shared__ unsigned char smem_raw[];
   C* y = reinterpret_cast<C*>(smem_raw);
   const int2 u = units[blockIdx.x];
@@ -479,59 +612,77 @@ __global__ void __launch_bounds__(kThreads)
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
-  const int q0 = blockIdx.y * a.Q;
-  const int Q = min(a.Q, a.nrhs - q0);
-  for (int idx = threadIdx.x; idx < RTp * Q; idx += blockDim.x) {
-    int q = idx % Q, r = idx / Q;
-    y[idx] = r < RT ? G[(titem * a.Et + padded_pos<D>(r, rt, a.Rt)) * a.nrhs + q0 + q] : czero<C>();
+  const int q0 = blockIdx.y * QT;
+  const int Qa = min(QT, a.nrhs - q0);
+  for (int idx = threadIdx.x; idx < RTp * QT; idx += kThreads) {
+    const int q = idx % QT, r = idx / QT;
+    y[idx] = (r < RT && q < Qa) ? G[(titem * a.Et + padded_pos<D>(r, rt, a.Rt)) * a.nrhs + q0 + q]
+                                : czero<C>();
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  constexpr int QM = 8;
-  for (int cc = 0; cc < 4; ++cc) {
-    const int col = c0 + w * 4 + cc;
-    if (col >= RS) break;
-    const CS* cp = cores + core_off[pair] + (long long)col * RTp;
-    C acc[QM];
+  const int cb = c0 + w * kAdjCols;
+  const int ncol = max(0, min(kAdjCols, RS - cb));
+  C acc[kAdjCols][QT];
 #pragma unroll
-    for (int q = 0; q < QM; ++q) acc[q] = czero<C>();
-    for (int r = lane; r < RTp; r += 64) {
-      C c;
-      if constexpr (sizeof(CS) == 4) {
-        unsigned v = reinterpret_cast<const unsigned*>(cp)[r];
-        c.x = bf16_to_f32((unsigned short)(v & 0xffff));
-        c.y = bf16_to_f32((unsigned short)(v >> 16));
-      } else {
-        CS v = cp[r];
-        c.x = v.x;
-        c.y = v.y;
+  for (int i = 0; i < kAdjCols; ++i)
+#pragma unroll
+    for (int q = 0; q < QT; ++q) acc[i][q] = czero<C>();
+  const typename CV::V* base = reinterpret_cast<const typename CV::V*>(cores + core_off[pair]);
+  const long long cstride = RTp / VR;
+  // columns past the last one re-read the last valid column (results unused)
+  const typename CV::V* cp[kAdjCols];
+#pragma unroll
+  for (int i = 0; i < kAdjCols; ++i) cp[i] = base + (long long)(cb + min(i, max(ncol - 1, 0))) * cstride;
+  if (ncol > 0) {
+    for (int rb = lane * VR; rb < RTp; rb += 64 * VR) {
+      typename CV::V vv[kAdjCols];
+#pragma unroll
+      for (int i = 0; i < kAdjCols; ++i) vv[i] = cp[i][rb / VR];
+      C yv[VR][QT];
+#pragma unroll
+      for (int v = 0; v < VR; ++v)
+#pragma unroll
+        for (int q = 0; q < QT; ++q) yv[v][q] = y[(rb + v) * QT + q];
+#pragma unroll
+      for (int i = 0; i < kAdjCols; ++i) {
+        C c[VR];
+        CV::get(vv[i], c);
+#pragma unroll
+        for (int v = 0; v < VR; ++v)
+#pragma unroll
+          for (int q = 0; q < QT; ++q) acc[i][q] = cfma_conj(acc[i][q], c[v], yv[v][q]);
       }
-#pragma unroll
-      for (int q = 0; q < QM; ++q)
-        if (q < Q) acc[q] = cfma_conj(acc[q], c, y[r * Q + q]);
-    }
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-      if (q < Q) {
-        T re = acc[q].x, im = acc[q].y;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          re += __shfl_xor(re, off, 64);
-          im += __shfl_xor(im, off, 64);
-        }
-        acc[q].x = re;
-        acc[q].y = im;
-      }
-    }
-    if (lane == 0) {
-      long long pos = padded_pos<D>(col, rs, a.Rs);
-      for (int q = 0; q < Q; ++q) F[(sitem * a.Es + pos) * a.nrhs + q0 + q] = acc[q];
     }
   }
+#pragma unroll
+  for (int i = 0; i < kAdjCols; ++i)
+#pragma unroll
+    for (int q = 0; q < QT; ++q) {
+      T re = acc[i][q].x, im = acc[i][q].y;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o, 64);
+        im += __shfl_xor(im, o, 64);
+      }
+      acc[i][q].x = re;
+      acc[i][q].y = im;
+    }
+  if (lane < ncol) {
+    // lane i writes column cb + i (values are identical across lanes)
+#pragma unroll
+    for (int i = 0; i < kAdjCols; ++i)
+      if (i == lane) {
+        const long long pos = padded_pos<D>(cb + i, rs, a.Rs);
+#pragma unroll
+        for (int q = 0; q < QT; ++q)
+          if (q < Qa) F[(sitem * a.Es + pos) * a.nrhs + q0 + q] = acc[i][q];
+      }
+  }
   if (c0 == 0) {
-    for (long long p = threadIdx.x; p < a.Es; p += blockDim.x)
+    for (long long p = threadIdx.x; p < a.Es; p += kThreads)
       if (is_padding<D>(p, rs, a.Rs))
-        for (int q = 0; q < Q; ++q) F[(sitem * a.Es + p) * a.nrhs + q0 + q] = czero<C>();
+        for (int q = 0; q < Qa; ++q) F[(sitem * a.Es + p) * a.nrhs + q0 + q] = czero<C>();
   }
 }
 
@@ -618,14 +769,41 @@ static StageArgs stage_args(const Plan& p, const Level& fine, const Level* coars
   return a;
 }
 
-static int fanout_lds_per_q(const StageArgs& a, int d) {
-  if (d == 2) return a.R[0] * a.A[1];
-  return a.R[0] * a.A[1] * a.A[2] + a.R[0] * a.R[1] * a.A[2];
+constexpr int kTargetWorkgroups = 2048;  // enough to cover 256 CUs several times
+
+template <class T, int D, int QT>
+static tb_status launch_fanout(StageArgs a, dim3 grid, size_t lds, const void* in, void* out,
+                               const void* mats, hipStream_t stream) {
+  using C = typename CplxOf<T>::type;
+  TB_TRY(set_lds(stage_fanout<T, D, QT>, lds));
+  stage_fanout<T, D, QT><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+  return TB_OK;
 }
 
-static int fanin_lds_per_q(const StageArgs& a, int d) {
-  if (d == 2) return a.A[0] * a.R[1];
-  return a.A[0] * a.R[1] * a.R[2] + a.A[0] * a.A[1] * a.R[2];
+template <class T, int D, int QT, int NPER>
+static tb_status launch_fanin(StageArgs a, dim3 grid, size_t lds, const void* in, void* out,
+                              const void* mats, hipStream_t stream) {
+  using C = typename CplxOf<T>::type;
+  TB_TRY(set_lds(stage_fanin<T, D, QT, NPER>, lds));
+  stage_fanin<T, D, QT, NPER><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+  return TB_OK;
+}
+
+// LDS elements of one workgroup for a slice of `chunk` entries of the first
+// mode and QT right-hand sides.
+static long long stage_lds_elems(const StageArgs& a, int d, bool fanout, int chunk, int QT) {
+  long long e = 0;
+  for (int k = 1; k < d; ++k) e += (long long)a.R[k] * a.A[k];
+  if (fanout) {
+    e += (long long)chunk * a.A[0];
+    if (d == 2) e += (long long)chunk * a.A[1] * QT;
+    else e += (long long)chunk * a.A[1] * a.A[2] * QT + (long long)chunk * a.R[1] * a.A[2] * QT;
+  } else {
+    e += (long long)a.R[0] * chunk;
+    if (d == 2) e += (long long)chunk * a.R[1] * QT;
+    else e += (long long)chunk * a.R[1] * a.R[2] * QT + (long long)chunk * a.A[1] * a.R[2] * QT;
+  }
+  return e;
 }
 
 template <class T>
@@ -635,36 +813,69 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
   const int d = p.d;
   int limit = 0;
   TB_TRY(lds_limit(&limit));
-  int mats_elems = 0;
-  for (int k = 0; k < d; ++k) mats_elems += a.R[k] * a.A[k];
-  int per_q = fanout ? fanout_lds_per_q(a, d) : fanin_lds_per_q(a, d);
-  int qmax = (int)((limit / (int)sizeof(C) - mats_elems) / std::max(per_q, 1));
+  const int QT = a.nrhs == 1 ? 1 : 8;
+  const long long blocks = (long long)n_items * a.nblk;
+  const int dim = fanout ? a.R[0] : a.A[0];
+  long long per_row = QT;  // fan-in outputs per entry of the first mode
+  for (int k = 1; k < d; ++k) per_row *= a.A[k];
+  int chunk = (int)std::max<long long>(1, (dim * blocks + kTargetWorkgroups - 1) / kTargetWorkgroups);
+  chunk = std::min(chunk, dim);
   if (!fanout) {
-    int nout = 1;
-    for (int k = 0; k < d; ++k) nout *= a.A[k];
-    qmax = std::min(qmax, kMaxPer * kThreads / nout);
+    const long long cmax = 16LL * kThreads / per_row;
+    if (cmax < 1)
+      return fail(TB_ERR_UNSUPPORTED, "transfer block exceeds the per-workgroup register budget");
+    chunk = (int)std::min<long long>(chunk, cmax);
   }
-  if (qmax < 1)
-    return fail(TB_ERR_UNSUPPORTED, "transfer block exceeds the per-workgroup LDS/register budget");
-  a.Q = std::min(a.nrhs, qmax);
-  size_t lds = (size_t)(mats_elems + (size_t)per_q * a.Q) * sizeof(C);
-  dim3 grid((unsigned)(n_items * a.nblk), (unsigned)((a.nrhs + a.Q - 1) / a.Q));
+  while (chunk > 1 && stage_lds_elems(a, d, fanout, chunk, QT) * (long long)sizeof(C) > limit) --chunk;
+  const size_t lds = (size_t)stage_lds_elems(a, d, fanout, chunk, QT) * sizeof(C);
+  if (lds > (size_t)limit)
+    return fail(TB_ERR_UNSUPPORTED, "transfer block exceeds the per-workgroup LDS budget");
+  a.chunk = chunk;
+  a.nsplit = (dim + chunk - 1) / chunk;
+  dim3 grid((unsigned)(blocks * a.nsplit), (unsigned)((a.nrhs + QT - 1) / QT));
+  const bool small = (long long)chunk * per_row <= 4LL * kThreads;
+  tb_status st;
   if (fanout) {
-    if (d == 2) {
-      TB_TRY(set_lds(stage_fanout<T, 2>, lds));
-      stage_fanout<T, 2><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
-    } else {
-      TB_TRY(set_lds(stage_fanout<T, 3>, lds));
-      stage_fanout<T, 3><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
-    }
+    if (d == 2) st = QT == 1 ? launch_fanout<T, 2, 1>(a, grid, lds, in, out, mats, stream)
+                             : launch_fanout<T, 2, 8>(a, grid, lds, in, out, mats, stream);
+    else st = QT == 1 ? launch_fanout<T, 3, 1>(a, grid, lds, in, out, mats, stream)
+                      : launch_fanout<T, 3, 8>(a, grid, lds, in, out, mats, stream);
+  } else if (d == 2) {
+    if (QT == 1) st = small ? launch_fanin<T, 2, 1, 4>(a, grid, lds, in, out, mats, stream)
+                            : launch_fanin<T, 2, 1, 16>(a, grid, lds, in, out, mats, stream);
+    else st = small ? launch_fanin<T, 2, 8, 4>(a, grid, lds, in, out, mats, stream)
+                    : launch_fanin<T, 2, 8, 16>(a, grid, lds, in, out, mats, stream);
   } else {
-    if (d == 2) {
-      TB_TRY(set_lds(stage_fanin<T, 2>, lds));
-      stage_fanin<T, 2><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
-    } else {
-      TB_TRY(set_lds(stage_fanin<T, 3>, lds));
-      stage_fanin<T, 3><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
-    }
+    if (QT == 1) st = small ? launch_fanin<T, 3, 1, 4>(a, grid, lds, in, out, mats, stream)
+                            : launch_fanin<T, 3, 1, 16>(a, grid, lds, in, out, mats, stream);
+    else st = small ? launch_fanin<T, 3, 8, 4>(a, grid, lds, in, out, mats, stream)
+                    : launch_fanin<T, 3, 8, 16>(a, grid, lds, in, out, mats, stream);
+  }
+  TB_TRY(st);
+  TB_HIP_TRY(hipGetLastError());
+  return TB_OK;
+}
+
+template <class T, class CS, int D, int QT>
+static tb_status launch_core_q(const Plan& p, CoreArgs a, bool adjoint, const void* cores,
+                               const void* in, void* out, int maxRS, int maxRTp, int limit,
+                               hipStream_t stream) {
+  using C = typename CplxOf<T>::type;
+  constexpr int VR = CoreVec<CS>::VR;
+  const unsigned gy = (unsigned)((a.nrhs + QT - 1) / QT);
+  if (!adjoint) {
+    const size_t lds = ((size_t)maxRS * QT + (size_t)kThreads * VR * QT) * sizeof(C);
+    if (lds > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "core block exceeds the LDS budget");
+    const int lv = VR == 1 ? 0 : (VR == 2 ? 1 : 2);
+    TB_TRY(set_lds(core_fwd<T, CS, D, QT>, lds));
+    core_fwd<T, CS, D, QT><<<dim3((unsigned)p.fwd_units[lv].size(), gy), kThreads, lds, stream>>>(
+        a, (const CS*)cores, p.core_off_d, p.pair_meta_d, p.fwd_units_d[lv], (const C*)in, (C*)out);
+  } else {
+    const size_t lds = (size_t)maxRTp * QT * sizeof(C);
+    if (lds > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "core block exceeds the LDS budget");
+    TB_TRY(set_lds(core_adj<T, CS, D, QT>, lds));
+    core_adj<T, CS, D, QT><<<dim3((unsigned)p.adj_units.size(), gy), kThreads, lds, stream>>>(
+        a, (const CS*)cores, p.core_off_d, p.pair_meta_d, p.adj_units_d, (const C*)in, (C*)out);
   }
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;
@@ -673,7 +884,6 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
 template <class T, class CS>
 static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* cores, const void* in,
                              void* out, hipStream_t stream) {
-  using C = typename CplxOf<T>::type;
   const int d = p.d;
   const Level& st = p.src[p.Lt];
   const Level& tt = p.tgt[p.Ls];
@@ -687,7 +897,6 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
     a.Rt[k] = tt.R[k];
   }
   a.nrhs = nrhs;
-  a.Q = std::min(nrhs, 8);
   int maxRS = 0, maxRTp = 0;
   for (long long pr = 0; pr < p.npairs; ++pr) {
     maxRS = std::max(maxRS, p.pair_meta[(size_t)pr * kPairMeta + 1]);
@@ -695,41 +904,11 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
   }
   int limit = 0;
   TB_TRY(lds_limit(&limit));
-  size_t lds;
-  for (;;) {
-    lds = adjoint ? (size_t)maxRTp * a.Q * sizeof(C)
-                  : ((size_t)maxRS * a.Q + (size_t)kThreads * a.Q) * sizeof(C);
-    if (lds <= (size_t)limit || a.Q == 1) break;
-    a.Q = std::max(1, a.Q / 2);
-  }
-  if (lds > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "core block exceeds the LDS budget");
-  const bool is_bf16 = sizeof(CS) == 4;
-  (void)is_bf16;
-  if (!adjoint) {
-    dim3 grid((unsigned)p.fwd_units.size(), (unsigned)((nrhs + a.Q - 1) / a.Q));
-    if (d == 2) {
-      TB_TRY(set_lds(core_fwd<T, CS, 2>, lds));
-      core_fwd<T, CS, 2><<<grid, kThreads, lds, stream>>>(a, (const CS*)cores, p.core_off_d, p.pair_meta_d,
-                                                         p.fwd_units_d, (const C*)in, (C*)out);
-    } else {
-      TB_TRY(set_lds(core_fwd<T, CS, 3>, lds));
-      core_fwd<T, CS, 3><<<grid, kThreads, lds, stream>>>(a, (const CS*)cores, p.core_off_d, p.pair_meta_d,
-                                                         p.fwd_units_d, (const C*)in, (C*)out);
-    }
-  } else {
-    dim3 grid((unsigned)p.adj_units.size(), (unsigned)((nrhs + a.Q - 1) / a.Q));
-    if (d == 2) {
-      TB_TRY(set_lds(core_adj<T, CS, 2>, lds));
-      core_adj<T, CS, 2><<<grid, kThreads, lds, stream>>>(a, (const CS*)cores, p.core_off_d, p.pair_meta_d,
-                                                         p.adj_units_d, (const C*)in, (C*)out);
-    } else {
-      TB_TRY(set_lds(core_adj<T, CS, 3>, lds));
-      core_adj<T, CS, 3><<<grid, kThreads, lds, stream>>>(a, (const CS*)cores, p.core_off_d, p.pair_meta_d,
-                                                         p.adj_units_d, (const C*)in, (C*)out);
-    }
-  }
-  TB_HIP_TRY(hipGetLastError());
-  return TB_OK;
+  if (nrhs == 1)
+    return d == 2 ? launch_core_q<T, CS, 2, 1>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream)
+                  : launch_core_q<T, CS, 3, 1>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream);
+  return d == 2 ? launch_core_q<T, CS, 2, 4>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream)
+                : launch_core_q<T, CS, 3, 4>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream);
 }
 
 // Records an event pair around one stage launch when timing is enabled.

@@ -106,9 +106,10 @@ struct Plan {
   void* cores[3] = {nullptr, nullptr, nullptr};  // indexed by tb_dtype
   int* pair_meta_d = nullptr;
   long long* core_off_d = nullptr;
-  // core work lists: forward row panels / adjoint column panels
-  std::vector<int2> fwd_units, adj_units;
-  int2* fwd_units_d = nullptr;
+  // core work lists: forward row panels of 64 VR rows (index log2 VR, for
+  // VR = 1, 2, 4 rows per 16-byte load) / adjoint panels of 32 columns
+  std::vector<int2> fwd_units[3], adj_units;
+  int2* fwd_units_d[3] = {nullptr, nullptr, nullptr};
   int2* adj_units_d = nullptr;
   // device skeleton tables of the two top levels (core evaluation)
   int* top_src_skel_d = nullptr;     // [item][k][Rs]
