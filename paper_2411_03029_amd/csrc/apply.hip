@@ -46,6 +46,18 @@ struct StageArgs {
   int outer_level, outer_block;   // outer multi-set level and block size
   int nrhs;
   int conj;
+  const int* rank_f;              // true ranks of the fine level [item][k][blk]
+  const int* rank_c;              // true ranks of the coarse level (null: leaves)
+  int nb_c;                       // blocks per mode of a coarse item
+  int Rc[kMaxD];                  // padded ranks of the coarse level
+};
+
+// True extent of mode k of the coarse block beta_k: the two children's
+// skeletons of sizes h1, h2 sit at offsets 0 and Rc in the padded block.
+// Leaves (caller's array) are dense: h1 = A, no second part.
+struct Seg {
+  int c, h1, off2;
+  __device__ int pos(int j) const { return j < h1 ? j : off2 + (j - h1); }
 };
 
 template <int D>
@@ -130,9 +142,28 @@ __device__ __forceinline__ long long fine_base(const StageArgs& a, int fi, const
   return base * a.nrhs + q0;
 }
 
+template <int D>
+__device__ __forceinline__ void coarse_segs(const StageArgs& a, int citem, const int* beta, Seg* sg) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    if (a.rank_c == nullptr) {
+      sg[k].c = a.A[k];
+      sg[k].h1 = a.A[k];
+      sg[k].off2 = 0;
+    } else {
+      const int* rc = a.rank_c + ((long long)citem * D + k) * a.nb_c + 2 * beta[k];
+      sg[k].h1 = rc[0];
+      sg[k].c = rc[0] + rc[1];
+      sg[k].off2 = a.Rc[k];
+    }
+  }
+}
+
 // --------------------------------------------------------------- fan-out --
 // fine(a_0..a_{D-1}, q) = sum_j prod_k M_k[a_k][j_k] coarse(j_0..j_{D-1}, q)
-// for a_0 in this workgroup's slice [lo, lo + na) of the first mode.
+// over true ranks (rows a_k < r_k) and the coarse block's true entries,
+// for a_0 in this workgroup's slice [lo, lo + na).  Padding is never
+// written or read: every consumer loops over true extents only.
 template <class T, int D, int QT>
 __global__ void __launch_bounds__(kThreads)
     stage_fanout(StageArgs a, const typename CplxOf<T>::type* __restrict__ coarse,
@@ -147,108 +178,117 @@ __global__ void __launch_bounds__(kThreads)
   const int fi = bid / a.nblk;
   int beta[D];
   unflatten_blk<D>(bid % a.nblk, a.nb, beta);
+  int r[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) r[k] = a.rank_f[((long long)fi * D + k) * a.nb + beta[k]];
   const int lo = split * a.chunk;
-  const int na = min(a.R[0], lo + a.chunk) - lo;
+  const int na = min(r[0], lo + a.chunk) - lo;
+  if (na <= 0) return;
+  const int citem = a.coarse_global ? (fi >> (D * a.lvl)) : parent_of<D>(fi, a.lvl);
+  Seg sg[D];
+  coarse_segs<D>(a, citem, beta, sg);
   const int q0 = blockIdx.y * QT;
   const int Qa = min(QT, a.nrhs - q0);
-  const int A0 = a.A[0];
-  // matrices: rows lo..lo+na of M_0, then M_1.. M_{D-1}
-  const C* mbase = mats + (long long)fi * a.mat_item_stride;
-  C* m0 = sm;
-  C* mk[D];
-  mk[0] = m0;
-  int off = na * A0;
-  {
-    const C* src = mbase + a.mat_k_off[0] + ((long long)beta[0] * a.R[0] + lo) * A0;
-    for (int i = threadIdx.x; i < na * A0; i += kThreads) {
-      C v = src[i];
-      if (a.conj) v.y = -v.y;
-      m0[i] = v;
-    }
-  }
-#pragma unroll
-  for (int k = 1; k < D; ++k) {
-    mk[k] = sm + off;
-    const int cnt = a.R[k] * a.A[k];
-    const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * cnt;
-    for (int i = threadIdx.x; i < cnt; i += kThreads) {
-      C v = src[i];
-      if (a.conj) v.y = -v.y;
-      mk[k][i] = v;
-    }
-    off += cnt;
-  }
-  C* buf1 = sm + off;
-  const int citem = a.coarse_global ? (fi >> (D * a.lvl)) : parent_of<D>(fi, a.lvl);
   CoarseAddr<D> ca;
   ca.init(a, citem, beta, q0);
   long long fs[D];
   const long long fb = fine_base<D>(a, fi, beta, q0, fs);
-  __syncthreads();
+  const C* mbase = mats + (long long)fi * a.mat_item_stride;
+  const C* M0 = mbase + a.mat_k_off[0] + (long long)beta[0] * a.R[0] * a.A[0];
+  // compact copies of M_1.. (r_k x c_k) in LDS
+  C* mk[D];
+  int off = 0;
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    mk[k] = sm + off;
+    const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
+    const int ck = sg[k].c;
+    for (int i = threadIdx.x; i < r[k] * ck; i += kThreads) {
+      const int row = i / ck, j = i % ck;
+      C v = src[row * a.A[k] + sg[k].pos(j)];
+      if (a.conj) v.y = -v.y;
+      mk[k][i] = v;
+    }
+    off += a.R[k] * a.A[k];
+  }
+  C* buf1 = sm + off;
+  const int c0 = sg[0].c, c1 = sg[1].c;
+  const int A0 = a.A[0];
   if constexpr (D == 2) {
-    const int A1 = a.A[1], R1 = a.R[1];
-    for (int idx = threadIdx.x; idx < na * A1 * QT; idx += kThreads) {
-      const int q = idx % QT, t = idx / QT, j1 = t % A1, ai = t / A1;
+    // buf1[ai][j1][q] = sum_j0 M0[lo+ai][j0] coarse(j0, j1, q)
+    for (int idx = threadIdx.x; idx < na * c1 * QT; idx += kThreads) {
+      const int q = idx % QT, t = idx / QT, j1 = t % c1, ai = t / c1;
       C acc = czero<C>();
       if (q < Qa) {
-        const C* src = coarse + ca.base + j1 * ca.stride[1] + q * ca.qstride;
-        const C* mr = m0 + ai * A0;
-        for (int j0 = 0; j0 < A0; ++j0) acc = cfma(acc, mr[j0], src[j0 * ca.stride[0]]);
+        const C* src = coarse + ca.base + sg[1].pos(j1) * ca.stride[1] + q * ca.qstride;
+        const C* mr = M0 + (lo + ai) * A0;
+        for (int j0 = 0; j0 < c0; ++j0) {
+          const int p0 = sg[0].pos(j0);
+          C m = mr[p0];
+          if (a.conj) m.y = -m.y;
+          acc = cfma(acc, m, src[p0 * ca.stride[0]]);
+        }
       }
       buf1[idx] = acc;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < na * R1 * QT; idx += kThreads) {
-      const int q = idx % QT, t = idx / QT, a1 = t % R1, ai = t / R1;
+    for (int idx = threadIdx.x; idx < na * r[1] * QT; idx += kThreads) {
+      const int q = idx % QT, t = idx / QT, a1 = t % r[1], ai = t / r[1];
       if (q >= Qa) continue;
-      const C* src = buf1 + (ai * A1) * QT + q;
-      const C* mr = mk[1] + a1 * A1;
+      const C* src = buf1 + (ai * c1) * QT + q;
+      const C* mr = mk[1] + a1 * c1;
       C acc = czero<C>();
-      for (int j1 = 0; j1 < A1; ++j1) acc = cfma(acc, mr[j1], src[j1 * QT]);
+      for (int j1 = 0; j1 < c1; ++j1) acc = cfma(acc, mr[j1], src[j1 * QT]);
       fine[fb + (lo + ai) * fs[0] + a1 * fs[1] + q] = acc;
     }
   } else {
-    const int A1 = a.A[1], A2 = a.A[2], R1 = a.R[1], R2 = a.R[2];
-    C* buf2 = buf1 + na * A1 * A2 * QT;
-    for (int idx = threadIdx.x; idx < na * A1 * A2 * QT; idx += kThreads) {
+    const int c2 = sg[2].c;
+    C* buf2 = buf1 + a.chunk * a.A[1] * a.A[2] * QT;
+    for (int idx = threadIdx.x; idx < na * c1 * c2 * QT; idx += kThreads) {
       const int q = idx % QT;
       int t = idx / QT;
-      const int j2 = t % A2;
-      t /= A2;
-      const int j1 = t % A1, ai = t / A1;
+      const int j2 = t % c2;
+      t /= c2;
+      const int j1 = t % c1, ai = t / c1;
       C acc = czero<C>();
       if (q < Qa) {
-        const C* src = coarse + ca.base + j1 * ca.stride[1] + j2 * ca.stride[2] + q * ca.qstride;
-        const C* mr = m0 + ai * A0;
-        for (int j0 = 0; j0 < A0; ++j0) acc = cfma(acc, mr[j0], src[j0 * ca.stride[0]]);
+        const C* src = coarse + ca.base + sg[1].pos(j1) * ca.stride[1] + sg[2].pos(j2) * ca.stride[2] +
+                       q * ca.qstride;
+        const C* mr = M0 + (lo + ai) * A0;
+        for (int j0 = 0; j0 < c0; ++j0) {
+          const int p0 = sg[0].pos(j0);
+          C m = mr[p0];
+          if (a.conj) m.y = -m.y;
+          acc = cfma(acc, m, src[p0 * ca.stride[0]]);
+        }
       }
       buf1[idx] = acc;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < na * R1 * A2 * QT; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < na * r[1] * c2 * QT; idx += kThreads) {
       const int q = idx % QT;
       int t = idx / QT;
-      const int j2 = t % A2;
-      t /= A2;
-      const int a1 = t % R1, ai = t / R1;
-      const C* src = buf1 + ((ai * A1) * A2 + j2) * QT + q;
-      const C* mr = mk[1] + a1 * A1;
+      const int j2 = t % c2;
+      t /= c2;
+      const int a1 = t % r[1], ai = t / r[1];
+      const C* src = buf1 + ((ai * c1) * c2 + j2) * QT + q;
+      const C* mr = mk[1] + a1 * c1;
       C acc = czero<C>();
-      for (int j1 = 0; j1 < A1; ++j1) acc = cfma(acc, mr[j1], src[j1 * A2 * QT]);
+      for (int j1 = 0; j1 < c1; ++j1) acc = cfma(acc, mr[j1], src[j1 * c2 * QT]);
       buf2[idx] = acc;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < na * R1 * R2 * QT; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < na * r[1] * r[2] * QT; idx += kThreads) {
       const int q = idx % QT;
       int t = idx / QT;
-      const int a2 = t % R2;
-      t /= R2;
-      const int a1 = t % R1, ai = t / R1;
+      const int a2 = t % r[2];
+      t /= r[2];
+      const int a1 = t % r[1], ai = t / r[1];
       if (q >= Qa) continue;
-      const C* src = buf2 + ((ai * R1 + a1) * A2) * QT + q;
-      const C* mr = mk[2] + a2 * A2;
+      const C* src = buf2 + ((ai * r[1] + a1) * c2) * QT + q;
+      const C* mr = mk[2] + a2 * c2;
       C acc = czero<C>();
-      for (int j2 = 0; j2 < A2; ++j2) acc = cfma(acc, mr[j2], src[j2 * QT]);
+      for (int j2 = 0; j2 < c2; ++j2) acc = cfma(acc, mr[j2], src[j2 * QT]);
       fine[fb + (lo + ai) * fs[0] + a1 * fs[1] + a2 * fs[2] + q] = acc;
     }
   }
@@ -256,9 +296,12 @@ __global__ void __launch_bounds__(kThreads)
 
 // ---------------------------------------------------------------- fan-in --
 // coarse(a_0..a_{D-1}, q) = sum_children sum_j prod_k M_k[j_k][a_k] fine_c(j, q)
-// for a_0 in this workgroup's slice [lo, lo + na) of the first coarse mode;
-// the outputs stay in registers (NPER per thread) across the children.
-template <class T, int D, int QT, int NPER>
+// over the children's true ranks, for the coarse block's true entries with
+// a_0 in this workgroup's slice [lo, lo + na) (compact numbering).  All
+// children are processed together: two barriers per workgroup.
+constexpr int kMaxChildren = 1 << kMaxD;
+
+template <class T, int D, int QT>
 __global__ void __launch_bounds__(kThreads)
     stage_fanin(StageArgs a, const typename CplxOf<T>::type* __restrict__ fine,
                 typename CplxOf<T>::type* __restrict__ coarse,
@@ -272,142 +315,161 @@ __global__ void __launch_bounds__(kThreads)
   const int ci = bid / a.nblk;
   int beta[D];
   unflatten_blk<D>(bid % a.nblk, a.nb, beta);
-  const int A0 = a.A[0], R0 = a.R[0];
+  Seg sg[D];
+  coarse_segs<D>(a, ci, beta, sg);
   const int lo = split * a.chunk;
-  const int na = min(A0, lo + a.chunk) - lo;
+  const int na = min(sg[0].c, lo + a.chunk) - lo;
+  if (na <= 0) return;
   const int q0 = blockIdx.y * QT;
   const int Qa = min(QT, a.nrhs - q0);
   const int nchild = a.coarse_global ? 1 : (1 << D);
-  int nout = na * QT;
-#pragma unroll
-  for (int k = 1; k < D; ++k) nout *= a.A[k];
-  C acc[NPER];
-#pragma unroll
-  for (int i = 0; i < NPER; ++i) acc[i] = czero<C>();
-  // LDS: m0 = M_0[:, lo..lo+na] (R0 x na), M_1.., buf1, buf2
-  C* m0 = sm;
-  C* mk[D];
-  mk[0] = m0;
-  int off = R0 * na;
-#pragma unroll
-  for (int k = 1; k < D; ++k) {
-    mk[k] = sm + off;
-    off += a.R[k] * a.A[k];
-  }
-  C* buf1 = sm + off;
-  for (int c = 0; c < nchild; ++c) {
+  // children: item, ranks, fine base
+  __shared__ int cfi[kMaxChildren], crk[kMaxChildren][kMaxD];
+  __shared__ long long cfb[kMaxChildren];
+  if (threadIdx.x < nchild) {
+    const int c = threadIdx.x;
     const int fi = a.coarse_global ? ci : child_of<D>(ci, a.lvl, c);
-    const C* mbase = mats + (long long)fi * a.mat_item_stride;
-    __syncthreads();
-    {
-      const C* src = mbase + a.mat_k_off[0] + (long long)beta[0] * R0 * A0 + lo;
-      for (int i = threadIdx.x; i < R0 * na; i += kThreads) {
-        const int j0 = i / na, ai = i % na;
-        C v = src[j0 * A0 + ai];
-        if (a.conj) v.y = -v.y;
-        m0[i] = v;
-      }
-    }
+    cfi[c] = fi;
+#pragma unroll
+    for (int k = 0; k < D; ++k) crk[c][k] = a.rank_f[((long long)fi * D + k) * a.nb + beta[k]];
+    long long fs_[D];
+    cfb[c] = fine_base<D>(a, fi, beta, q0, fs_);
+  }
+  long long fs[D];
+  (void)fine_base<D>(a, 0, beta, 0, fs);   // strides only
+  __syncthreads();
+  const int A0 = a.A[0];
+  const int R1 = a.R[1];
+  const int c1 = sg[1].c;
+  // per-child compact copies of M_1.. (r_k x c_k, row stride A_k) in LDS
+  int msz = 0;
+#pragma unroll
+  for (int k = 1; k < D; ++k) msz += a.R[k] * a.A[k];
+  C* mall = sm;
+  for (int c = 0; c < nchild; ++c) {
+    const C* mbase = mats + (long long)cfi[c] * a.mat_item_stride;
+    int off = c * msz;
 #pragma unroll
     for (int k = 1; k < D; ++k) {
-      const int cnt = a.R[k] * a.A[k];
-      const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * cnt;
-      for (int i = threadIdx.x; i < cnt; i += kThreads) {
-        C v = src[i];
+      const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
+      const int ck = sg[k].c, rk = crk[c][k];
+      for (int i = threadIdx.x; i < rk * ck; i += kThreads) {
+        const int row = i / ck, j = i % ck;
+        C v = src[row * a.A[k] + sg[k].pos(j)];
         if (a.conj) v.y = -v.y;
-        mk[k][i] = v;
+        mall[off + i] = v;
       }
-    }
-    long long fs[D];
-    const long long fb = fine_base<D>(a, fi, beta, q0, fs);
-    __syncthreads();
-    if constexpr (D == 2) {
-      const int R1 = a.R[1], A1 = a.A[1];
-      for (int idx = threadIdx.x; idx < na * R1 * QT; idx += kThreads) {
-        const int q = idx % QT, t = idx / QT, j1 = t % R1, ai = t / R1;
-        C s = czero<C>();
-        if (q < Qa) {
-          const C* src = fine + fb + j1 * fs[1] + q;
-          for (int j0 = 0; j0 < R0; ++j0) s = cfma(s, m0[j0 * na + ai], src[j0 * fs[0]]);
-        }
-        buf1[idx] = s;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < NPER; ++i) {
-        const int idx = threadIdx.x + i * kThreads;
-        if (idx < nout) {
-          const int q = idx % QT, t = idx / QT, a1 = t % A1, ai = t / A1;
-          const C* src = buf1 + (ai * R1) * QT + q;
-          C s = acc[i];
-          for (int j1 = 0; j1 < R1; ++j1) s = cfma(s, mk[1][j1 * A1 + a1], src[j1 * QT]);
-          acc[i] = s;
-        }
-      }
-    } else {
-      const int R1 = a.R[1], R2 = a.R[2], A1 = a.A[1], A2 = a.A[2];
-      C* buf2 = buf1 + na * R1 * R2 * QT;
-      for (int idx = threadIdx.x; idx < na * R1 * R2 * QT; idx += kThreads) {
-        const int q = idx % QT;
-        int t = idx / QT;
-        const int j2 = t % R2;
-        t /= R2;
-        const int j1 = t % R1, ai = t / R1;
-        C s = czero<C>();
-        if (q < Qa) {
-          const C* src = fine + fb + j1 * fs[1] + j2 * fs[2] + q;
-          for (int j0 = 0; j0 < R0; ++j0) s = cfma(s, m0[j0 * na + ai], src[j0 * fs[0]]);
-        }
-        buf1[idx] = s;
-      }
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < na * A1 * R2 * QT; idx += kThreads) {
-        const int q = idx % QT;
-        int t = idx / QT;
-        const int j2 = t % R2;
-        t /= R2;
-        const int a1 = t % A1, ai = t / A1;
-        const C* src = buf1 + ((ai * R1) * R2 + j2) * QT + q;
-        C s = czero<C>();
-        for (int j1 = 0; j1 < R1; ++j1) s = cfma(s, mk[1][j1 * A1 + a1], src[j1 * R2 * QT]);
-        buf2[idx] = s;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < NPER; ++i) {
-        const int idx = threadIdx.x + i * kThreads;
-        if (idx < nout) {
-          const int q = idx % QT;
-          int t = idx / QT;
-          const int a2 = t % A2;
-          t /= A2;
-          const int a1 = t % A1, ai = t / A1;
-          const C* src = buf2 + ((ai * A1 + a1) * R2) * QT + q;
-          C s = acc[i];
-          for (int j2 = 0; j2 < R2; ++j2) s = cfma(s, mk[2][j2 * A2 + a2], src[j2 * QT]);
-          acc[i] = s;
-        }
-      }
+      off += a.R[k] * a.A[k];
     }
   }
-  CoarseAddr<D> ca;
-  ca.init(a, ci, beta, q0);
-#pragma unroll
-  for (int i = 0; i < NPER; ++i) {
-    const int idx = threadIdx.x + i * kThreads;
-    if (idx < nout) {
-      const int q = idx % QT;
+  C* buf1 = sm + nchild * msz;
+  if constexpr (D == 2) {
+    // buf1[c][ai][j1][q] = sum_j0 M0_c[j0][pos(lo+ai)] fine_c(j0, j1, q), j1 < r1(c)
+    const int per_c = na * R1 * QT;
+    for (int idx = threadIdx.x; idx < nchild * per_c; idx += kThreads) {
+      const int c = idx / per_c;
+      int t = idx % per_c;
+      const int q = t % QT;
+      t /= QT;
+      const int j1 = t % R1, ai = t / R1;
+      if (j1 >= crk[c][1]) continue;
+      C acc = czero<C>();
       if (q < Qa) {
-        int t = idx / QT;
-        long long o = ca.base + q * ca.qstride;
-#pragma unroll
-        for (int k = D - 1; k >= 1; --k) {
-          o += (long long)(t % a.A[k]) * ca.stride[k];
-          t /= a.A[k];
+        const C* M0 = mats + (long long)cfi[c] * a.mat_item_stride + a.mat_k_off[0] +
+                      (long long)beta[0] * a.R[0] * A0 + sg[0].pos(lo + ai);
+        const C* src = fine + cfb[c] + j1 * fs[1] + q;
+        const int r0 = crk[c][0];
+        for (int j0 = 0; j0 < r0; ++j0) {
+          C m = M0[j0 * A0];
+          if (a.conj) m.y = -m.y;
+          acc = cfma(acc, m, src[j0 * fs[0]]);
         }
-        o += (long long)(lo + t) * ca.stride[0];
-        coarse[o] = acc[i];
       }
+      buf1[idx] = acc;
+    }
+    __syncthreads();
+    CoarseAddr<D> ca;
+    ca.init(a, ci, beta, q0);
+    for (int idx = threadIdx.x; idx < na * c1 * QT; idx += kThreads) {
+      const int q = idx % QT, t = idx / QT, j1o = t % c1, ai = t / c1;
+      if (q >= Qa) continue;
+      C acc = czero<C>();
+      for (int c = 0; c < nchild; ++c) {
+        const C* m1 = mall + c * msz;
+        const C* src = buf1 + c * per_c + (ai * R1) * QT + q;
+        const int r1 = crk[c][1];
+        for (int j1 = 0; j1 < r1; ++j1) acc = cfma(acc, m1[j1 * c1 + j1o], src[j1 * QT]);
+      }
+      coarse[ca.base + sg[0].pos(lo + ai) * ca.stride[0] + sg[1].pos(j1o) * ca.stride[1] + q * ca.qstride] =
+          acc;
+    }
+  } else {
+    const int R2 = a.R[2];
+    const int c2 = sg[2].c;
+    const int per_c1 = na * R1 * R2 * QT;
+    const int per_c2 = na * a.A[1] * R2 * QT;
+    C* buf2 = buf1 + nchild * per_c1;
+    for (int idx = threadIdx.x; idx < nchild * per_c1; idx += kThreads) {
+      const int c = idx / per_c1;
+      int t = idx % per_c1;
+      const int q = t % QT;
+      t /= QT;
+      const int j2 = t % R2;
+      t /= R2;
+      const int j1 = t % R1, ai = t / R1;
+      if (j1 >= crk[c][1] || j2 >= crk[c][2]) continue;
+      C acc = czero<C>();
+      if (q < Qa) {
+        const C* M0 = mats + (long long)cfi[c] * a.mat_item_stride + a.mat_k_off[0] +
+                      (long long)beta[0] * a.R[0] * A0 + sg[0].pos(lo + ai);
+        const C* src = fine + cfb[c] + j1 * fs[1] + j2 * fs[2] + q;
+        const int r0 = crk[c][0];
+        for (int j0 = 0; j0 < r0; ++j0) {
+          C m = M0[j0 * A0];
+          if (a.conj) m.y = -m.y;
+          acc = cfma(acc, m, src[j0 * fs[0]]);
+        }
+      }
+      buf1[idx] = acc;
+    }
+    __syncthreads();
+    // buf2[c][ai][j1o][j2][q] = sum_j1 M1_c[j1][j1o] buf1[c][ai][j1][j2][q]
+    for (int idx = threadIdx.x; idx < nchild * per_c2; idx += kThreads) {
+      const int c = idx / per_c2;
+      int t = idx % per_c2;
+      const int q = t % QT;
+      t /= QT;
+      const int j2 = t % R2;
+      t /= R2;
+      const int j1o = t % a.A[1], ai = t / a.A[1];
+      const int r1 = crk[c][1];
+      if (j1o >= c1 || j2 >= crk[c][2]) continue;
+      const C* m1 = mall + c * msz;
+      const C* src = buf1 + c * per_c1 + ((ai * R1) * R2 + j2) * QT + q;
+      C acc = czero<C>();
+      for (int j1 = 0; j1 < r1; ++j1) acc = cfma(acc, m1[j1 * c1 + j1o], src[j1 * R2 * QT]);
+      buf2[idx] = acc;
+    }
+    __syncthreads();
+    CoarseAddr<D> ca;
+    ca.init(a, ci, beta, q0);
+    const int m2off = a.R[1] * a.A[1];
+    for (int idx = threadIdx.x; idx < na * c1 * c2 * QT; idx += kThreads) {
+      const int q = idx % QT;
+      int t = idx / QT;
+      const int j2o = t % c2;
+      t /= c2;
+      const int j1o = t % c1, ai = t / c1;
+      if (q >= Qa) continue;
+      C acc = czero<C>();
+      for (int c = 0; c < nchild; ++c) {
+        const C* m2 = mall + c * msz + m2off;
+        const C* src = buf2 + c * per_c2 + ((ai * a.A[1] + j1o) * R2) * QT + q;
+        const int r2 = crk[c][2];
+        for (int j2 = 0; j2 < r2; ++j2) acc = cfma(acc, m2[j2 * c2 + j2o], src[j2 * QT]);
+      }
+      coarse[ca.base + sg[0].pos(lo + ai) * ca.stride[0] + sg[1].pos(j1o) * ca.stride[1] +
+             sg[2].pos(j2o) * ca.stride[2] + q * ca.qstride] = acc;
     }
   }
 }
@@ -687,6 +749,8 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // ------------------------------------------------------------------ host --
+constexpr int kTargetWorkgroups = 2048;  // enough to cover 256 CUs several times
+
 static int g_lds_limit = 0;
 
 static tb_status lds_limit(int* out) {
@@ -762,14 +826,16 @@ static StageArgs stage_args(const Plan& p, const Level& fine, const Level* coars
       st *= (long long)coarse->nb * coarse->R[k];
     }
   }
+  a.rank_f = fine.rank_d;
+  a.rank_c = coarse ? coarse->rank_d : nullptr;
+  a.nb_c = coarse ? coarse->nb : 1;
+  for (int k = 0; k < d; ++k) a.Rc[k] = coarse ? coarse->R[k] : 0;
   a.outer_level = source ? p.Ls : p.Lt;
   a.outer_block = (int)(p.n >> a.outer_level);
   a.nrhs = nrhs;
   a.conj = conj ? 1 : 0;
   return a;
 }
-
-constexpr int kTargetWorkgroups = 2048;  // enough to cover 256 CUs several times
 
 template <class T, int D, int QT>
 static tb_status launch_fanout(StageArgs a, dim3 grid, size_t lds, const void* in, void* out,
@@ -780,30 +846,50 @@ static tb_status launch_fanout(StageArgs a, dim3 grid, size_t lds, const void* i
   return TB_OK;
 }
 
-template <class T, int D, int QT, int NPER>
+template <class T, int D, int QT>
 static tb_status launch_fanin(StageArgs a, dim3 grid, size_t lds, const void* in, void* out,
                               const void* mats, hipStream_t stream) {
   using C = typename CplxOf<T>::type;
-  TB_TRY(set_lds(stage_fanin<T, D, QT, NPER>, lds));
-  stage_fanin<T, D, QT, NPER><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+  TB_TRY(set_lds(stage_fanin<T, D, QT>, lds));
+  stage_fanin<T, D, QT><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
   return TB_OK;
 }
 
 // LDS elements of one workgroup for a slice of `chunk` entries of the first
-// mode and QT right-hand sides.
+// mode and QT right-hand sides (padded extents bound the true ones).
 static long long stage_lds_elems(const StageArgs& a, int d, bool fanout, int chunk, int QT) {
-  long long e = 0;
-  for (int k = 1; k < d; ++k) e += (long long)a.R[k] * a.A[k];
+  long long msz = 0;
+  for (int k = 1; k < d; ++k) msz += (long long)a.R[k] * a.A[k];
   if (fanout) {
-    e += (long long)chunk * a.A[0];
+    long long e = msz;
     if (d == 2) e += (long long)chunk * a.A[1] * QT;
     else e += (long long)chunk * a.A[1] * a.A[2] * QT + (long long)chunk * a.R[1] * a.A[2] * QT;
-  } else {
-    e += (long long)a.R[0] * chunk;
-    if (d == 2) e += (long long)chunk * a.R[1] * QT;
-    else e += (long long)chunk * a.R[1] * a.R[2] * QT + (long long)chunk * a.A[1] * a.R[2] * QT;
+    return e;
   }
+  const long long nchild = a.coarse_global ? 1 : (1LL << d);
+  long long e = nchild * msz;
+  if (d == 2) e += nchild * chunk * a.R[1] * QT;
+  else e += nchild * chunk * a.R[1] * a.R[2] * QT + nchild * chunk * a.A[1] * a.R[2] * QT;
   return e;
+}
+
+template <class T, int D>
+static tb_status launch_stage_d(StageArgs a, bool fanout, int QT, dim3 grid, size_t lds, const void* in,
+                                void* out, const void* mats, hipStream_t stream) {
+  if (fanout) {
+    switch (QT) {
+      case 1: return launch_fanout<T, D, 1>(a, grid, lds, in, out, mats, stream);
+      case 2: return launch_fanout<T, D, 2>(a, grid, lds, in, out, mats, stream);
+      case 4: return launch_fanout<T, D, 4>(a, grid, lds, in, out, mats, stream);
+      default: return launch_fanout<T, D, 8>(a, grid, lds, in, out, mats, stream);
+    }
+  }
+  switch (QT) {
+    case 1: return launch_fanin<T, D, 1>(a, grid, lds, in, out, mats, stream);
+    case 2: return launch_fanin<T, D, 2>(a, grid, lds, in, out, mats, stream);
+    case 4: return launch_fanin<T, D, 4>(a, grid, lds, in, out, mats, stream);
+    default: return launch_fanin<T, D, 8>(a, grid, lds, in, out, mats, stream);
+  }
 }
 
 template <class T>
@@ -813,44 +899,23 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
   const int d = p.d;
   int limit = 0;
   TB_TRY(lds_limit(&limit));
-  const int QT = a.nrhs == 1 ? 1 : 8;
+  // keep two workgroups' LDS per CU where possible
+  const long long budget = std::min<long long>(limit, 80 * 1024);
   const long long blocks = (long long)n_items * a.nblk;
   const int dim = fanout ? a.R[0] : a.A[0];
-  long long per_row = QT;  // fan-in outputs per entry of the first mode
-  for (int k = 1; k < d; ++k) per_row *= a.A[k];
+  int QT = a.nrhs >= 8 ? 8 : (a.nrhs >= 4 ? 4 : (a.nrhs >= 2 ? 2 : 1));
+  while (QT > 1 && stage_lds_elems(a, d, fanout, 1, QT) * (long long)sizeof(C) > budget) QT /= 2;
   int chunk = (int)std::max<long long>(1, (dim * blocks + kTargetWorkgroups - 1) / kTargetWorkgroups);
   chunk = std::min(chunk, dim);
-  if (!fanout) {
-    const long long cmax = 16LL * kThreads / per_row;
-    if (cmax < 1)
-      return fail(TB_ERR_UNSUPPORTED, "transfer block exceeds the per-workgroup register budget");
-    chunk = (int)std::min<long long>(chunk, cmax);
-  }
-  while (chunk > 1 && stage_lds_elems(a, d, fanout, chunk, QT) * (long long)sizeof(C) > limit) --chunk;
+  while (chunk > 1 && stage_lds_elems(a, d, fanout, chunk, QT) * (long long)sizeof(C) > budget) --chunk;
   const size_t lds = (size_t)stage_lds_elems(a, d, fanout, chunk, QT) * sizeof(C);
   if (lds > (size_t)limit)
     return fail(TB_ERR_UNSUPPORTED, "transfer block exceeds the per-workgroup LDS budget");
   a.chunk = chunk;
   a.nsplit = (dim + chunk - 1) / chunk;
   dim3 grid((unsigned)(blocks * a.nsplit), (unsigned)((a.nrhs + QT - 1) / QT));
-  const bool small = (long long)chunk * per_row <= 4LL * kThreads;
-  tb_status st;
-  if (fanout) {
-    if (d == 2) st = QT == 1 ? launch_fanout<T, 2, 1>(a, grid, lds, in, out, mats, stream)
-                             : launch_fanout<T, 2, 8>(a, grid, lds, in, out, mats, stream);
-    else st = QT == 1 ? launch_fanout<T, 3, 1>(a, grid, lds, in, out, mats, stream)
-                      : launch_fanout<T, 3, 8>(a, grid, lds, in, out, mats, stream);
-  } else if (d == 2) {
-    if (QT == 1) st = small ? launch_fanin<T, 2, 1, 4>(a, grid, lds, in, out, mats, stream)
-                            : launch_fanin<T, 2, 1, 16>(a, grid, lds, in, out, mats, stream);
-    else st = small ? launch_fanin<T, 2, 8, 4>(a, grid, lds, in, out, mats, stream)
-                    : launch_fanin<T, 2, 8, 16>(a, grid, lds, in, out, mats, stream);
-  } else {
-    if (QT == 1) st = small ? launch_fanin<T, 3, 1, 4>(a, grid, lds, in, out, mats, stream)
-                            : launch_fanin<T, 3, 1, 16>(a, grid, lds, in, out, mats, stream);
-    else st = small ? launch_fanin<T, 3, 8, 4>(a, grid, lds, in, out, mats, stream)
-                    : launch_fanin<T, 3, 8, 16>(a, grid, lds, in, out, mats, stream);
-  }
+  const tb_status st = d == 2 ? launch_stage_d<T, 2>(a, fanout, QT, grid, lds, in, out, mats, stream)
+                              : launch_stage_d<T, 3>(a, fanout, QT, grid, lds, in, out, mats, stream);
   TB_TRY(st);
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;

@@ -127,6 +127,9 @@ static tb_status pad_level(Plan& p, Level& lv, const Level* prev) {
     X32[i] = make_float2((float)X64[i].x, (float)X64[i].y);
   TB_TRY(upload(p, &lv.X64, X64));
   TB_TRY(upload(p, &lv.X32, X32));
+  std::vector<int> ranks(lv.ids.size());
+  for (size_t i = 0; i < ranks.size(); ++i) ranks[i] = lv.ids[i].r;
+  TB_TRY(upload(p, &lv.rank_d, ranks));
   return TB_OK;
 }
 

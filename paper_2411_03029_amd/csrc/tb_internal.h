@@ -70,6 +70,7 @@ struct Level {
   long long E = 0;                      // entries per item tensor
   double2* X64 = nullptr;
   float2* X32 = nullptr;
+  int* rank_d = nullptr;                // true ranks [item][k][blk]
   const IdRec& id(int item, int k, int blk, int d) const {
     return ids[((size_t)item * d + k) * nb + blk];
   }
