@@ -106,6 +106,81 @@ def cpu_baseline_leg(kind, d, n, tol, f_host, gpu_out):
     return base, errors
 
 
+def calibrate_copy(nbytes: int) -> int:
+    """A plain device-to-device copy of nbytes (3 times), to scale the HBM
+    byte counters (FETCH_SIZE / WRITE_SIZE) of a profiled run."""
+    import torch
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "copies": 3}))
+    return 0
+
+
+def _rocprof_rows(directory: str, suffix: str):
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True):
+        with open(path, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _counter_per_dispatch(directory: str, counter: str, name_part: str) -> float:
+    """Average value of `counter` over dispatches whose kernel name contains
+    name_part (rocprofv3 --pmc CSV)."""
+    vals = {}
+    for r in _rocprof_rows(directory, "counter_collection.csv"):
+        if r.get("Counter_Name") == counter and name_part in r.get("Kernel_Name", ""):
+            key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    if not vals:
+        raise SystemExit(f"no {counter} rows for {name_part} under {directory}")
+    return sum(vals.values()) / len(vals)
+
+
+def summarize(trace_dir, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes,
+              workload, command) -> int:
+    """Write the committed profile summaries under profiles/ from rocprofv3
+    CSV output: kernel-trace statistics, and the HBM traffic of the forward
+    core kernel scaled by the counters of a plain copy of copy_bytes."""
+    stats = _rocprof_rows(trace_dir, "kernel_stats.csv")
+    lines = [f"# rocprofv3 kernel statistics: workload {workload}", "",
+             f"command: {command['trace']}", "",
+             "| kernel | calls | total (us) | average (us) | percent |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0))):
+        name = r["Name"]
+        short = name.split("(")[0].replace("void ", "")
+        lines.append(f"| {short} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"kernel_stats_{workload}.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    core = "core_fwd<float, HIP_vector_type<float, 2u>"
+    copy_name = "copy"
+    f_core = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", core)
+    w_core = _counter_per_dispatch(write_dir, "WRITE_SIZE", core)
+    f_copy = _counter_per_dispatch(copy_fetch_dir, "FETCH_SIZE", copy_name)
+    w_copy = _counter_per_dispatch(copy_write_dir, "WRITE_SIZE", copy_name)
+    fetch_scale = copy_bytes / f_copy      # bytes per counter unit (KiB nominal)
+    write_scale = copy_bytes / w_copy
+    traffic = f_core * fetch_scale + w_core * write_scale
+    out = {"workload": workload, "kernel": "core_fwd (complex FP32)",
+           "kernel_source_sha256_16": kernel_hash(),
+           "fetch_per_launch_raw": f_core, "write_per_launch_raw": w_core,
+           "copy_bytes": copy_bytes, "copy_fetch_raw": f_copy, "copy_write_raw": w_copy,
+           "fetch_bytes_per_launch": f_core * fetch_scale,
+           "write_bytes_per_launch": w_core * write_scale,
+           "bytes_per_launch": traffic, "commands": command}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,7 +188,19 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="helmholtz_cubes_n64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--summarize", nargs=5, metavar="DIR",
+                    help="write profiles/ from rocprofv3 CSV dirs: trace fetch write "
+                         "copy_fetch copy_write")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--commands-json", default="{}")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        return calibrate_copy(args.calibrate_copy)
+    if args.summarize:
+        return summarize(*args.summarize, args.copy_bytes, args.workload,
+                         json.loads(args.commands_json))
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
