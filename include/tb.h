@@ -79,11 +79,11 @@ typedef struct tb_plan_s* tb_plan;
  * defaults listed per field. */
 typedef struct {
   int leaf_size;        /* C_b, indices per leaf per mode; 0 -> 8            */
-  int lt_override;      /* 0 -> target middle level floor(L/2); v > 0 sets
+  int lt_override;      /* 0 -> target middle level ceil(L/2); v > 0 sets
                            it to v - 1 (source middle level = L - that)     */
   int proxy_pair;       /* samples of the paired mode per ID column; 0 -> 2;
                            < 0 -> every index of the node                  */
-  int proxy_other;      /* samples of every other mode; 0 -> 2*leaf (d = 2)
+  int proxy_other;      /* samples of every other mode; 0 -> 4*leaf (d = 2)
                            or 4 (d = 3); < 0 -> every index of the node     */
   double id_tol_scale;  /* ID tolerance = id_tol_scale * tol; 0 -> 0.3      */
   unsigned store_mask;  /* core precisions kept (TB_STORE_*); 0 -> C64      */

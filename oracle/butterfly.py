@@ -13,7 +13,7 @@ Trees and levels (section 3.2)
 Every mode of both grids has a binary tree of L levels with leaves of C_b
 indices, n = C_b 2^L; node b at level l covers [b n/2^l, (b+1) n/2^l).  The
 paper takes L even and meets in the middle at L^c = L/2.  For odd L this
-oracle puts the target middle level at Lt = floor(L/2) and the source middle
+oracle puts the target middle level at Lt = ceil(L/2) and the source middle
 level at Ls = L - Lt (identical to the paper when L is even):
 
 * source side, levels l = 0..Lt: for every source middle multi-set s (level
@@ -93,7 +93,7 @@ def proxies(lo: int, length: int, p: int) -> np.ndarray:
 def default_proxy_counts(d: int, leaf: int) -> tuple:
     """(p_pair, p_other) used when none are given: the paired mode takes
     p_pair samples per ID column, every other mode p_other samples."""
-    return 2, (2 * leaf if d == 2 else 4)
+    return 2, (4 * leaf if d == 2 else 4)
 
 
 DEFAULT_ID_TOL_SCALE = 0.3
@@ -186,7 +186,7 @@ def construct(op: Operator, tol: float, leaf: int = 8, p_pair: int | None = None
     (The paper runs its IDs at the tolerance itself and reports end-to-end
     errors of 1-2 times it; one middle-level Tucker-ID alone can reach
     sqrt(2d) eps by section 3.1, and the nesting over levels adds to that.)
-    ``lt`` overrides the target middle level (default floor(L/2))."""
+    ``lt`` overrides the target middle level (default ceil(L/2))."""
     n, d = op.n, op.d
     L = int(round(math.log2(n / leaf)))
     if leaf * (1 << L) != n or L < 0:
@@ -194,7 +194,7 @@ def construct(op: Operator, tol: float, leaf: int = 8, p_pair: int | None = None
     dp, do = default_proxy_counts(d, leaf)
     p_pair = dp if p_pair is None else p_pair
     p_other = do if p_other is None else p_other
-    Lt = L // 2 if lt is None else lt
+    Lt = L - L // 2 if lt is None else lt
     if not 0 <= Lt <= L:
         raise ValueError("target middle level out of range")
     Ls = L - Lt

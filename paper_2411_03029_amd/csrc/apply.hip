@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(kThreads)
 // children are processed together: two barriers per workgroup.
 constexpr int kMaxChildren = 1 << kMaxD;
 
-template <class T, int D, int QT>
+template <class T, int D, int QT, bool SM>
 __global__ void __launch_bounds__(kThreads)
     stage_fanin(StageArgs a, const typename CplxOf<T>::type* __restrict__ fine,
                 typename CplxOf<T>::type* __restrict__ coarse,
@@ -341,12 +341,13 @@ __global__ void __launch_bounds__(kThreads)
   const int A0 = a.A[0];
   const int R1 = a.R[1];
   const int c1 = sg[1].c;
-  // per-child compact copies of M_1.. (r_k x c_k, row stride A_k) in LDS
+  // per-child compact copies of M_1.. (r_k x c_k, row stride c_k) in LDS
+  // (SM), or the padded matrices read from global memory (!SM)
   int msz = 0;
 #pragma unroll
   for (int k = 1; k < D; ++k) msz += a.R[k] * a.A[k];
   C* mall = sm;
-  for (int c = 0; c < nchild; ++c) {
+  for (int c = 0; SM && c < nchild; ++c) {
     const C* mbase = mats + (long long)cfi[c] * a.mat_item_stride;
     int off = c * msz;
 #pragma unroll
@@ -362,7 +363,19 @@ __global__ void __launch_bounds__(kThreads)
       off += a.R[k] * a.A[k];
     }
   }
-  C* buf1 = sm + nchild * msz;
+  C* buf1 = sm + (SM ? nchild * msz : 0);
+  // M_k(c)[j][jo]: row j, compact column jo of child c's matrix for mode k
+  auto mat = [&](int c, int k, int j, int jo) -> C {
+    if constexpr (SM) {
+      const int off = k == 1 ? 0 : a.R[1] * a.A[1];
+      return mall[c * msz + off + j * sg[k].c + jo];
+    } else {
+      C v = mats[(long long)cfi[c] * a.mat_item_stride + a.mat_k_off[k] +
+                 (long long)beta[k] * a.R[k] * a.A[k] + j * a.A[k] + sg[k].pos(jo)];
+      if (a.conj) v.y = -v.y;
+      return v;
+    }
+  };
   if constexpr (D == 2) {
     // buf1[c][ai][j1][q] = sum_j0 M0_c[j0][pos(lo+ai)] fine_c(j0, j1, q), j1 < r1(c)
     const int per_c = na * R1 * QT;
@@ -395,10 +408,9 @@ __global__ void __launch_bounds__(kThreads)
       if (q >= Qa) continue;
       C acc = czero<C>();
       for (int c = 0; c < nchild; ++c) {
-        const C* m1 = mall + c * msz;
         const C* src = buf1 + c * per_c + (ai * R1) * QT + q;
         const int r1 = crk[c][1];
-        for (int j1 = 0; j1 < r1; ++j1) acc = cfma(acc, m1[j1 * c1 + j1o], src[j1 * QT]);
+        for (int j1 = 0; j1 < r1; ++j1) acc = cfma(acc, mat(c, 1, j1, j1o), src[j1 * QT]);
       }
       coarse[ca.base + sg[0].pos(lo + ai) * ca.stride[0] + sg[1].pos(j1o) * ca.stride[1] + q * ca.qstride] =
           acc;
@@ -444,16 +456,14 @@ __global__ void __launch_bounds__(kThreads)
       const int j1o = t % a.A[1], ai = t / a.A[1];
       const int r1 = crk[c][1];
       if (j1o >= c1 || j2 >= crk[c][2]) continue;
-      const C* m1 = mall + c * msz;
       const C* src = buf1 + c * per_c1 + ((ai * R1) * R2 + j2) * QT + q;
       C acc = czero<C>();
-      for (int j1 = 0; j1 < r1; ++j1) acc = cfma(acc, m1[j1 * c1 + j1o], src[j1 * R2 * QT]);
+      for (int j1 = 0; j1 < r1; ++j1) acc = cfma(acc, mat(c, 1, j1, j1o), src[j1 * R2 * QT]);
       buf2[idx] = acc;
     }
     __syncthreads();
     CoarseAddr<D> ca;
     ca.init(a, ci, beta, q0);
-    const int m2off = a.R[1] * a.A[1];
     for (int idx = threadIdx.x; idx < na * c1 * c2 * QT; idx += kThreads) {
       const int q = idx % QT;
       int t = idx / QT;
@@ -463,10 +473,9 @@ __global__ void __launch_bounds__(kThreads)
       if (q >= Qa) continue;
       C acc = czero<C>();
       for (int c = 0; c < nchild; ++c) {
-        const C* m2 = mall + c * msz + m2off;
         const C* src = buf2 + c * per_c2 + ((ai * a.A[1] + j1o) * R2) * QT + q;
         const int r2 = crk[c][2];
-        for (int j2 = 0; j2 < r2; ++j2) acc = cfma(acc, m2[j2 * c2 + j2o], src[j2 * QT]);
+        for (int j2 = 0; j2 < r2; ++j2) acc = cfma(acc, mat(c, 2, j2, j2o), src[j2 * QT]);
       }
       coarse[ca.base + sg[0].pos(lo + ai) * ca.stride[0] + sg[1].pos(j1o) * ca.stride[1] +
              sg[2].pos(j2o) * ca.stride[2] + q * ca.qstride] = acc;
@@ -748,6 +757,205 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// --------------------------------------------------------- MFMA cores --
+// Many right-hand sides: the core contraction is a dense complex GEMM per
+// pair, G (R_T x Q) = C (R_T x R_S) F (R_S x Q), run on the matrix cores as
+// four real v_mfma_f32_16x16x4f32 per complex 16 x 16 x 4 step:
+//   Gr += Cr Fr - Ci Fi,   Gi += Cr Fi + Ci Fr.
+// Lane layout of the 16x16x4 f32 MFMA: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator register j holds D[4 (l / 16) + j][l % 16].
+// BF16 cores are widened to FP32 in registers (FP32 accumulation).
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kMQ = 32;    // right-hand sides per workgroup (two 16-wide tiles)
+constexpr int kMT = 4;     // 16-row (or 16-column) tiles per wave
+constexpr int kMKC = 64;   // forward: rows of F staged per chunk
+constexpr int kMKA = 16;   // adjoint: rows of C and G staged per chunk
+
+template <class CS>
+__device__ __forceinline__ float2 load_core1(const CS* p) {
+  if constexpr (sizeof(CS) == 4) {
+    const unsigned u = *reinterpret_cast<const unsigned*>(p);
+    return CoreVec<unsigned>::one(u);
+  } else {
+    return *reinterpret_cast<const float2*>(p);
+  }
+}
+
+__device__ __forceinline__ void cmfma(v4f& ar, v4f& ai, float2 x, float2 y) {
+  ar = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.x, ar, 0, 0, 0);
+  ar = __builtin_amdgcn_mfma_f32_16x16x4f32(-x.y, y.y, ar, 0, 0, 0);
+  ai = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, y.y, ai, 0, 0, 0);
+  ai = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, y.x, ai, 0, 0, 0);
+}
+
+// Forward: a workgroup owns 4 waves x kMT x 16 = 256 rows of one pair and
+// kMQ right-hand sides; F is staged through LDS in chunks of kMKC rows.
+template <class CS, int D>
+__global__ void __launch_bounds__(kThreads)
+    core_fwd_mfma(CoreArgs a, const CS* __restrict__ cores, const long long* __restrict__ core_off,
+                  const int* __restrict__ meta, const int2* __restrict__ units,
+                  const float2* __restrict__ F, float2* __restrict__ G) {
+  __shared__ float2 fs[kMKC * kMQ];
+  const int2 u = units[blockIdx.x];
+  const int pair = u.x, r0 = u.y;
+  const int* m = meta + pair * kPairMeta;
+  const int RT = m[0], RS = m[1], RTp = m[2];
+  int rt[D], rs[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    rt[k] = m[3 + k];
+    rs[k] = m[6 + k];
+  }
+  const long long t = pair / a.nS, s = pair % a.nS;
+  const long long sitem = s * a.nT + t, titem = t * a.nS + s;
+  const int q0 = blockIdx.y * kMQ;
+  const int Qa = min(kMQ, a.nrhs - q0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const CS* cb = cores + core_off[pair];
+  v4f accr[kMT][2], acci[kMT][2];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      accr[i][c] = v4f{0, 0, 0, 0};
+      acci[i][c] = v4f{0, 0, 0, 0};
+    }
+  int rowc[kMT];
+  bool live[kMT];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) {
+    const int tile0 = r0 + (w + 4 * i) * 16;
+    live[i] = tile0 < RT;
+    rowc[i] = min(tile0 + (lane & 15), RTp - 1);
+  }
+  for (int kc = 0; kc < RS; kc += kMKC) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kMKC * kMQ; idx += kThreads) {
+      const int kk = kc + idx / kMQ, q = idx % kMQ;
+      fs[idx] = (kk < RS && q < Qa) ? F[(sitem * a.Es + padded_pos<D>(kk, rs, a.Rs)) * a.nrhs + q0 + q]
+                                    : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const int kend = min(kMKC, RS - kc);
+    for (int ks = 0; ks < kend; ks += 4) {
+      const int kcl = min(kc + ks + (lane >> 4), RS - 1);
+      float2 av[kMT];
+#pragma unroll
+      for (int i = 0; i < kMT; ++i) av[i] = load_core1(cb + (long long)kcl * RTp + rowc[i]);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const float2 bv = fs[(ks + (lane >> 4)) * kMQ + c * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < kMT; ++i)
+          if (live[i]) cmfma(accr[i][c], acci[i][c], av[i], bv);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) {
+    if (!live[i]) continue;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = r0 + (w + 4 * i) * 16 + 4 * (lane >> 4) + j;
+        const int col = c * 16 + (lane & 15);
+        if (row < RT && col < Qa)
+          G[(titem * a.Et + padded_pos<D>(row, rt, a.Rt)) * a.nrhs + q0 + col] =
+              make_float2(accr[i][c][j], acci[i][c][j]);
+      }
+  }
+}
+
+// Adjoint: F (R_S x Q) = C^H G.  A workgroup owns 256 columns of one pair
+// and kMQ right-hand sides; 16-row slabs of C (all 256 columns) and of G are
+// staged through LDS, so the global reads stay column-contiguous while each
+// lane reads the transposed fragment from LDS.
+template <class CS, int D>
+__global__ void __launch_bounds__(kThreads)
+    core_adj_mfma(CoreArgs a, const CS* __restrict__ cores, const long long* __restrict__ core_off,
+                  const int* __restrict__ meta, const int2* __restrict__ units,
+                  const float2* __restrict__ G, float2* __restrict__ F) {
+  constexpr int kCols = 4 * kMT * 16;           // 256
+  constexpr int kLd = kMKA + 1;                 // padded column length in LDS
+  __shared__ float2 cs_[kCols * kLd];
+  __shared__ float2 gs[kMKA * kMQ];
+  const int2 u = units[blockIdx.x];
+  const int pair = u.x, c0 = u.y;
+  const int* m = meta + pair * kPairMeta;
+  const int RT = m[0], RS = m[1], RTp = m[2];
+  int rt[D], rs[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    rt[k] = m[3 + k];
+    rs[k] = m[6 + k];
+  }
+  const long long t = pair / a.nS, s = pair % a.nS;
+  const long long sitem = s * a.nT + t, titem = t * a.nS + s;
+  const int q0 = blockIdx.y * kMQ;
+  const int Qa = min(kMQ, a.nrhs - q0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const CS* cb = cores + core_off[pair];
+  v4f accr[kMT][2], acci[kMT][2];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      accr[i][c] = v4f{0, 0, 0, 0};
+      acci[i][c] = v4f{0, 0, 0, 0};
+    }
+  bool live[kMT];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) live[i] = c0 + (w + 4 * i) * 16 < RS;
+  for (int k0 = 0; k0 < RTp; k0 += kMKA) {
+    __syncthreads();
+    // C slab: rows k0..k0+15 of columns c0..c0+255 (zero past the pair)
+    for (int idx = threadIdx.x; idx < kCols * kMKA; idx += kThreads) {
+      const int col = idx / kMKA, r = idx % kMKA;
+      const int gc = c0 + col, gr = k0 + r;
+      float2 v = make_float2(0.f, 0.f);
+      if (gc < RS && gr < RTp) v = load_core1(cb + (long long)gc * RTp + gr);
+      cs_[col * kLd + r] = v;
+    }
+    for (int idx = threadIdx.x; idx < kMKA * kMQ; idx += kThreads) {
+      const int r = idx / kMQ, q = idx % kMQ;
+      const int gr = k0 + r;
+      gs[idx] = (gr < RT && q < Qa) ? G[(titem * a.Et + padded_pos<D>(gr, rt, a.Rt)) * a.nrhs + q0 + q]
+                                    : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kMKA; ks += 4) {
+      float2 bv[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) bv[c] = gs[(ks + (lane >> 4)) * kMQ + c * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < kMT; ++i) {
+        if (!live[i]) continue;
+        float2 av = cs_[((w + 4 * i) * 16 + (lane & 15)) * kLd + ks + (lane >> 4)];
+        av.y = -av.y;  // conj(C)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) cmfma(accr[i][c], acci[i][c], av, bv[c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) {
+    if (!live[i]) continue;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = c0 + (w + 4 * i) * 16 + 4 * (lane >> 4) + j;
+        const int q = c * 16 + (lane & 15);
+        if (col < RS && q < Qa)
+          F[(sitem * a.Es + padded_pos<D>(col, rs, a.Rs)) * a.nrhs + q0 + q] =
+              make_float2(accr[i][c][j], acci[i][c][j]);
+      }
+  }
+}
+
 // ------------------------------------------------------------------ host --
 constexpr int kTargetWorkgroups = 2048;  // enough to cover 256 CUs several times
 
@@ -847,17 +1055,23 @@ static tb_status launch_fanout(StageArgs a, dim3 grid, size_t lds, const void* i
 }
 
 template <class T, int D, int QT>
-static tb_status launch_fanin(StageArgs a, dim3 grid, size_t lds, const void* in, void* out,
+static tb_status launch_fanin(StageArgs a, bool sm, dim3 grid, size_t lds, const void* in, void* out,
                               const void* mats, hipStream_t stream) {
   using C = typename CplxOf<T>::type;
-  TB_TRY(set_lds(stage_fanin<T, D, QT>, lds));
-  stage_fanin<T, D, QT><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+  if (sm) {
+    TB_TRY(set_lds(stage_fanin<T, D, QT, true>, lds));
+    stage_fanin<T, D, QT, true><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+  } else {
+    TB_TRY(set_lds(stage_fanin<T, D, QT, false>, lds));
+    stage_fanin<T, D, QT, false><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+  }
   return TB_OK;
 }
 
 // LDS elements of one workgroup for a slice of `chunk` entries of the first
 // mode and QT right-hand sides (padded extents bound the true ones).
-static long long stage_lds_elems(const StageArgs& a, int d, bool fanout, int chunk, int QT) {
+static long long stage_lds_elems(const StageArgs& a, int d, bool fanout, int chunk, int QT,
+                                 bool sm = true) {
   long long msz = 0;
   for (int k = 1; k < d; ++k) msz += (long long)a.R[k] * a.A[k];
   if (fanout) {
@@ -867,15 +1081,15 @@ static long long stage_lds_elems(const StageArgs& a, int d, bool fanout, int chu
     return e;
   }
   const long long nchild = a.coarse_global ? 1 : (1LL << d);
-  long long e = nchild * msz;
+  long long e = sm ? nchild * msz : 0;
   if (d == 2) e += nchild * chunk * a.R[1] * QT;
   else e += nchild * chunk * a.R[1] * a.R[2] * QT + nchild * chunk * a.A[1] * a.R[2] * QT;
   return e;
 }
 
 template <class T, int D>
-static tb_status launch_stage_d(StageArgs a, bool fanout, int QT, dim3 grid, size_t lds, const void* in,
-                                void* out, const void* mats, hipStream_t stream) {
+static tb_status launch_stage_d(StageArgs a, bool fanout, bool sm, int QT, dim3 grid, size_t lds,
+                                const void* in, void* out, const void* mats, hipStream_t stream) {
   if (fanout) {
     switch (QT) {
       case 1: return launch_fanout<T, D, 1>(a, grid, lds, in, out, mats, stream);
@@ -885,10 +1099,10 @@ static tb_status launch_stage_d(StageArgs a, bool fanout, int QT, dim3 grid, siz
     }
   }
   switch (QT) {
-    case 1: return launch_fanin<T, D, 1>(a, grid, lds, in, out, mats, stream);
-    case 2: return launch_fanin<T, D, 2>(a, grid, lds, in, out, mats, stream);
-    case 4: return launch_fanin<T, D, 4>(a, grid, lds, in, out, mats, stream);
-    default: return launch_fanin<T, D, 8>(a, grid, lds, in, out, mats, stream);
+    case 1: return launch_fanin<T, D, 1>(a, sm, grid, lds, in, out, mats, stream);
+    case 2: return launch_fanin<T, D, 2>(a, sm, grid, lds, in, out, mats, stream);
+    case 4: return launch_fanin<T, D, 4>(a, sm, grid, lds, in, out, mats, stream);
+    default: return launch_fanin<T, D, 8>(a, sm, grid, lds, in, out, mats, stream);
   }
 }
 
@@ -903,19 +1117,21 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
   const long long budget = std::min<long long>(limit, 80 * 1024);
   const long long blocks = (long long)n_items * a.nblk;
   const int dim = fanout ? a.R[0] : a.A[0];
+  // fan-in matrices are staged in LDS when they fit, else read from global
+  const bool sm = fanout || stage_lds_elems(a, d, false, 1, 1, true) * (long long)sizeof(C) <= budget;
   int QT = a.nrhs >= 8 ? 8 : (a.nrhs >= 4 ? 4 : (a.nrhs >= 2 ? 2 : 1));
-  while (QT > 1 && stage_lds_elems(a, d, fanout, 1, QT) * (long long)sizeof(C) > budget) QT /= 2;
+  while (QT > 1 && stage_lds_elems(a, d, fanout, 1, QT, sm) * (long long)sizeof(C) > budget) QT /= 2;
   int chunk = (int)std::max<long long>(1, (dim * blocks + kTargetWorkgroups - 1) / kTargetWorkgroups);
   chunk = std::min(chunk, dim);
-  while (chunk > 1 && stage_lds_elems(a, d, fanout, chunk, QT) * (long long)sizeof(C) > budget) --chunk;
-  const size_t lds = (size_t)stage_lds_elems(a, d, fanout, chunk, QT) * sizeof(C);
+  while (chunk > 1 && stage_lds_elems(a, d, fanout, chunk, QT, sm) * (long long)sizeof(C) > budget) --chunk;
+  const size_t lds = (size_t)stage_lds_elems(a, d, fanout, chunk, QT, sm) * sizeof(C);
   if (lds > (size_t)limit)
     return fail(TB_ERR_UNSUPPORTED, "transfer block exceeds the per-workgroup LDS budget");
   a.chunk = chunk;
   a.nsplit = (dim + chunk - 1) / chunk;
   dim3 grid((unsigned)(blocks * a.nsplit), (unsigned)((a.nrhs + QT - 1) / QT));
-  const tb_status st = d == 2 ? launch_stage_d<T, 2>(a, fanout, QT, grid, lds, in, out, mats, stream)
-                              : launch_stage_d<T, 3>(a, fanout, QT, grid, lds, in, out, mats, stream);
+  const tb_status st = d == 2 ? launch_stage_d<T, 2>(a, fanout, sm, QT, grid, lds, in, out, mats, stream)
+                              : launch_stage_d<T, 3>(a, fanout, sm, QT, grid, lds, in, out, mats, stream);
   TB_TRY(st);
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;
@@ -946,6 +1162,22 @@ static tb_status launch_core_q(const Plan& p, CoreArgs a, bool adjoint, const vo
   return TB_OK;
 }
 
+constexpr int kMfmaMinRhs = 8;   // from this many right-hand sides the matrix cores run the core
+
+template <class CS, int D>
+static tb_status launch_core_mfma(const Plan& p, const CoreArgs& a, bool adjoint, const void* cores,
+                                  const void* in, void* out, hipStream_t stream) {
+  const unsigned gy = (unsigned)((a.nrhs + kMQ - 1) / kMQ);
+  if (!adjoint)
+    core_fwd_mfma<CS, D><<<dim3((unsigned)p.mfma_fwd_units.size(), gy), kThreads, 0, stream>>>(
+        a, (const CS*)cores, p.core_off_d, p.pair_meta_d, p.mfma_fwd_units_d, (const float2*)in, (float2*)out);
+  else
+    core_adj_mfma<CS, D><<<dim3((unsigned)p.mfma_adj_units.size(), gy), kThreads, 0, stream>>>(
+        a, (const CS*)cores, p.core_off_d, p.pair_meta_d, p.mfma_adj_units_d, (const float2*)in, (float2*)out);
+  TB_HIP_TRY(hipGetLastError());
+  return TB_OK;
+}
+
 template <class T, class CS>
 static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* cores, const void* in,
                              void* out, hipStream_t stream) {
@@ -967,9 +1199,17 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
     maxRS = std::max(maxRS, p.pair_meta[(size_t)pr * kPairMeta + 1]);
     maxRTp = std::max(maxRTp, p.pair_meta[(size_t)pr * kPairMeta + 2]);
   }
+  if constexpr (sizeof(T) == 4) {
+    if (nrhs >= kMfmaMinRhs)
+      return d == 2 ? launch_core_mfma<CS, 2>(p, a, adjoint, cores, in, out, stream)
+                    : launch_core_mfma<CS, 3>(p, a, adjoint, cores, in, out, stream);
+  }
   int limit = 0;
   TB_TRY(lds_limit(&limit));
-  if (nrhs == 1)
+  using C = typename CplxOf<T>::type;
+  const size_t need4 = adjoint ? (size_t)maxRTp * 4 * sizeof(C)
+                               : ((size_t)maxRS * 4 + (size_t)kThreads * CoreVec<CS>::VR * 4) * sizeof(C);
+  if (nrhs == 1 || need4 > (size_t)limit)
     return d == 2 ? launch_core_q<T, CS, 2, 1>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream)
                   : launch_core_q<T, CS, 3, 1>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream);
   return d == 2 ? launch_core_q<T, CS, 2, 4>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream)

@@ -661,14 +661,14 @@ extern "C" tb_status tb_construct(tb_kernel kind, int d, long long n, double ome
   p.n = n;
   p.leaf = leaf;
   p.L = L;
-  p.Lt = o.lt_override > 0 ? o.lt_override - 1 : L / 2;
+  p.Lt = o.lt_override > 0 ? o.lt_override - 1 : L - L / 2;
   if (p.Lt > L) return fail(TB_ERR_INVALID_ARG, "lt_override beyond the tree depth");
   p.Ls = L - p.Lt;
   p.omega = kind == TB_KERNEL_HELMHOLTZ ? omega : 0.0;
   p.tol = tol;
   p.eps_id = tol * (o.id_tol_scale > 0 ? o.id_tol_scale : 0.3);
   p.proxy_pair = o.proxy_pair == 0 ? 2 : o.proxy_pair;
-  p.proxy_other = o.proxy_other == 0 ? (d == 2 ? 2 * leaf : 4) : o.proxy_other;
+  p.proxy_other = o.proxy_other == 0 ? (d == 2 ? 4 * leaf : 4) : o.proxy_other;
   if (o.radon_custom) {
     p.ra = o.radon_a;
     p.rb = o.radon_b;

@@ -112,6 +112,10 @@ struct Plan {
   std::vector<int2> fwd_units[3], adj_units;
   int2* fwd_units_d[3] = {nullptr, nullptr, nullptr};
   int2* adj_units_d = nullptr;
+  // many right-hand sides (matrix cores): 256-row / 256-column panels
+  std::vector<int2> mfma_fwd_units, mfma_adj_units;
+  int2* mfma_fwd_units_d = nullptr;
+  int2* mfma_adj_units_d = nullptr;
   // device skeleton tables of the two top levels (core evaluation)
   int* top_src_skel_d = nullptr;     // [item][k][Rs]
   int* top_tgt_skel_d = nullptr;     // [item][k][Rt]

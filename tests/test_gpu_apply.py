@@ -140,3 +140,26 @@ def test_dtype_without_cores_is_rejected(tmp_path):
         plan.apply(f, dtype="c128")
     with pytest.raises(ValueError):
         plan.apply(to_dev(inputs.rhs_batch(8, 3, 1, config=94), torch.complex64))
+
+
+@pytest.mark.parametrize("name,nrhs", [("helm3_n32", 8), ("helm3_n32", 40), ("radon2_n32", 17),
+                                       ("fourier2_n64", 33)])
+def test_batched_rhs_matrix_cores(name, nrhs, tmp_path):
+    # from 8 right-hand sides the core contraction runs on the matrix cores
+    # (complex via four real 16x16x4 FP32 MFMAs); BF16 cores accumulate in
+    # FP32 (bound: BF16 rounding 2^-9 per core entry, random signs)
+    torch = torch_gpu()
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path, store=("c64", "cbf16"))
+    n, d = op.n, op.d
+    f = inputs.rhs_batch(n, d, nrhs, config=98)
+    ue, ve = bf.apply(op, f), bf.apply_adjoint(op, f)
+    for dt, tol in (("c64", 2e-5), ("cbf16", 5e-3)):
+        say(f"[gpu] batched {name} nrhs={nrhs} {dt}")
+        x = to_dev(f, torch.complex64)
+        u = to_host(plan.apply(x, dtype=dt))
+        v = to_host(plan.apply_adjoint(x, dtype=dt))
+        torch.cuda.synchronize()
+        for q in range(nrhs):
+            assert relerr(u[q], ue[q]) <= tol, (dt, q, relerr(u[q], ue[q]))
+            assert relerr(v[q], ve[q]) <= tol, (dt, q, relerr(v[q], ve[q]))
