@@ -142,6 +142,26 @@ tb_status tb_apply(tb_plan p, const void* f, void* u, long long nrhs,
 tb_status tb_apply_adjoint(tb_plan p, const void* g, void* v, long long nrhs,
                            tb_dtype io, void* hip_stream);
 
+/* Several operators in one submission: plan i maps in[i] -> out[i] with
+ * nrhs[i] right-hand sides (forward, or adjoint if adjoint != 0), all of
+ * element type io.  The plans' kernel sequences are the parallel branches of
+ * one HIP graph, captured on the first call for a given (plans, pointers,
+ * nrhs, direction, io) and replayed as a single graph launch on hip_stream by
+ * later calls with the same arguments.  Up to 32 graphs are cached (oldest
+ * dropped first); a graph is also dropped by tb_batched_reset, by the
+ * destruction of one of its plans and when a plan's workspace has to grow.
+ * Plans must be distinct; each plan's workspace is shared with its tb_apply
+ * calls, so calls on one plan from different streams race.  Arrays as for
+ * tb_apply.  A capturing call synchronises the device (workspaces are
+ * allocated before capture); the legacy null stream is not captured (a
+ * private stream is) but the replay runs on it. */
+tb_status tb_apply_batched(int nplans, const tb_plan* plans, const void* const* in,
+                           void* const* out, const long long* nrhs, int adjoint,
+                           tb_dtype io, void* hip_stream);
+
+/* Drop every cached batched graph (call before freeing captured arrays). */
+tb_status tb_batched_reset(void);
+
 /* Fill *info.  Host only; no device work. */
 tb_status tb_plan_info(tb_plan p, tb_plan_info_t* info);
 

@@ -140,6 +140,50 @@ class Plan:
         _lib.check(_lib.load().tb_plan_save(self._h, path.encode()))
 
 
+def apply_batched(plans, xs, outs=None, adjoint: bool = False, dtype: str = "c64",
+                  stream=None):
+    """Apply several plans (of any n, d and RHS count) in one HIP graph launch.
+
+    ``xs[i]`` has shape (nrhs_i, n_i, ..) or (n_i, ..); ``outs`` (optional)
+    are contiguous tensors of the same shapes.  The graph is cached on the
+    argument pointers, so a loop that reuses the same ``xs``/``outs`` pays the
+    capture once and then one launch per call.
+    """
+    import torch
+    if len(plans) != len(xs) or (outs is not None and len(outs) != len(xs)):
+        raise ValueError("plans, xs and outs must have the same length")
+    want = torch.complex128 if dtype == "c128" else torch.complex64
+    ins, res, counts = [], [], []
+    for i, (p, x) in enumerate(zip(plans, xs)):
+        info = p.info()
+        n, d = info["n"], info["d"]
+        if not x.is_cuda or x.dtype != want or not x.is_contiguous():
+            raise ValueError(f"xs[{i}] must be a contiguous CUDA {want} tensor")
+        xb = x.unsqueeze(0) if x.dim() == d else x
+        if tuple(xb.shape[1:]) != (n,) * d:
+            raise ValueError(f"xs[{i}]: expected (nrhs, {n}^{d}), got {tuple(x.shape)}")
+        o = torch.empty_like(x) if outs is None else outs[i]
+        if o.shape != x.shape or o.dtype != want or not o.is_contiguous():
+            raise ValueError(f"outs[{i}] must be a contiguous tensor shaped like xs[{i}]")
+        ins.append(xb.data_ptr())
+        res.append(o)
+        counts.append(xb.shape[0])
+    m = len(plans)
+    P = ctypes.c_void_p
+    hs = (P * m)(*[p.handle for p in plans])
+    ip = (P * m)(*ins)
+    op = (P * m)(*[o.data_ptr() for o in res])
+    nr = (ctypes.c_longlong * m)(*counts)
+    _lib.check(_lib.load().tb_apply_batched(m, hs, ip, op, nr, 1 if adjoint else 0,
+                                            DTYPES[dtype], _stream_handle(stream)))
+    return res
+
+
+def batched_reset() -> None:
+    """Drop the cached graphs of apply_batched."""
+    _lib.check(_lib.load().tb_batched_reset())
+
+
 def construct(kind, d: int, n: int, tol: float, omega: float | None = None,
               stream=None, **opts) -> Plan:
     """Build the butterfly of operator ``kind`` on the GPU (Algorithm 1).

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "cplx.h"
 #include "tb_internal.h"
@@ -980,6 +981,29 @@ static tb_status set_lds(K kernel, size_t bytes) {
   return TB_OK;
 }
 
+static tb_status ensure_workspace(Plan& p, size_t bytes) {
+  if (p.ws.bytes >= bytes) return TB_OK;
+  if (p.ws.base) {
+    drop_graphs_for(&p);  // cached graphs hold the old workspace address
+    TB_HIP_TRY(hipDeviceSynchronize());
+    TB_HIP_TRY(hipFree(p.ws.base));
+    p.device_bytes -= p.ws.bytes;
+    p.ws.base = nullptr;
+    p.ws.bytes = 0;
+  }
+  if (p.max_device_bytes && p.device_bytes + bytes > p.max_device_bytes)
+    return fail(TB_ERR_OOM, "apply workspace exceeds the plan's device memory cap");
+  hipError_t e = hipMalloc(&p.ws.base, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p.ws.base = nullptr;
+    return fail(TB_ERR_OOM, std::string("apply workspace: ") + hipGetErrorString(e));
+  }
+  p.ws.bytes = bytes;
+  p.device_bytes += bytes;
+  return TB_OK;
+}
+
 struct Buffers {
   std::vector<size_t> src_off, tgt_off;  // byte offsets in the workspace
   size_t total = 0;
@@ -1236,25 +1260,7 @@ static tb_status apply_typed(Plan& p, const void* in, void* out, long long nrhs,
   using C = typename CplxOf<T>::type;
   const size_t esz = sizeof(C);
   Buffers b = layout(p, nrhs, esz);
-  if (p.ws.bytes < b.total) {
-    if (p.ws.base) {
-      TB_HIP_TRY(hipDeviceSynchronize());
-      TB_HIP_TRY(hipFree(p.ws.base));
-      p.device_bytes -= p.ws.bytes;
-      p.ws.base = nullptr;
-      p.ws.bytes = 0;
-    }
-    if (p.max_device_bytes && p.device_bytes + b.total > p.max_device_bytes)
-      return fail(TB_ERR_OOM, "apply workspace exceeds the plan's device memory cap");
-    hipError_t e = hipMalloc(&p.ws.base, b.total);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p.ws.base = nullptr;
-      return fail(TB_ERR_OOM, std::string("apply workspace: ") + hipGetErrorString(e));
-    }
-    p.ws.bytes = b.total;
-    p.device_bytes += b.total;
-  }
+  TB_TRY(ensure_workspace(p, b.total));
   char* ws = static_cast<char*>(p.ws.base);
   auto S = [&](int l) { return (void*)(ws + b.src_off[l]); };
   auto Tb = [&](int l) { return (void*)(ws + b.tgt_off[l]); };
@@ -1324,7 +1330,183 @@ tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs, tb_dtype
   return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
 }
 
+tb_status prepare_workspace(Plan& p, long long nrhs, tb_dtype io) {
+  const size_t esz = io == TB_C128 ? sizeof(double2) : sizeof(float2);
+  return ensure_workspace(p, layout(p, nrhs, esz).total);
+}
+
+// ------------------------------------------------------- batched graphs --
+struct GraphKey {
+  std::vector<const Plan*> plans;
+  std::vector<const void*> in;
+  std::vector<void*> out;
+  std::vector<long long> nrhs;
+  int adjoint = 0;
+  int io = 0;
+  bool operator==(const GraphKey& o) const {
+    return plans == o.plans && in == o.in && out == o.out && nrhs == o.nrhs && adjoint == o.adjoint &&
+           io == o.io;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+constexpr size_t kMaxCachedGraphs = 32;
+static std::recursive_mutex g_graph_mu;
+static std::vector<GraphEntry> g_graphs;
+static std::vector<hipStream_t> g_branch_streams;
+
+static void destroy_entry(GraphEntry& e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.graph) (void)hipGraphDestroy(e.graph);
+  e.exec = nullptr;
+  e.graph = nullptr;
+}
+
+void drop_graphs_for(const Plan* p) {
+  std::lock_guard<std::recursive_mutex> lk(g_graph_mu);
+  for (size_t i = 0; i < g_graphs.size();) {
+    bool uses = false;
+    for (const Plan* q : g_graphs[i].key.plans) uses |= q == p;
+    if (uses) {
+      destroy_entry(g_graphs[i]);
+      g_graphs.erase(g_graphs.begin() + (long)i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+static tb_status capture_batched(const GraphKey& key, std::vector<Plan*>& plans, hipStream_t stream,
+                                 GraphEntry* out_entry) {
+  const int np = (int)plans.size();
+  while ((int)g_branch_streams.size() < np) {
+    hipStream_t st = nullptr;
+    TB_HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    g_branch_streams.push_back(st);
+  }
+  // workspaces must exist before capture (no allocation inside a graph)
+  for (int i = 0; i < np; ++i) TB_TRY(prepare_workspace(*plans[i], key.nrhs[i], (tb_dtype)key.io));
+  TB_HIP_TRY(hipDeviceSynchronize());
+  std::vector<hipEvent_t> ev(np + 1, nullptr);
+  for (auto& e : ev) TB_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  auto cleanup = [&]() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  hipStream_t cap = stream;
+  hipStream_t own = nullptr;
+  if (cap == nullptr) {  // the legacy default stream cannot be captured
+    TB_HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    cap = own;
+  }
+  std::vector<bool> timing(np);
+  for (int i = 0; i < np; ++i) {
+    timing[i] = plans[i]->timing;
+    plans[i]->timing = false;
+  }
+  tb_status st = TB_OK;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) st = fail(TB_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  if (st == TB_OK) {
+    e = hipEventRecord(ev[np], cap);
+    for (int i = 0; i < np && e == hipSuccess; ++i) e = hipStreamWaitEvent(g_branch_streams[i], ev[np], 0);
+    if (e != hipSuccess) st = fail(TB_ERR_HIP, std::string("graph fork: ") + hipGetErrorString(e));
+    for (int i = 0; i < np && st == TB_OK; ++i) {
+      st = run_apply(*plans[i], key.in[i], key.out[i], key.nrhs[i], (tb_dtype)key.io, key.adjoint != 0,
+                     g_branch_streams[i]);
+      if (st == TB_OK) {
+        e = hipEventRecord(ev[i], g_branch_streams[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cap, ev[i], 0);
+        if (e != hipSuccess) st = fail(TB_ERR_HIP, std::string("graph join: ") + hipGetErrorString(e));
+      }
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cap, &graph);
+    if (st == TB_OK && e != hipSuccess)
+      st = fail(TB_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    if (st == TB_OK) {
+      hipGraphExec_t exec = nullptr;
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        st = fail(TB_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        (void)hipGraphDestroy(graph);
+      } else {
+        out_entry->key = key;
+        out_entry->graph = graph;
+        out_entry->exec = exec;
+      }
+    } else if (graph) {
+      (void)hipGraphDestroy(graph);
+    }
+  }
+  for (int i = 0; i < np; ++i) plans[i]->timing = timing[i];
+  cleanup();
+  if (own) (void)hipStreamDestroy(own);
+  return st;
+}
+
+tb_status run_batched(int nplans, const tb_plan* handles, const void* const* in, void* const* out,
+                      const long long* nrhs, int adjoint, tb_dtype io, hipStream_t stream) {
+  if (nplans < 1 || nplans > 256 || !handles || !in || !out || !nrhs)
+    return fail(TB_ERR_INVALID_ARG, "tb_apply_batched: need 1..256 plans and non-null arrays");
+  if (io < TB_C128 || io > TB_CBF16) return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
+  GraphKey key;
+  std::vector<Plan*> plans;
+  for (int i = 0; i < nplans; ++i) {
+    Plan* p = reinterpret_cast<Plan*>(handles[i]);
+    if (!p || !in[i] || !out[i]) return fail(TB_ERR_INVALID_ARG, "tb_apply_batched: null plan or array");
+    if (nrhs[i] < 1 || nrhs[i] > (1 << 20)) return fail(TB_ERR_INVALID_ARG, "nrhs must be in [1, 2^20]");
+    if (!p->cores[io]) return fail(TB_ERR_INVALID_ARG, "a plan holds no cores of the requested precision");
+    if (in[i] == out[i]) return fail(TB_ERR_INVALID_ARG, "input and output must not alias");
+    for (Plan* q : plans)
+      if (q == p) return fail(TB_ERR_INVALID_ARG, "tb_apply_batched: plans must be distinct");
+    plans.push_back(p);
+    key.plans.push_back(p);
+    key.in.push_back(in[i]);
+    key.out.push_back(out[i]);
+    key.nrhs.push_back(nrhs[i]);
+  }
+  key.adjoint = adjoint ? 1 : 0;
+  key.io = io;
+  std::lock_guard<std::recursive_mutex> lk(g_graph_mu);
+  GraphEntry* hit = nullptr;
+  for (GraphEntry& e : g_graphs)
+    if (e.key == key) hit = &e;
+  if (!hit) {
+    if (g_graphs.size() >= kMaxCachedGraphs) {  // oldest first
+      destroy_entry(g_graphs.front());
+      g_graphs.erase(g_graphs.begin());
+    }
+    GraphEntry fresh;
+    TB_TRY(capture_batched(key, plans, stream, &fresh));
+    g_graphs.push_back(fresh);
+    hit = &g_graphs.back();
+  }
+  TB_HIP_TRY(hipGraphLaunch(hit->exec, stream));
+  return TB_OK;
+}
+
+tb_status batched_reset() {
+  std::lock_guard<std::recursive_mutex> lk(g_graph_mu);
+  for (GraphEntry& e : g_graphs) destroy_entry(e);
+  g_graphs.clear();
+  return TB_OK;
+}
+
 }  // namespace tb
+
+extern "C" tb_status tb_apply_batched(int nplans, const tb_plan* plans, const void* const* in,
+                                      void* const* out, const long long* nrhs, int adjoint, tb_dtype io,
+                                      void* hip_stream) {
+  return tb::run_batched(nplans, plans, in, out, nrhs, adjoint, io, static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" tb_status tb_batched_reset(void) { return tb::batched_reset(); }
 
 extern "C" tb_status tb_apply(tb_plan ph, const void* f, void* u, long long nrhs, tb_dtype io,
                               void* hip_stream) {

@@ -26,6 +26,7 @@ tb_status fail(tb_status s, const std::string& msg) {
 Plan::~Plan() {
   // Kernels of this plan may still be in flight on some stream.
   (void)hipDeviceSynchronize();
+  drop_graphs_for(this);
   for (void* ptr : allocations) (void)hipFree(ptr);
   if (ws.base) (void)hipFree(ws.base);
   for (StageEvent& e : events) {

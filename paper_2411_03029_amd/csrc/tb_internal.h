@@ -142,6 +142,8 @@ tb_status launch_core_eval(Plan& p, hipStream_t stream, const double2* host_core
 tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs,
                     tb_dtype io, bool adjoint, hipStream_t stream);
 tb_status run_construct_ids(Plan& p, hipStream_t stream);
+tb_status prepare_workspace(Plan& p, long long nrhs, tb_dtype io);
+void drop_graphs_for(const Plan* p);
 
 inline int ipow2(int e) { return 1 << e; }
 
