@@ -162,6 +162,44 @@ tb_status tb_apply_batched(int nplans, const tb_plan* plans, const void* const* 
 /* Drop every cached batched graph (call before freeing captured arrays). */
 tb_status tb_batched_reset(void);
 
+/* Autotuner for the launch shapes of every kernel of tb_apply and
+ * tb_apply_adjoint on p for nrhs right-hand sides of element type io.
+ * Per launch it times the candidates (transfer stages: right-hand sides per
+ * workgroup 1/2/4/8, outputs per thread 1/8, sliced or whole blocks; core:
+ * vector kernels for 1 or 4 right-hand sides per pass, matrix cores for FP32
+ * and BF16) with HIP events on zero-filled scratch buffers it allocates and
+ * frees, and keeps the fastest; later applies with exactly this (nrhs, io),
+ * batched ones included, use it (other shapes keep the built-in heuristic).
+ * cache_path (nullable): a text file of earlier results, one line per
+ * (plan signature, io, nrhs); a hit skips the trials, a miss appends the new
+ * line.  The signature hashes the construction inputs and every rank, so a
+ * line only matches a plan with identical launch shapes.  *trials (nullable)
+ * receives the number of configurations timed (0 on a cache hit).
+ * Synchronises hip_stream; drops cached batched graphs of p. */
+tb_status tb_plan_autotune(tb_plan p, long long nrhs, tb_dtype io, const char* cache_path,
+                           void* hip_stream, int* trials);
+
+/* Launch configuration of one kernel of the apply sequence; 0 in a field
+ * keeps the built-in heuristic for it. */
+typedef struct {
+  int outputs_per_thread; /* transfer stages: 1 or 8 */
+  int rhs_tile;           /* transfer stages: right-hand sides per workgroup, 1/2/4/8 */
+  int whole_blocks;       /* transfer stages: 1 = one workgroup per block (no slices) */
+  int core_kernel;        /* core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = matrix cores */
+  int fanin_in_turn;      /* fan-in stages: 1 = children in turn, first mode in registers */
+} tb_launch_cfg;
+
+/* Set the configuration of launch `slot` for applies of p with exactly this
+ * (nrhs, io) (manual tuning; tests force every candidate this way).  Slots
+ * of the forward sequence: 0 .. Lt = source leaf and transfers (levels
+ * 0 .. Lt), Lt + 1 = core, then target transfers and leaf (levels Ls .. 0);
+ * the adjoint sequence follows at offset Lt + Ls + 3: target levels
+ * 0 .. Ls, core, source levels Lt .. 0 (Lt, Ls from tb_plan_info).  Other
+ * slots of a (nrhs, io) without an entry keep the heuristic.  Out-of-range
+ * fields are TB_ERR_INVALID_ARG; a configuration that does not fit its
+ * launch makes that apply fail with TB_ERR_UNSUPPORTED. */
+tb_status tb_plan_set_launch(tb_plan p, long long nrhs, tb_dtype io, int slot, const tb_launch_cfg* cfg);
+
 /* Fill *info.  Host only; no device work. */
 tb_status tb_plan_info(tb_plan p, tb_plan_info_t* info);
 

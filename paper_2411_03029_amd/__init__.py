@@ -70,7 +70,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:  # modules may be gone at interpreter exit
             _lib.load().tb_destroy(h)
             self._h = None
 
@@ -124,6 +124,35 @@ class Plan:
     def apply_adjoint(self, g, out=None, dtype="c64"):
         """v = K_BF^H g."""
         return self._run(_lib.load().tb_apply_adjoint, g, out, dtype)
+
+    def autotune(self, nrhs: int, dtype: str = "c64", cache: str | None = None,
+                 stream=None) -> int:
+        """Time the launch candidates of every apply kernel for ``nrhs``
+        right-hand sides and keep the fastest (see tb_plan_autotune).
+        Returns the number of configurations timed (0 on a cache hit)."""
+        trials = ctypes.c_int(0)
+        _lib.check(_lib.load().tb_plan_autotune(
+            self._h, int(nrhs), DTYPES[dtype], cache.encode() if cache else None,
+            _stream_handle(stream), ctypes.byref(trials)))
+        return trials.value
+
+    def set_launch(self, nrhs: int, slot: int, dtype: str = "c64", outputs_per_thread=0,
+                   rhs_tile=0, whole_blocks=0, core_kernel=0, fanin_in_turn=0) -> None:
+        """Force the configuration of one launch slot (see tb_plan_set_launch)."""
+        c = _lib.TbLaunchCfg(outputs_per_thread, rhs_tile, whole_blocks, core_kernel,
+                             fanin_in_turn)
+        _lib.check(_lib.load().tb_plan_set_launch(self._h, int(nrhs), DTYPES[dtype], int(slot),
+                                                  ctypes.byref(c)))
+
+    def launch_slots(self) -> list:
+        """Stage names of the launch slots, forward sequence then adjoint."""
+        i = self.info()
+        Lt, Ls = i["Lt"], i["Ls"]
+        fwd = (["src_leaf"] + ["src_transfer"] * Lt + ["core"] + ["tgt_transfer"] * Ls +
+               ["tgt_leaf"])
+        adj = (["tgt_leaf_adj"] + ["tgt_transfer_adj"] * Ls + ["core_adj"] +
+               ["src_transfer_adj"] * Lt + ["src_leaf_adj"])
+        return fwd + adj
 
     def set_timing(self, enable: bool = True) -> None:
         """Record HIP events around every apply kernel (per-stage timing)."""

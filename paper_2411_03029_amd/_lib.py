@@ -20,7 +20,7 @@ TB_STORE_C128, TB_STORE_C64, TB_STORE_CBF16 = 1, 2, 4
 
 # every symbol include/tb.h declares
 EXPORTS = ("tb_construct", "tb_apply", "tb_apply_adjoint", "tb_apply_batched",
-           "tb_batched_reset", "tb_plan_info",
+           "tb_batched_reset", "tb_plan_autotune", "tb_plan_set_launch", "tb_plan_info",
            "tb_plan_save", "tb_plan_load", "tb_destroy", "tb_plan_set_timing",
            "tb_plan_stage_times", "tb_last_error", "tb_status_string")
 
@@ -36,6 +36,12 @@ class TbOptions(ctypes.Structure):
                 ("max_rank", ctypes.c_int), ("max_device_bytes", ctypes.c_size_t),
                 ("radon_custom", ctypes.c_int), ("radon_a", ctypes.c_double),
                 ("radon_b", ctypes.c_double), ("radon_den", ctypes.c_double)]
+
+
+class TbLaunchCfg(ctypes.Structure):
+    _fields_ = [("outputs_per_thread", ctypes.c_int), ("rhs_tile", ctypes.c_int),
+                ("whole_blocks", ctypes.c_int), ("core_kernel", ctypes.c_int),
+                ("fanin_in_turn", ctypes.c_int)]
 
 
 class TbPlanInfo(ctypes.Structure):
@@ -79,6 +85,10 @@ def load() -> ctypes.CDLL:
                                      ctypes.POINTER(P), ctypes.POINTER(ctypes.c_longlong),
                                      ctypes.c_int, ctypes.c_int, P]
     lib.tb_batched_reset.argtypes = []
+    lib.tb_plan_set_launch.argtypes = [P, ctypes.c_longlong, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(TbLaunchCfg)]
+    lib.tb_plan_autotune.argtypes = [P, ctypes.c_longlong, ctypes.c_int, ctypes.c_char_p, P,
+                                     ctypes.POINTER(ctypes.c_int)]
     lib.tb_plan_info.argtypes = [P, ctypes.POINTER(TbPlanInfo)]
     lib.tb_plan_save.argtypes = [P, ctypes.c_char_p]
     lib.tb_plan_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(TbOptions),
@@ -92,7 +102,7 @@ def load() -> ctypes.CDLL:
     lib.tb_status_string.restype = ctypes.c_char_p
     lib.tb_status_string.argtypes = [ctypes.c_int]
     for name in ("tb_construct", "tb_apply", "tb_apply_adjoint", "tb_apply_batched",
-                 "tb_batched_reset", "tb_plan_info",
+                 "tb_batched_reset", "tb_plan_autotune", "tb_plan_set_launch", "tb_plan_info",
                  "tb_plan_save", "tb_plan_load", "tb_plan_set_timing",
                  "tb_plan_stage_times"):
         getattr(lib, name).restype = ctypes.c_int

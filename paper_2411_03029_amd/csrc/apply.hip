@@ -23,6 +23,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <functional>
 #include <mutex>
 
 #include "cplx.h"
@@ -160,12 +163,54 @@ __device__ __forceinline__ void coarse_segs(const StageArgs& a, int citem, const
   }
 }
 
+// Register-blocked mode product shared by the stage kernels:
+//   acc[g] += sum_{j < nj} m(g, j) x(j),  g < ng (wave-uniform, ng <= G).
+// One thread owns a fiber x of the contracted mode and G outputs along the
+// new mode, so each input element is loaded once per group of G outputs.
+// G = 1 keeps every thread busy on small blocks (one right-hand side);
+// G = 8 cuts loads when right-hand sides fill the workgroup.  The stage
+// kernels take G (kG) as a template parameter; the autotuner picks it.
+template <int G, class C, class MF, class XF>
+__device__ __forceinline__ void gdot(C (&acc)[G], int ng, int nj, MF m, XF x) {
+#pragma unroll 2
+  for (int j = 0; j < nj; ++j) {
+    const C xv = x(j);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (g < ng) acc[g] = cfma(acc[g], m(g, j), xv);
+  }
+}
+
+template <int G, class C>
+__device__ __forceinline__ void gzero(C (&acc)[G]) {
+#pragma unroll
+  for (int g = 0; g < G; ++g) acc[g] = czero<C>();
+}
+
+
+// Workgroup -> (block, slice, right-hand-side tile); the tile index runs
+// fastest so that workgroups sharing cache lines of the q-innermost
+// intermediates are dispatched together.
+struct StageBid {
+  int item_blk, split, q0;
+};
+__device__ __forceinline__ StageBid stage_bid(const StageArgs& a, int QT) {
+  const int nqt = (a.nrhs + QT - 1) / QT;
+  int bid = blockIdx.x;
+  StageBid s;
+  s.q0 = (bid % nqt) * QT;
+  bid /= nqt;
+  s.split = bid % a.nsplit;
+  s.item_blk = bid / a.nsplit;
+  return s;
+}
+
 // --------------------------------------------------------------- fan-out --
 // fine(a_0..a_{D-1}, q) = sum_j prod_k M_k[a_k][j_k] coarse(j_0..j_{D-1}, q)
 // over true ranks (rows a_k < r_k) and the coarse block's true entries,
 // for a_0 in this workgroup's slice [lo, lo + na).  Padding is never
 // written or read: every consumer loops over true extents only.
-template <class T, int D, int QT>
+template <class T, int D, int QT, int kG>
 __global__ void __launch_bounds__(kThreads)
     stage_fanout(StageArgs a, const typename CplxOf<T>::type* __restrict__ coarse,
                  typename CplxOf<T>::type* __restrict__ fine,
@@ -173,124 +218,172 @@ __global__ void __launch_bounds__(kThreads)
   using C = typename CplxOf<T>::type;
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
-  int bid = blockIdx.x;
-  const int split = bid % a.nsplit;
-  bid /= a.nsplit;
-  const int fi = bid / a.nblk;
+  const StageBid sb = stage_bid(a, QT);
+  const int fi = sb.item_blk / a.nblk;
   int beta[D];
-  unflatten_blk<D>(bid % a.nblk, a.nb, beta);
+  unflatten_blk<D>(sb.item_blk % a.nblk, a.nb, beta);
   int r[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) r[k] = a.rank_f[((long long)fi * D + k) * a.nb + beta[k]];
-  const int lo = split * a.chunk;
+  const int lo = sb.split * a.chunk;
   const int na = min(r[0], lo + a.chunk) - lo;
   if (na <= 0) return;
   const int citem = a.coarse_global ? (fi >> (D * a.lvl)) : parent_of<D>(fi, a.lvl);
   Seg sg[D];
   coarse_segs<D>(a, citem, beta, sg);
-  const int q0 = blockIdx.y * QT;
+  const int q0 = sb.q0;
   const int Qa = min(QT, a.nrhs - q0);
   CoarseAddr<D> ca;
   ca.init(a, citem, beta, q0);
   long long fs[D];
   const long long fb = fine_base<D>(a, fi, beta, q0, fs);
   const C* mbase = mats + (long long)fi * a.mat_item_stride;
-  const C* M0 = mbase + a.mat_k_off[0] + (long long)beta[0] * a.R[0] * a.A[0];
-  // compact copies of M_1.. (r_k x c_k) in LDS
+  // compact copies in LDS: rows [lo, lo + na) of M_0 (read in place from
+  // global memory when G = 1: one use per load), all true rows of M_1..
   C* mk[D];
   int off = 0;
+  const C* M0g = mbase + a.mat_k_off[0] + (long long)beta[0] * a.R[0] * a.A[0];
 #pragma unroll
-  for (int k = 1; k < D; ++k) {
+  for (int k = 0; k < D; ++k) {
     mk[k] = sm + off;
     const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
     const int ck = sg[k].c;
-    for (int i = threadIdx.x; i < r[k] * ck; i += kThreads) {
+    const int r0 = k == 0 ? lo : 0;
+    const int nr = k == 0 ? (kG == 1 ? 0 : na) : r[k];
+    for (int i = threadIdx.x; i < nr * ck; i += kThreads) {
       const int row = i / ck, j = i % ck;
-      C v = src[row * a.A[k] + sg[k].pos(j)];
+      C v = src[(r0 + row) * a.A[k] + sg[k].pos(j)];
       if (a.conj) v.y = -v.y;
       mk[k][i] = v;
     }
-    off += a.R[k] * a.A[k];
+    off += k == 0 ? a.chunk * a.A[0] : a.R[k] * a.A[k];
   }
   C* buf1 = sm + off;
   const int c0 = sg[0].c, c1 = sg[1].c;
-  const int A0 = a.A[0];
+  const int ng0 = (na + kG - 1) / kG;
+  // M_0[lo + ai][compact j]
+  auto m0 = [&](int ai, int j) -> C {
+    if constexpr (kG == 1) {
+      C v = M0g[(lo + ai) * a.A[0] + sg[0].pos(j)];
+      if (a.conj) v.y = -v.y;
+      return v;
+    } else {
+      return mk[0][ai * c0 + j];
+    }
+  };
+  if constexpr (kG > 1) __syncthreads();
   if constexpr (D == 2) {
     // buf1[ai][j1][q] = sum_j0 M0[lo+ai][j0] coarse(j0, j1, q)
-    for (int idx = threadIdx.x; idx < na * c1 * QT; idx += kThreads) {
-      const int q = idx % QT, t = idx / QT, j1 = t % c1, ai = t / c1;
-      C acc = czero<C>();
+    for (int idx = threadIdx.x; idx < ng0 * c1 * QT; idx += kThreads) {
+      int q, j1, t;
+      if (a.coarse_global) {  // mode 1 is contiguous in the caller's array
+        j1 = idx % c1;
+        t = idx / c1;
+        q = t % QT;
+        t /= QT;
+      } else {
+        q = idx % QT;
+        t = idx / QT;
+        j1 = t % c1;
+        t /= c1;
+      }
+      const int a0 = t * kG, ng = min(kG, na - a0);
+      C acc[kG];
+      gzero(acc);
       if (q < Qa) {
         const C* src = coarse + ca.base + sg[1].pos(j1) * ca.stride[1] + q * ca.qstride;
-        const C* mr = M0 + (lo + ai) * A0;
-        for (int j0 = 0; j0 < c0; ++j0) {
-          const int p0 = sg[0].pos(j0);
-          C m = mr[p0];
-          if (a.conj) m.y = -m.y;
-          acc = cfma(acc, m, src[p0 * ca.stride[0]]);
-        }
+        gdot(acc, ng, c0, [&](int g, int j) { return m0(a0 + g, j); },
+             [&](int j) { return src[sg[0].pos(j) * ca.stride[0]]; });
       }
-      buf1[idx] = acc;
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (g < ng) buf1[((a0 + g) * c1 + j1) * QT + q] = acc[g];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < na * r[1] * QT; idx += kThreads) {
-      const int q = idx % QT, t = idx / QT, a1 = t % r[1], ai = t / r[1];
+    // fine[lo+ai][a1][q] = sum_j1 M1[a1][j1] buf1[ai][j1][q]
+    const int ng1 = (r[1] + kG - 1) / kG;
+    for (int idx = threadIdx.x; idx < ng1 * na * QT; idx += kThreads) {
+      const int q = idx % QT;
+      int t = idx / QT;
+      const int ai = t % na, a1 = (t / na) * kG, ng = min(kG, r[1] - a1);
       if (q >= Qa) continue;
+      C acc[kG];
+      gzero(acc);
       const C* src = buf1 + (ai * c1) * QT + q;
-      const C* mr = mk[1] + a1 * c1;
-      C acc = czero<C>();
-      for (int j1 = 0; j1 < c1; ++j1) acc = cfma(acc, mr[j1], src[j1 * QT]);
-      fine[fb + (lo + ai) * fs[0] + a1 * fs[1] + q] = acc;
+      gdot(acc, ng, c1, [&](int g, int j) { return mk[1][(a1 + g) * c1 + j]; },
+           [&](int j) { return src[j * QT]; });
+      C* dst = fine + fb + (lo + ai) * fs[0] + q;
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (g < ng) dst[(a1 + g) * fs[1]] = acc[g];
     }
   } else {
     const int c2 = sg[2].c;
     C* buf2 = buf1 + a.chunk * a.A[1] * a.A[2] * QT;
-    for (int idx = threadIdx.x; idx < na * c1 * c2 * QT; idx += kThreads) {
-      const int q = idx % QT;
-      int t = idx / QT;
-      const int j2 = t % c2;
-      t /= c2;
-      const int j1 = t % c1, ai = t / c1;
-      C acc = czero<C>();
+    // buf1[ai][j1][j2][q] = sum_j0 M0[lo+ai][j0] coarse(j0, j1, j2, q)
+    for (int idx = threadIdx.x; idx < ng0 * c1 * c2 * QT; idx += kThreads) {
+      int q, j2, t;
+      if (a.coarse_global) {
+        j2 = idx % c2;
+        t = idx / c2;
+        q = t % QT;
+        t /= QT;
+      } else {
+        q = idx % QT;
+        t = idx / QT;
+        j2 = t % c2;
+        t /= c2;
+      }
+      const int j1 = t % c1, a0 = (t / c1) * kG, ng = min(kG, na - a0);
+      C acc[kG];
+      gzero(acc);
       if (q < Qa) {
         const C* src = coarse + ca.base + sg[1].pos(j1) * ca.stride[1] + sg[2].pos(j2) * ca.stride[2] +
                        q * ca.qstride;
-        const C* mr = M0 + (lo + ai) * A0;
-        for (int j0 = 0; j0 < c0; ++j0) {
-          const int p0 = sg[0].pos(j0);
-          C m = mr[p0];
-          if (a.conj) m.y = -m.y;
-          acc = cfma(acc, m, src[p0 * ca.stride[0]]);
-        }
+        gdot(acc, ng, c0, [&](int g, int j) { return m0(a0 + g, j); },
+             [&](int j) { return src[sg[0].pos(j) * ca.stride[0]]; });
       }
-      buf1[idx] = acc;
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (g < ng) buf1[(((a0 + g) * c1 + j1) * c2 + j2) * QT + q] = acc[g];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < na * r[1] * c2 * QT; idx += kThreads) {
+    // buf2[ai][a1][j2][q] = sum_j1 M1[a1][j1] buf1[ai][j1][j2][q]
+    const int ng1 = (r[1] + kG - 1) / kG;
+    for (int idx = threadIdx.x; idx < ng1 * na * c2 * QT; idx += kThreads) {
       const int q = idx % QT;
       int t = idx / QT;
       const int j2 = t % c2;
       t /= c2;
-      const int a1 = t % r[1], ai = t / r[1];
+      const int ai = t % na, a1 = (t / na) * kG, ng = min(kG, r[1] - a1);
+      C acc[kG];
+      gzero(acc);
       const C* src = buf1 + ((ai * c1) * c2 + j2) * QT + q;
-      const C* mr = mk[1] + a1 * c1;
-      C acc = czero<C>();
-      for (int j1 = 0; j1 < c1; ++j1) acc = cfma(acc, mr[j1], src[j1 * c2 * QT]);
-      buf2[idx] = acc;
+      gdot(acc, ng, c1, [&](int g, int j) { return mk[1][(a1 + g) * c1 + j]; },
+           [&](int j) { return src[j * c2 * QT]; });
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (g < ng) buf2[((ai * r[1] + a1 + g) * c2 + j2) * QT + q] = acc[g];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < na * r[1] * r[2] * QT; idx += kThreads) {
+    // fine[lo+ai][a1][a2][q] = sum_j2 M2[a2][j2] buf2[ai][a1][j2][q]
+    const int ng2 = (r[2] + kG - 1) / kG;
+    for (int idx = threadIdx.x; idx < ng2 * na * r[1] * QT; idx += kThreads) {
       const int q = idx % QT;
       int t = idx / QT;
-      const int a2 = t % r[2];
-      t /= r[2];
-      const int a1 = t % r[1], ai = t / r[1];
+      const int a1 = t % r[1];
+      t /= r[1];
+      const int ai = t % na, a2 = (t / na) * kG, ng = min(kG, r[2] - a2);
       if (q >= Qa) continue;
+      C acc[kG];
+      gzero(acc);
       const C* src = buf2 + ((ai * r[1] + a1) * c2) * QT + q;
-      const C* mr = mk[2] + a2 * c2;
-      C acc = czero<C>();
-      for (int j2 = 0; j2 < c2; ++j2) acc = cfma(acc, mr[j2], src[j2 * QT]);
-      fine[fb + (lo + ai) * fs[0] + a1 * fs[1] + a2 * fs[2] + q] = acc;
+      gdot(acc, ng, c2, [&](int g, int j) { return mk[2][(a2 + g) * c2 + j]; },
+           [&](int j) { return src[j * QT]; });
+      C* dst = fine + fb + (lo + ai) * fs[0] + a1 * fs[1] + q;
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (g < ng) dst[(a2 + g) * fs[2]] = acc[g];
     }
   }
 }
@@ -302,7 +395,7 @@ __global__ void __launch_bounds__(kThreads)
 // children are processed together: two barriers per workgroup.
 constexpr int kMaxChildren = 1 << kMaxD;
 
-template <class T, int D, int QT, bool SM>
+template <class T, int D, int QT, bool SM, int kG>
 __global__ void __launch_bounds__(kThreads)
     stage_fanin(StageArgs a, const typename CplxOf<T>::type* __restrict__ fine,
                 typename CplxOf<T>::type* __restrict__ coarse,
@@ -310,18 +403,16 @@ __global__ void __launch_bounds__(kThreads)
   using C = typename CplxOf<T>::type;
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
-  int bid = blockIdx.x;
-  const int split = bid % a.nsplit;
-  bid /= a.nsplit;
-  const int ci = bid / a.nblk;
+  const StageBid sb = stage_bid(a, QT);
+  const int ci = sb.item_blk / a.nblk;
   int beta[D];
-  unflatten_blk<D>(bid % a.nblk, a.nb, beta);
+  unflatten_blk<D>(sb.item_blk % a.nblk, a.nb, beta);
   Seg sg[D];
   coarse_segs<D>(a, ci, beta, sg);
-  const int lo = split * a.chunk;
+  const int lo = sb.split * a.chunk;
   const int na = min(sg[0].c, lo + a.chunk) - lo;
   if (na <= 0) return;
-  const int q0 = blockIdx.y * QT;
+  const int q0 = sb.q0;
   const int Qa = min(QT, a.nrhs - q0);
   const int nchild = a.coarse_global ? 1 : (1 << D);
   // children: item, ranks, fine base
@@ -342,15 +433,27 @@ __global__ void __launch_bounds__(kThreads)
   const int A0 = a.A[0];
   const int R1 = a.R[1];
   const int c1 = sg[1].c;
-  // per-child compact copies of M_1.. (r_k x c_k, row stride c_k) in LDS
-  // (SM), or the padded matrices read from global memory (!SM)
-  int msz = 0;
+  // per child, compact in LDS (SM): M_0[j][lo + ai] transposed to
+  // [ai][j] (na x r_0), then M_k (r_k x c_k, row stride c_k) for k >= 1;
+  // without SM the padded matrices are read from global memory
+  int msz = a.chunk * a.R[0];
 #pragma unroll
   for (int k = 1; k < D; ++k) msz += a.R[k] * a.A[k];
   C* mall = sm;
   for (int c = 0; SM && c < nchild; ++c) {
     const C* mbase = mats + (long long)cfi[c] * a.mat_item_stride;
     int off = c * msz;
+    if (kG > 1) {
+      const C* src = mbase + a.mat_k_off[0] + (long long)beta[0] * a.R[0] * A0;
+      const int r0 = crk[c][0];
+      for (int i = threadIdx.x; i < na * r0; i += kThreads) {
+        const int ai = i / r0, j = i % r0;
+        C v = src[j * A0 + sg[0].pos(lo + ai)];
+        if (a.conj) v.y = -v.y;
+        mall[off + i] = v;
+      }
+    }
+    off += a.chunk * a.R[0];
 #pragma unroll
     for (int k = 1; k < D; ++k) {
       const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
@@ -365,10 +468,21 @@ __global__ void __launch_bounds__(kThreads)
     }
   }
   C* buf1 = sm + (SM ? nchild * msz : 0);
+  // M_0(c)[j][lo + ai]
+  auto mat0 = [&](int c, int ai, int j) -> C {
+    if constexpr (SM && kG > 1) {
+      return mall[c * msz + ai * crk[c][0] + j];
+    } else {
+      C v = mats[(long long)cfi[c] * a.mat_item_stride + a.mat_k_off[0] +
+                 (long long)beta[0] * a.R[0] * A0 + j * A0 + sg[0].pos(lo + ai)];
+      if (a.conj) v.y = -v.y;
+      return v;
+    }
+  };
   // M_k(c)[j][jo]: row j, compact column jo of child c's matrix for mode k
   auto mat = [&](int c, int k, int j, int jo) -> C {
     if constexpr (SM) {
-      const int off = k == 1 ? 0 : a.R[1] * a.A[1];
+      const int off = a.chunk * a.R[0] + (k == 1 ? 0 : a.R[1] * a.A[1]);
       return mall[c * msz + off + j * sg[k].c + jo];
     } else {
       C v = mats[(long long)cfi[c] * a.mat_item_stride + a.mat_k_off[k] +
@@ -377,44 +491,60 @@ __global__ void __launch_bounds__(kThreads)
       return v;
     }
   };
+  const int ng0 = (na + kG - 1) / kG;
+  if constexpr (kG > 1) __syncthreads();  // staged M_0 slices
   if constexpr (D == 2) {
     // buf1[c][ai][j1][q] = sum_j0 M0_c[j0][pos(lo+ai)] fine_c(j0, j1, q), j1 < r1(c)
     const int per_c = na * R1 * QT;
-    for (int idx = threadIdx.x; idx < nchild * per_c; idx += kThreads) {
-      const int c = idx / per_c;
-      int t = idx % per_c;
-      const int q = t % QT;
-      t /= QT;
-      const int j1 = t % R1, ai = t / R1;
+    for (int idx = threadIdx.x; idx < nchild * ng0 * R1 * QT; idx += kThreads) {
+      const int q = idx % QT;
+      int t = idx / QT;
+      const int j1 = t % R1;
+      t /= R1;
+      const int a0 = (t % ng0) * kG, c = t / ng0, ng = min(kG, na - a0);
       if (j1 >= crk[c][1]) continue;
-      C acc = czero<C>();
+      C acc[kG];
+      gzero(acc);
       if (q < Qa) {
-        const C* M0 = mats + (long long)cfi[c] * a.mat_item_stride + a.mat_k_off[0] +
-                      (long long)beta[0] * a.R[0] * A0 + sg[0].pos(lo + ai);
         const C* src = fine + cfb[c] + j1 * fs[1] + q;
-        const int r0 = crk[c][0];
-        for (int j0 = 0; j0 < r0; ++j0) {
-          C m = M0[j0 * A0];
-          if (a.conj) m.y = -m.y;
-          acc = cfma(acc, m, src[j0 * fs[0]]);
-        }
+        gdot(acc, ng, crk[c][0], [&](int g, int j) { return mat0(c, a0 + g, j); },
+             [&](int j) { return src[j * fs[0]]; });
       }
-      buf1[idx] = acc;
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (g < ng) buf1[c * per_c + ((a0 + g) * R1 + j1) * QT + q] = acc[g];
     }
     __syncthreads();
     CoarseAddr<D> ca;
     ca.init(a, ci, beta, q0);
-    for (int idx = threadIdx.x; idx < na * c1 * QT; idx += kThreads) {
-      const int q = idx % QT, t = idx / QT, j1o = t % c1, ai = t / c1;
+    // coarse[lo+ai][j1o][q] = sum_c sum_j1 M1_c[j1][j1o] buf1[c][ai][j1][q]
+    const int ng1 = (c1 + kG - 1) / kG;
+    for (int idx = threadIdx.x; idx < ng1 * na * QT; idx += kThreads) {
+      int q, ai, t;
+      if (a.coarse_global) {
+        ai = idx % na;
+        t = idx / na;
+        q = t % QT;
+        t /= QT;
+      } else {
+        q = idx % QT;
+        t = idx / QT;
+        ai = t % na;
+        t /= na;
+      }
+      const int j1o = t * kG, ng = min(kG, c1 - j1o);
       if (q >= Qa) continue;
-      C acc = czero<C>();
+      C acc[kG];
+      gzero(acc);
       for (int c = 0; c < nchild; ++c) {
         const C* src = buf1 + c * per_c + (ai * R1) * QT + q;
-        const int r1 = crk[c][1];
-        for (int j1 = 0; j1 < r1; ++j1) acc = cfma(acc, mat(c, 1, j1, j1o), src[j1 * QT]);
+        gdot(acc, ng, crk[c][1], [&](int g, int j) { return mat(c, 1, j, j1o + g); },
+             [&](int j) { return src[j * QT]; });
       }
-      coarse[ca.base + sg[0].pos(lo + ai) * ca.stride[0] + sg[1].pos(j1o) * ca.stride[1] + q * ca.qstride] =
-          acc;
+      C* dst = coarse + ca.base + sg[0].pos(lo + ai) * ca.stride[0] + q * ca.qstride;
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (g < ng) dst[sg[1].pos(j1o + g) * ca.stride[1]] = acc[g];
     }
   } else {
     const int R2 = a.R[2];
@@ -422,64 +552,284 @@ __global__ void __launch_bounds__(kThreads)
     const int per_c1 = na * R1 * R2 * QT;
     const int per_c2 = na * a.A[1] * R2 * QT;
     C* buf2 = buf1 + nchild * per_c1;
-    for (int idx = threadIdx.x; idx < nchild * per_c1; idx += kThreads) {
-      const int c = idx / per_c1;
-      int t = idx % per_c1;
-      const int q = t % QT;
-      t /= QT;
+    // buf1[c][ai][j1][j2][q] = sum_j0 M0_c[j0][pos(lo+ai)] fine_c(j0, j1, j2, q)
+    for (int idx = threadIdx.x; idx < nchild * ng0 * R1 * R2 * QT; idx += kThreads) {
+      const int q = idx % QT;
+      int t = idx / QT;
       const int j2 = t % R2;
       t /= R2;
-      const int j1 = t % R1, ai = t / R1;
+      const int j1 = t % R1;
+      t /= R1;
+      const int a0 = (t % ng0) * kG, c = t / ng0, ng = min(kG, na - a0);
       if (j1 >= crk[c][1] || j2 >= crk[c][2]) continue;
-      C acc = czero<C>();
+      C acc[kG];
+      gzero(acc);
       if (q < Qa) {
-        const C* M0 = mats + (long long)cfi[c] * a.mat_item_stride + a.mat_k_off[0] +
-                      (long long)beta[0] * a.R[0] * A0 + sg[0].pos(lo + ai);
         const C* src = fine + cfb[c] + j1 * fs[1] + j2 * fs[2] + q;
-        const int r0 = crk[c][0];
-        for (int j0 = 0; j0 < r0; ++j0) {
-          C m = M0[j0 * A0];
-          if (a.conj) m.y = -m.y;
-          acc = cfma(acc, m, src[j0 * fs[0]]);
-        }
+        gdot(acc, ng, crk[c][0], [&](int g, int j) { return mat0(c, a0 + g, j); },
+             [&](int j) { return src[j * fs[0]]; });
       }
-      buf1[idx] = acc;
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (g < ng) buf1[c * per_c1 + (((a0 + g) * R1 + j1) * R2 + j2) * QT + q] = acc[g];
     }
     __syncthreads();
     // buf2[c][ai][j1o][j2][q] = sum_j1 M1_c[j1][j1o] buf1[c][ai][j1][j2][q]
-    for (int idx = threadIdx.x; idx < nchild * per_c2; idx += kThreads) {
-      const int c = idx / per_c2;
-      int t = idx % per_c2;
-      const int q = t % QT;
-      t /= QT;
+    const int ng1 = (c1 + kG - 1) / kG;
+    for (int idx = threadIdx.x; idx < nchild * ng1 * na * R2 * QT; idx += kThreads) {
+      const int q = idx % QT;
+      int t = idx / QT;
       const int j2 = t % R2;
       t /= R2;
-      const int j1o = t % a.A[1], ai = t / a.A[1];
-      const int r1 = crk[c][1];
-      if (j1o >= c1 || j2 >= crk[c][2]) continue;
+      const int ai = t % na;
+      t /= na;
+      const int j1o = (t % ng1) * kG, c = t / ng1, ng = min(kG, c1 - j1o);
+      if (j2 >= crk[c][2]) continue;
+      C acc[kG];
+      gzero(acc);
       const C* src = buf1 + c * per_c1 + ((ai * R1) * R2 + j2) * QT + q;
-      C acc = czero<C>();
-      for (int j1 = 0; j1 < r1; ++j1) acc = cfma(acc, mat(c, 1, j1, j1o), src[j1 * R2 * QT]);
-      buf2[idx] = acc;
+      gdot(acc, ng, crk[c][1], [&](int g, int j) { return mat(c, 1, j, j1o + g); },
+           [&](int j) { return src[j * R2 * QT]; });
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (g < ng) buf2[c * per_c2 + ((ai * a.A[1] + j1o + g) * R2 + j2) * QT + q] = acc[g];
     }
     __syncthreads();
     CoarseAddr<D> ca;
     ca.init(a, ci, beta, q0);
-    for (int idx = threadIdx.x; idx < na * c1 * c2 * QT; idx += kThreads) {
-      const int q = idx % QT;
-      int t = idx / QT;
-      const int j2o = t % c2;
-      t /= c2;
-      const int j1o = t % c1, ai = t / c1;
+    // coarse[lo+ai][j1o][j2o][q] = sum_c sum_j2 M2_c[j2][j2o] buf2[c][ai][j1o][j2][q]
+    const int ng2 = (c2 + kG - 1) / kG;
+    for (int idx = threadIdx.x; idx < ng2 * na * c1 * QT; idx += kThreads) {
+      int q, j1o, t;
+      if (a.coarse_global) {
+        j1o = idx % c1;
+        t = idx / c1;
+        q = t % QT;
+        t /= QT;
+      } else {
+        q = idx % QT;
+        t = idx / QT;
+        j1o = t % c1;
+        t /= c1;
+      }
+      const int ai = t % na, j2o = (t / na) * kG, ng = min(kG, c2 - j2o);
       if (q >= Qa) continue;
-      C acc = czero<C>();
+      C acc[kG];
+      gzero(acc);
       for (int c = 0; c < nchild; ++c) {
         const C* src = buf2 + c * per_c2 + ((ai * a.A[1] + j1o) * R2) * QT + q;
-        const int r2 = crk[c][2];
-        for (int j2 = 0; j2 < r2; ++j2) acc = cfma(acc, mat(c, 2, j2, j2o), src[j2 * QT]);
+        gdot(acc, ng, crk[c][2], [&](int g, int j) { return mat(c, 2, j, j2o + g); },
+             [&](int j) { return src[j * QT]; });
       }
-      coarse[ca.base + sg[0].pos(lo + ai) * ca.stride[0] + sg[1].pos(j1o) * ca.stride[1] +
-             sg[2].pos(j2o) * ca.stride[2] + q * ca.qstride] = acc;
+      C* dst = coarse + ca.base + sg[0].pos(lo + ai) * ca.stride[0] + sg[1].pos(j1o) * ca.stride[1] +
+               q * ca.qstride;
+#pragma unroll
+      for (int g = 0; g < kG; ++g)
+        if (g < ng) dst[sg[2].pos(j2o + g) * ca.stride[2]] = acc[g];
+    }
+  }
+}
+
+// ------------------------------------------------------ fan-in, in turn --
+// The same sum as stage_fanin, with the 2^d children taken one after the
+// other: per child the modes D-1 .. 1 are contracted through LDS (one
+// child's intermediates at a time) and mode 0 is accumulated in registers.
+// Each thread owns up to kSeqFib output fibers (a_1..a_{D-1}, q) and all
+// rows a_0 of its slice (at most kSeqRows), so nothing is re-read across
+// slices unless the coarse block has more than kSeqRows rows.
+constexpr int kSeqRows = 16;
+
+template <class T>
+struct SeqFib {
+  static constexpr int value = sizeof(T) == 8 ? 2 : 4;
+};
+
+template <class T, int D, int QT>
+__global__ void __launch_bounds__(kThreads)
+    stage_fanin_seq(StageArgs a, const typename CplxOf<T>::type* __restrict__ fine,
+                    typename CplxOf<T>::type* __restrict__ coarse,
+                    const typename CplxOf<T>::type* __restrict__ mats) {
+  using C = typename CplxOf<T>::type;
+  constexpr int kF = SeqFib<T>::value;
+  constexpr int kGs = 8;
+  extern __shared__ unsigned char smem_raw[];
+  C* sm = reinterpret_cast<C*>(smem_raw);
+  const StageBid sb = stage_bid(a, QT);
+  const int ci = sb.item_blk / a.nblk;
+  int beta[D];
+  unflatten_blk<D>(sb.item_blk % a.nblk, a.nb, beta);
+  Seg sg[D];
+  coarse_segs<D>(a, ci, beta, sg);
+  const int lo = sb.split * a.chunk;
+  const int na = min(sg[0].c, lo + a.chunk) - lo;
+  if (na <= 0) return;
+  const int q0 = sb.q0;
+  const int Qa = min(QT, a.nrhs - q0);
+  const int nchild = a.coarse_global ? 1 : (1 << D);
+  __shared__ int cfi[kMaxChildren], crk[kMaxChildren][kMaxD];
+  __shared__ long long cfb[kMaxChildren];
+  if (threadIdx.x < nchild) {
+    const int c = threadIdx.x;
+    const int fi = a.coarse_global ? ci : child_of<D>(ci, a.lvl, c);
+    cfi[c] = fi;
+#pragma unroll
+    for (int k = 0; k < D; ++k) crk[c][k] = a.rank_f[((long long)fi * D + k) * a.nb + beta[k]];
+    long long fs_[D];
+    cfb[c] = fine_base<D>(a, fi, beta, q0, fs_);
+  }
+  long long fs[D];
+  (void)fine_base<D>(a, 0, beta, 0, fs);  // strides only
+  __syncthreads();
+  // every child's matrices, compact: M_0 [j][ai] (r_0 x na), M_k [j][a_k]
+  // (r_k x c_k) for k >= 1
+  int msz = a.R[0] * a.chunk;
+#pragma unroll
+  for (int k = 1; k < D; ++k) msz += a.R[k] * a.A[k];
+  for (int c = 0; c < nchild; ++c) {
+    const C* mbase = mats + (long long)cfi[c] * a.mat_item_stride;
+    int off = c * msz;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
+      const int ck = k == 0 ? na : sg[k].c, rk = crk[c][k], j0 = k == 0 ? lo : 0;
+      for (int i = threadIdx.x; i < rk * ck; i += kThreads) {
+        const int row = i / ck, j = i % ck;
+        C v = src[row * a.A[k] + sg[k].pos(j0 + j)];
+        if (a.conj) v.y = -v.y;
+        sm[off + i] = v;
+      }
+      off += k == 0 ? a.R[0] * a.chunk : a.R[k] * a.A[k];
+    }
+  }
+  C* t1 = sm + nchild * msz;
+  const int c1 = sg[1].c;
+  const int c2 = D == 3 ? sg[D - 1].c : 1;
+  C* t2 = t1 + (D == 3 ? a.R[0] * a.R[1] * a.A[D - 1] * QT : 0);
+  // output fibers: (a_1, q) for D = 2, (a_1, a_2, q) for D = 3; the
+  // contiguous index of the destination runs fastest
+  const int nfib = c1 * c2 * QT;
+  auto fiber = [&](int f, int* a1, int* a2, int* q) {
+    if (a.coarse_global) {
+      const int inner = D == 3 ? c2 : c1;
+      const int x = f % inner, t = f / inner;
+      *q = t % QT;
+      if (D == 3) {
+        *a2 = x;
+        *a1 = t / QT;
+      } else {
+        *a1 = x;
+        *a2 = 0;
+      }
+    } else {
+      *q = f % QT;
+      const int t = f / QT;
+      *a2 = D == 3 ? t % c2 : 0;
+      *a1 = D == 3 ? t / c2 : t;
+    }
+  };
+  C acc[kF][kSeqRows];
+#pragma unroll
+  for (int f = 0; f < kF; ++f)
+#pragma unroll
+    for (int r = 0; r < kSeqRows; ++r) acc[f][r] = czero<C>();
+  __syncthreads();
+  for (int c = 0; c < nchild; ++c) {
+    const int r0 = crk[c][0], r1 = crk[c][1];
+    const C* M0c = sm + c * msz;
+    const C* M1c = M0c + a.R[0] * a.chunk;
+    const C* fc = fine + cfb[c];
+    const C* xin;  // [j0][a1][a2][q] input of the mode-0 step
+    if constexpr (D == 2) {
+      // t1[j0][a1][q] = sum_j1 M1c[j1][a1] fine_c(j0, j1, q)
+      const int ng = (c1 + kGs - 1) / kGs;
+      for (int idx = threadIdx.x; idx < ng * r0 * QT; idx += kThreads) {
+        const int q = idx % QT;
+        const int t = idx / QT;
+        const int j0 = t % r0, a1 = (t / r0) * kGs, n1 = min(kGs, c1 - a1);
+        C o[kGs];
+        gzero(o);
+        if (q < Qa)
+          gdot(o, n1, r1, [&](int g, int j) { return M1c[j * c1 + a1 + g]; },
+               [&](int j) { return fc[j0 * fs[0] + j * fs[1] + q]; });
+#pragma unroll
+        for (int g = 0; g < kGs; ++g)
+          if (g < n1) t1[(j0 * c1 + a1 + g) * QT + q] = o[g];
+      }
+      xin = t1;
+    } else {
+      const int r2 = crk[c][2];
+      const C* M2c = M1c + a.R[1] * a.A[1];
+      // t1[j0][j1][a2][q] = sum_j2 M2c[j2][a2] fine_c(j0, j1, j2, q)
+      const int ng2 = (c2 + kGs - 1) / kGs;
+      for (int idx = threadIdx.x; idx < ng2 * r0 * r1 * QT; idx += kThreads) {
+        const int q = idx % QT;
+        int t = idx / QT;
+        const int j1 = t % r1;
+        t /= r1;
+        const int j0 = t % r0, a2 = (t / r0) * kGs, n2 = min(kGs, c2 - a2);
+        C o[kGs];
+        gzero(o);
+        if (q < Qa)
+          gdot(o, n2, r2, [&](int g, int j) { return M2c[j * c2 + a2 + g]; },
+               [&](int j) { return fc[j0 * fs[0] + j1 * fs[1] + j * fs[2] + q]; });
+#pragma unroll
+        for (int g = 0; g < kGs; ++g)
+          if (g < n2) t1[((j0 * r1 + j1) * c2 + a2 + g) * QT + q] = o[g];
+      }
+      __syncthreads();
+      // t2[j0][a1][a2][q] = sum_j1 M1c[j1][a1] t1[j0][j1][a2][q]
+      const int ng1 = (c1 + kGs - 1) / kGs;
+      for (int idx = threadIdx.x; idx < ng1 * r0 * c2 * QT; idx += kThreads) {
+        const int q = idx % QT;
+        int t = idx / QT;
+        const int a2 = t % c2;
+        t /= c2;
+        const int j0 = t % r0, a1 = (t / r0) * kGs, n1 = min(kGs, c1 - a1);
+        C o[kGs];
+        gzero(o);
+        const C* src = t1 + ((j0 * r1) * c2 + a2) * QT + q;
+        gdot(o, n1, r1, [&](int g, int j) { return M1c[j * c1 + a1 + g]; },
+             [&](int j) { return src[j * c2 * QT]; });
+#pragma unroll
+        for (int g = 0; g < kGs; ++g)
+          if (g < n1) t2[((j0 * c1 + a1 + g) * c2 + a2) * QT + q] = o[g];
+      }
+      xin = t2;
+    }
+    __syncthreads();
+    // acc[f][ai] += sum_j0 M0c[j0][ai] xin[j0][a1][a2][q]
+#pragma unroll
+    for (int f = 0; f < kF; ++f) {
+      const int fid = threadIdx.x + f * kThreads;
+      if (fid < nfib) {
+        int a1, a2, q;
+        fiber(fid, &a1, &a2, &q);
+        const C* src = xin + (a1 * c2 + a2) * QT + q;
+        for (int j0 = 0; j0 < r0; ++j0) {
+          const C xv = src[j0 * c1 * c2 * QT];
+#pragma unroll
+          for (int r = 0; r < kSeqRows; ++r)
+            if (r < na) acc[f][r] = cfma(acc[f][r], M0c[j0 * na + r], xv);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  CoarseAddr<D> ca;
+  ca.init(a, ci, beta, q0);
+#pragma unroll
+  for (int f = 0; f < kF; ++f) {
+    const int fid = threadIdx.x + f * kThreads;
+    if (fid < nfib) {
+      int a1, a2, q;
+      fiber(fid, &a1, &a2, &q);
+      if (q < Qa) {
+        C* dst = coarse + ca.base + sg[1].pos(a1) * ca.stride[1] + q * ca.qstride;
+        if (D == 3) dst += sg[D - 1].pos(a2) * ca.stride[D - 1];
+#pragma unroll
+        for (int r = 0; r < kSeqRows; ++r)
+          if (r < na) dst[sg[0].pos(lo + r) * ca.stride[0]] = acc[f][r];
+      }
     }
   }
 }
@@ -1069,25 +1419,25 @@ static StageArgs stage_args(const Plan& p, const Level& fine, const Level* coars
   return a;
 }
 
-template <class T, int D, int QT>
+template <class T, int D, int QT, int G>
 static tb_status launch_fanout(StageArgs a, dim3 grid, size_t lds, const void* in, void* out,
                                const void* mats, hipStream_t stream) {
   using C = typename CplxOf<T>::type;
-  TB_TRY(set_lds(stage_fanout<T, D, QT>, lds));
-  stage_fanout<T, D, QT><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+  TB_TRY(set_lds(stage_fanout<T, D, QT, G>, lds));
+  stage_fanout<T, D, QT, G><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
   return TB_OK;
 }
 
-template <class T, int D, int QT>
+template <class T, int D, int QT, int G>
 static tb_status launch_fanin(StageArgs a, bool sm, dim3 grid, size_t lds, const void* in, void* out,
                               const void* mats, hipStream_t stream) {
   using C = typename CplxOf<T>::type;
   if (sm) {
-    TB_TRY(set_lds(stage_fanin<T, D, QT, true>, lds));
-    stage_fanin<T, D, QT, true><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+    TB_TRY(set_lds(stage_fanin<T, D, QT, true, G>, lds));
+    stage_fanin<T, D, QT, true, G><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
   } else {
-    TB_TRY(set_lds(stage_fanin<T, D, QT, false>, lds));
-    stage_fanin<T, D, QT, false><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+    TB_TRY(set_lds(stage_fanin<T, D, QT, false, G>, lds));
+    stage_fanin<T, D, QT, false, G><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
   }
   return TB_OK;
 }
@@ -1099,41 +1449,114 @@ static long long stage_lds_elems(const StageArgs& a, int d, bool fanout, int chu
   long long msz = 0;
   for (int k = 1; k < d; ++k) msz += (long long)a.R[k] * a.A[k];
   if (fanout) {
-    long long e = msz;
+    long long e = msz + (long long)chunk * a.A[0];
     if (d == 2) e += (long long)chunk * a.A[1] * QT;
     else e += (long long)chunk * a.A[1] * a.A[2] * QT + (long long)chunk * a.R[1] * a.A[2] * QT;
     return e;
   }
   const long long nchild = a.coarse_global ? 1 : (1LL << d);
-  long long e = sm ? nchild * msz : 0;
+  long long e = sm ? nchild * (msz + (long long)chunk * a.R[0]) : 0;
   if (d == 2) e += nchild * chunk * a.R[1] * QT;
   else e += nchild * chunk * a.R[1] * a.R[2] * QT + nchild * chunk * a.A[1] * a.R[2] * QT;
   return e;
 }
 
+// LDS elements and feasibility of stage_fanin_seq for a slice of `chunk`
+// rows and QT right-hand sides (padded extents bound the true ones).
+static long long seq_lds_elems(const StageArgs& a, int d, int chunk, int QT) {
+  const long long nchild = a.coarse_global ? 1 : (1LL << d);
+  long long msz = (long long)a.R[0] * chunk;
+  for (int k = 1; k < d; ++k) msz += (long long)a.R[k] * a.A[k];
+  long long e = nchild * msz;
+  if (d == 2) e += (long long)a.R[0] * a.A[1] * QT;
+  else e += (long long)a.R[0] * a.R[1] * a.A[2] * QT + (long long)a.R[0] * a.A[1] * a.A[2] * QT;
+  return e;
+}
+
 template <class T, int D>
-static tb_status launch_stage_d(StageArgs a, bool fanout, bool sm, int QT, dim3 grid, size_t lds,
-                                const void* in, void* out, const void* mats, hipStream_t stream) {
-  if (fanout) {
-    switch (QT) {
-      case 1: return launch_fanout<T, D, 1>(a, grid, lds, in, out, mats, stream);
-      case 2: return launch_fanout<T, D, 2>(a, grid, lds, in, out, mats, stream);
-      case 4: return launch_fanout<T, D, 4>(a, grid, lds, in, out, mats, stream);
-      default: return launch_fanout<T, D, 8>(a, grid, lds, in, out, mats, stream);
-    }
-  }
+static tb_status launch_fanin_seq(StageArgs a, int QT, dim3 grid, size_t lds, const void* in, void* out,
+                                  const void* mats, hipStream_t stream) {
+  using C = typename CplxOf<T>::type;
   switch (QT) {
-    case 1: return launch_fanin<T, D, 1>(a, sm, grid, lds, in, out, mats, stream);
-    case 2: return launch_fanin<T, D, 2>(a, sm, grid, lds, in, out, mats, stream);
-    case 4: return launch_fanin<T, D, 4>(a, sm, grid, lds, in, out, mats, stream);
-    default: return launch_fanin<T, D, 8>(a, sm, grid, lds, in, out, mats, stream);
+#define TB_SEQ_CASE(Q)                                                                            \
+  case Q:                                                                                         \
+    TB_TRY(set_lds(stage_fanin_seq<T, D, Q>, lds));                                               \
+    stage_fanin_seq<T, D, Q><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats); \
+    return TB_OK;
+    TB_SEQ_CASE(1)
+    TB_SEQ_CASE(2)
+    TB_SEQ_CASE(4)
+    TB_SEQ_CASE(8)
+#undef TB_SEQ_CASE
   }
+  return fail(TB_ERR_INVALID_ARG, "bad RHS tile");
 }
 
 template <class T>
-static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_items, const void* in,
-                              void* out, const void* mats, hipStream_t stream) {
+static tb_status launch_stage_seq(const Plan& p, StageArgs a, int n_items, const void* in, void* out,
+                                  const void* mats, hipStream_t stream, const LaunchCfg& cfg) {
   using C = typename CplxOf<T>::type;
+  const int d = p.d;
+  int limit = 0;
+  TB_TRY(lds_limit(&limit));
+  const long long budget = std::min<long long>(limit, 80 * 1024);
+  const long long fib1 = d == 2 ? a.A[1] : (long long)a.A[1] * a.A[2];
+  const int chunk = std::min(a.A[0], kSeqRows);
+  const int qcap = cfg.QT > 0 ? cfg.QT : 8;
+  int QT = 1;
+  while (QT * 2 <= qcap && QT * 2 <= a.nrhs) QT *= 2;
+  while (QT > 1 && (seq_lds_elems(a, d, chunk, QT) * (long long)sizeof(C) > budget ||
+                    fib1 * QT > (long long)SeqFib<T>::value * kThreads))
+    QT /= 2;
+  if (cfg.QT > 0 && QT != cfg.QT) return fail(TB_ERR_UNSUPPORTED, "RHS tile does not fit this stage");
+  if (fib1 * QT > (long long)SeqFib<T>::value * kThreads)
+    return fail(TB_ERR_UNSUPPORTED, "coarse block too wide for the in-turn fan-in");
+  const size_t lds = (size_t)seq_lds_elems(a, d, chunk, QT) * sizeof(C);
+  if (lds > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "in-turn fan-in exceeds the LDS limit");
+  const long long blocks = (long long)n_items * a.nblk;
+  a.chunk = chunk;
+  a.nsplit = (a.A[0] + chunk - 1) / chunk;
+  const long long nwg = blocks * a.nsplit * ((a.nrhs + QT - 1) / QT);
+  if (nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many right-hand sides for one launch");
+  dim3 grid((unsigned)nwg);
+  const tb_status st = d == 2 ? launch_fanin_seq<T, 2>(a, QT, grid, lds, in, out, mats, stream)
+                              : launch_fanin_seq<T, 3>(a, QT, grid, lds, in, out, mats, stream);
+  TB_TRY(st);
+  TB_HIP_TRY(hipGetLastError());
+  return TB_OK;
+}
+
+template <class T, int D, int G>
+static tb_status launch_stage_g(StageArgs a, bool fanout, bool sm, int QT, dim3 grid, size_t lds,
+                                const void* in, void* out, const void* mats, hipStream_t stream) {
+  if (fanout) {
+    switch (QT) {
+      case 1: return launch_fanout<T, D, 1, G>(a, grid, lds, in, out, mats, stream);
+      case 2: return launch_fanout<T, D, 2, G>(a, grid, lds, in, out, mats, stream);
+      case 4: return launch_fanout<T, D, 4, G>(a, grid, lds, in, out, mats, stream);
+      default: return launch_fanout<T, D, 8, G>(a, grid, lds, in, out, mats, stream);
+    }
+  }
+  switch (QT) {
+    case 1: return launch_fanin<T, D, 1, G>(a, sm, grid, lds, in, out, mats, stream);
+    case 2: return launch_fanin<T, D, 2, G>(a, sm, grid, lds, in, out, mats, stream);
+    case 4: return launch_fanin<T, D, 4, G>(a, sm, grid, lds, in, out, mats, stream);
+    default: return launch_fanin<T, D, 8, G>(a, sm, grid, lds, in, out, mats, stream);
+  }
+}
+
+// One transfer launch.  cfg fields left at 0 take the heuristic: the
+// largest RHS tile QT <= 8 that fits the LDS budget, G = 8 from QT = 4 on,
+// and slices of the first mode until about kTargetWorkgroups workgroups
+// exist (split = 1: one slice per block when it fits).
+template <class T>
+static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_items, const void* in,
+                              void* out, const void* mats, hipStream_t stream, const LaunchCfg& cfg) {
+  using C = typename CplxOf<T>::type;
+  if (cfg.alt == 1) {
+    if (fanout) return fail(TB_ERR_UNSUPPORTED, "no in-turn variant of the fan-out");
+    return launch_stage_seq<T>(p, a, n_items, in, out, mats, stream, cfg);
+  }
   const int d = p.d;
   int limit = 0;
   TB_TRY(lds_limit(&limit));
@@ -1143,9 +1566,14 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
   const int dim = fanout ? a.R[0] : a.A[0];
   // fan-in matrices are staged in LDS when they fit, else read from global
   const bool sm = fanout || stage_lds_elems(a, d, false, 1, 1, true) * (long long)sizeof(C) <= budget;
-  int QT = a.nrhs >= 8 ? 8 : (a.nrhs >= 4 ? 4 : (a.nrhs >= 2 ? 2 : 1));
+  const int qcap = cfg.QT > 0 ? cfg.QT : 8;
+  int QT = 1;
+  while (QT * 2 <= qcap && QT * 2 <= a.nrhs) QT *= 2;
   while (QT > 1 && stage_lds_elems(a, d, fanout, 1, QT, sm) * (long long)sizeof(C) > budget) QT /= 2;
-  int chunk = (int)std::max<long long>(1, (dim * blocks + kTargetWorkgroups - 1) / kTargetWorkgroups);
+  if (cfg.QT > 0 && QT != cfg.QT) return fail(TB_ERR_UNSUPPORTED, "RHS tile does not fit this stage");
+  int chunk = cfg.split == 1
+                  ? dim
+                  : (int)std::max<long long>(1, (dim * blocks + kTargetWorkgroups - 1) / kTargetWorkgroups);
   chunk = std::min(chunk, dim);
   while (chunk > 1 && stage_lds_elems(a, d, fanout, chunk, QT, sm) * (long long)sizeof(C) > budget) --chunk;
   const size_t lds = (size_t)stage_lds_elems(a, d, fanout, chunk, QT, sm) * sizeof(C);
@@ -1153,9 +1581,17 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
     return fail(TB_ERR_UNSUPPORTED, "transfer block exceeds the per-workgroup LDS budget");
   a.chunk = chunk;
   a.nsplit = (dim + chunk - 1) / chunk;
-  dim3 grid((unsigned)(blocks * a.nsplit), (unsigned)((a.nrhs + QT - 1) / QT));
-  const tb_status st = d == 2 ? launch_stage_d<T, 2>(a, fanout, sm, QT, grid, lds, in, out, mats, stream)
-                              : launch_stage_d<T, 3>(a, fanout, sm, QT, grid, lds, in, out, mats, stream);
+  const long long nwg = blocks * a.nsplit * ((a.nrhs + QT - 1) / QT);
+  if (nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many right-hand sides for one launch");
+  dim3 grid((unsigned)nwg);
+  const int G = cfg.G > 0 ? cfg.G : (QT >= 4 ? 8 : 1);
+  tb_status st;
+  if (G == 8)
+    st = d == 2 ? launch_stage_g<T, 2, 8>(a, fanout, sm, QT, grid, lds, in, out, mats, stream)
+                : launch_stage_g<T, 3, 8>(a, fanout, sm, QT, grid, lds, in, out, mats, stream);
+  else
+    st = d == 2 ? launch_stage_g<T, 2, 1>(a, fanout, sm, QT, grid, lds, in, out, mats, stream)
+                : launch_stage_g<T, 3, 1>(a, fanout, sm, QT, grid, lds, in, out, mats, stream);
   TB_TRY(st);
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;
@@ -1204,7 +1640,7 @@ static tb_status launch_core_mfma(const Plan& p, const CoreArgs& a, bool adjoint
 
 template <class T, class CS>
 static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* cores, const void* in,
-                             void* out, hipStream_t stream) {
+                             void* out, hipStream_t stream, const LaunchCfg& cfg) {
   const int d = p.d;
   const Level& st = p.src[p.Lt];
   const Level& tt = p.tgt[p.Ls];
@@ -1224,16 +1660,19 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
     maxRTp = std::max(maxRTp, p.pair_meta[(size_t)pr * kPairMeta + 2]);
   }
   if constexpr (sizeof(T) == 4) {
-    if (nrhs >= kMfmaMinRhs)
+    if (cfg.core == 3 || (cfg.core == 0 && nrhs >= kMfmaMinRhs))
       return d == 2 ? launch_core_mfma<CS, 2>(p, a, adjoint, cores, in, out, stream)
                     : launch_core_mfma<CS, 3>(p, a, adjoint, cores, in, out, stream);
+  } else {
+    if (cfg.core == 3) return fail(TB_ERR_UNSUPPORTED, "no matrix-core path for FP64");
   }
   int limit = 0;
   TB_TRY(lds_limit(&limit));
   using C = typename CplxOf<T>::type;
   const size_t need4 = adjoint ? (size_t)maxRTp * 4 * sizeof(C)
                                : ((size_t)maxRS * 4 + (size_t)kThreads * CoreVec<CS>::VR * 4) * sizeof(C);
-  if (nrhs == 1 || need4 > (size_t)limit)
+  if (cfg.core == 2 && need4 > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "core tile exceeds LDS");
+  if (cfg.core == 1 || nrhs == 1 || need4 > (size_t)limit)
     return d == 2 ? launch_core_q<T, CS, 2, 1>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream)
                   : launch_core_q<T, CS, 3, 1>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream);
   return d == 2 ? launch_core_q<T, CS, 2, 4>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream)
@@ -1254,61 +1693,79 @@ static tb_status timed(Plan& p, int stage, hipStream_t stream, F&& launch) {
   return st;
 }
 
+// The kernel launches of one apply, in order; run(cfg) enqueues one launch.
+struct Step {
+  int stage;
+  bool core, fanout;
+  std::function<tb_status(const LaunchCfg&)> run;
+};
+
 template <class T, class CS>
-static tb_status apply_typed(Plan& p, const void* in, void* out, long long nrhs, bool adjoint,
-                             const void* cores, hipStream_t stream) {
+static tb_status build_steps(Plan& p, const void* in, void* out, long long nrhs, bool adjoint,
+                             const void* cores, hipStream_t stream, std::vector<Step>* steps) {
   using C = typename CplxOf<T>::type;
   const size_t esz = sizeof(C);
   Buffers b = layout(p, nrhs, esz);
   TB_TRY(ensure_workspace(p, b.total));
   char* ws = static_cast<char*>(p.ws.base);
-  auto S = [&](int l) { return (void*)(ws + b.src_off[l]); };
-  auto Tb = [&](int l) { return (void*)(ws + b.tgt_off[l]); };
-  auto mats = [&](const Level& lv) -> const void* {
+  auto S = [ws, b](int l) { return (void*)(ws + b.src_off[l]); };
+  auto Tb = [ws, b](int l) { return (void*)(ws + b.tgt_off[l]); };
+  auto mats = [](const Level& lv) -> const void* {
     return sizeof(T) == 8 ? (const void*)lv.X64 : (const void*)lv.X32;
   };
   const int rhs = (int)nrhs;
+  Plan* pp = &p;
+  auto stage = [&](int id, const Level& lv, const Level* coarse, bool source, bool conj, bool fanout,
+                   int n_items, const void* src, void* dst) {
+    StageArgs a = stage_args(p, lv, coarse, source, rhs, conj);
+    const void* m = mats(lv);
+    steps->push_back({id, false, fanout, [=](const LaunchCfg& c) {
+                        return launch_stage<T>(*pp, a, fanout, n_items, src, dst, m, stream, c);
+                      }});
+  };
+  auto core = [&](bool adj, const void* src, void* dst) {
+    steps->push_back({adj ? TB_STAGE_CORE_ADJ : TB_STAGE_CORE, true, false, [=](const LaunchCfg& c) {
+                        return launch_core<T, CS>(*pp, adj, rhs, cores, src, dst, stream, c);
+                      }});
+  };
+  steps->clear();
   if (!adjoint) {
     // (1) V then W: coarse (f or level l-1) -> fine (level l)
-    for (int l = 0; l <= p.Lt; ++l) {
-      const Level& lv = p.src[l];
-      StageArgs a = stage_args(p, lv, l ? &p.src[l - 1] : nullptr, true, rhs, false);
-      TB_TRY(timed(p, l ? TB_STAGE_SRC_TRANSFER : TB_STAGE_SRC_LEAF, stream, [&] {
-        return launch_stage<T>(p, a, true, lv.nitems, l ? S(l - 1) : in, S(l), mats(lv), stream);
-      }));
-    }
+    for (int l = 0; l <= p.Lt; ++l)
+      stage(l ? TB_STAGE_SRC_TRANSFER : TB_STAGE_SRC_LEAF, p.src[l], l ? &p.src[l - 1] : nullptr, true,
+            false, true, p.src[l].nitems, l ? S(l - 1) : in, S(l));
     // (2) cores
-    TB_TRY(timed(p, TB_STAGE_CORE, stream, [&] {
-      return launch_core<T, CS>(p, false, rhs, cores, S(p.Lt), Tb(p.Ls), stream);
-    }));
+    core(false, S(p.Lt), Tb(p.Ls));
     // (3) P^T accumulated into the parents, then U^T into u
-    for (int l = p.Ls; l >= 0; --l) {
-      const Level& lv = p.tgt[l];
-      StageArgs a = stage_args(p, lv, l ? &p.tgt[l - 1] : nullptr, false, rhs, false);
-      int ncoarse = l ? p.tgt[l - 1].nitems : lv.nitems;
-      TB_TRY(timed(p, l ? TB_STAGE_TGT_TRANSFER : TB_STAGE_TGT_LEAF, stream, [&] {
-        return launch_stage<T>(p, a, false, ncoarse, Tb(l), l ? Tb(l - 1) : out, mats(lv), stream);
-      }));
-    }
+    for (int l = p.Ls; l >= 0; --l)
+      stage(l ? TB_STAGE_TGT_TRANSFER : TB_STAGE_TGT_LEAF, p.tgt[l], l ? &p.tgt[l - 1] : nullptr, false,
+            false, false, l ? p.tgt[l - 1].nitems : p.tgt[l].nitems, Tb(l), l ? Tb(l - 1) : out);
   } else {
-    for (int l = 0; l <= p.Ls; ++l) {
-      const Level& lv = p.tgt[l];
-      StageArgs a = stage_args(p, lv, l ? &p.tgt[l - 1] : nullptr, false, rhs, true);
-      TB_TRY(timed(p, l ? TB_STAGE_TGT_TRANSFER_ADJ : TB_STAGE_TGT_LEAF_ADJ, stream, [&] {
-        return launch_stage<T>(p, a, true, lv.nitems, l ? Tb(l - 1) : in, Tb(l), mats(lv), stream);
-      }));
-    }
-    TB_TRY(timed(p, TB_STAGE_CORE_ADJ, stream, [&] {
-      return launch_core<T, CS>(p, true, rhs, cores, Tb(p.Ls), S(p.Lt), stream);
-    }));
-    for (int l = p.Lt; l >= 0; --l) {
-      const Level& lv = p.src[l];
-      StageArgs a = stage_args(p, lv, l ? &p.src[l - 1] : nullptr, true, rhs, true);
-      int ncoarse = l ? p.src[l - 1].nitems : lv.nitems;
-      TB_TRY(timed(p, l ? TB_STAGE_SRC_TRANSFER_ADJ : TB_STAGE_SRC_LEAF_ADJ, stream, [&] {
-        return launch_stage<T>(p, a, false, ncoarse, S(l), l ? S(l - 1) : out, mats(lv), stream);
-      }));
-    }
+    for (int l = 0; l <= p.Ls; ++l)
+      stage(l ? TB_STAGE_TGT_TRANSFER_ADJ : TB_STAGE_TGT_LEAF_ADJ, p.tgt[l], l ? &p.tgt[l - 1] : nullptr,
+            false, true, true, p.tgt[l].nitems, l ? Tb(l - 1) : in, Tb(l));
+    core(true, Tb(p.Ls), S(p.Lt));
+    for (int l = p.Lt; l >= 0; --l)
+      stage(l ? TB_STAGE_SRC_TRANSFER_ADJ : TB_STAGE_SRC_LEAF_ADJ, p.src[l], l ? &p.src[l - 1] : nullptr,
+            true, true, false, l ? p.src[l - 1].nitems : p.src[l].nitems, S(l), l ? S(l - 1) : out);
+  }
+  return TB_OK;
+}
+
+static int steps_per_direction(const Plan& p) { return p.Lt + p.Ls + 3; }
+
+template <class T, class CS>
+static tb_status apply_typed(Plan& p, tb_dtype io, const void* in, void* out, long long nrhs, bool adjoint,
+                             const void* cores, hipStream_t stream) {
+  std::vector<Step> steps;
+  const tb_status built = build_steps<T, CS>(p, in, out, nrhs, adjoint, cores, stream, &steps);
+  TB_TRY(built);
+  const auto it = p.tuned.find({(int)io, nrhs});
+  const LaunchCfg none{};
+  const int base = adjoint ? steps_per_direction(p) : 0;
+  for (size_t i = 0; i < steps.size(); ++i) {
+    const LaunchCfg& cfg = it == p.tuned.end() ? none : it->second[base + i];
+    TB_TRY(timed(p, steps[i].stage, stream, [&] { return steps[i].run(cfg); }));
   }
   return TB_OK;
 }
@@ -1323,11 +1780,224 @@ tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs, tb_dtype
                 "the plan holds no cores of the requested precision (see store_mask)");
   if (in == out) return fail(TB_ERR_INVALID_ARG, "input and output must not alias");
   switch (io) {
-    case TB_C128: return apply_typed<double, double2>(p, in, out, nrhs, adjoint, p.cores[io], stream);
-    case TB_C64: return apply_typed<float, float2>(p, in, out, nrhs, adjoint, p.cores[io], stream);
-    case TB_CBF16: return apply_typed<float, unsigned>(p, in, out, nrhs, adjoint, p.cores[io], stream);
+    case TB_C128: return apply_typed<double, double2>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
+    case TB_C64: return apply_typed<float, float2>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
+    case TB_CBF16: return apply_typed<float, unsigned>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
   }
   return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
+}
+
+// ------------------------------------------------------------ autotuner --
+// For every kernel launch of both directions the candidate configurations
+// are timed (one warm-up, then the best of kTuneReps launches, HIP events)
+// on zero-filled buffers of the requested shape, and the fastest is kept in
+// p.tuned[(io, nrhs)].  Launches are independent of the data, so each slot
+// is tuned in place of its position in the sequence.
+constexpr int kTuneReps = 3;
+
+static uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ULL;
+  }
+  return h;
+}
+
+// Identifies the shapes of every launch: construction inputs, levels and
+// every true rank.
+static uint64_t plan_signature(const Plan& p) {
+  uint64_t h = 1469598103934665603ULL;
+  const long long head[] = {(long long)p.kind, p.d, p.leaf, p.L, p.Lt, p.Ls, p.n, p.npairs};
+  h = fnv1a(h, head, sizeof(head));
+  h = fnv1a(h, &p.omega, sizeof(p.omega));
+  h = fnv1a(h, &p.tol, sizeof(p.tol));
+  for (const auto* side : {&p.src, &p.tgt})
+    for (const Level& lv : *side) {
+      const long long dims[] = {lv.nitems, lv.nb, lv.R[0], lv.R[1], lv.R[2], lv.A[0], lv.A[1], lv.A[2]};
+      h = fnv1a(h, dims, sizeof(dims));
+      for (const IdRec& id : lv.ids) {
+        const int rc[] = {id.r, id.c};
+        h = fnv1a(h, rc, sizeof(rc));
+      }
+    }
+  return h;
+}
+
+static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout) {
+  std::vector<LaunchCfg> out;
+  for (int qt : {1, 2, 4, 8}) {
+    if (qt > 1 && qt > nrhs) break;
+    for (int g : {1, 8})
+      for (int split : {0, 1}) {
+        LaunchCfg c;
+        c.G = g;
+        c.QT = qt;
+        c.split = split;
+        out.push_back(c);
+      }
+    if (!fanout) {
+      LaunchCfg c;
+      c.QT = qt;
+      c.alt = 1;
+      out.push_back(c);
+    }
+  }
+  return out;
+}
+
+static std::vector<LaunchCfg> core_candidates(long long nrhs, tb_dtype io) {
+  std::vector<LaunchCfg> out;
+  LaunchCfg c;
+  c.core = 1;
+  out.push_back(c);
+  if (nrhs >= 2) {
+    c.core = 2;
+    out.push_back(c);
+  }
+  if (io != TB_C128 && nrhs >= 4) {
+    c.core = 3;
+    out.push_back(c);
+  }
+  return out;
+}
+
+static bool read_cache(const char* path, uint64_t sig, int io, long long nrhs, size_t nslots,
+                       std::vector<LaunchCfg>* cfg) {
+  FILE* fh = std::fopen(path, "r");
+  if (!fh) return false;
+  char line[8192];
+  bool found = false;
+  while (!found && std::fgets(line, sizeof(line), fh)) {
+    unsigned long long s = 0;
+    int fio = 0, n = 0, pos = 0;
+    long long fr = 0;
+    if (std::sscanf(line, "tbtune2 %llx %d %lld %d%n", &s, &fio, &fr, &n, &pos) != 4) continue;
+    if (s != sig || fio != io || fr != nrhs || (size_t)n != nslots) continue;
+    std::vector<LaunchCfg> v(n);
+    const char* q = line + pos;
+    bool ok = true;
+    for (int i = 0; i < n && ok; ++i) {
+      int used = 0;
+      ok = std::sscanf(q, " %d,%d,%d,%d,%d%n", &v[i].G, &v[i].QT, &v[i].split, &v[i].core, &v[i].alt,
+                       &used) == 5;
+      q += used;
+    }
+    if (ok) {
+      *cfg = v;
+      found = true;
+    }
+  }
+  std::fclose(fh);
+  return found;
+}
+
+static void append_cache(const char* path, uint64_t sig, int io, long long nrhs,
+                         const std::vector<LaunchCfg>& cfg) {
+  FILE* fh = std::fopen(path, "a");
+  if (!fh) return;
+  std::fprintf(fh, "tbtune2 %016llx %d %lld %d", (unsigned long long)sig, io, nrhs, (int)cfg.size());
+  for (const LaunchCfg& c : cfg) std::fprintf(fh, " %d,%d,%d,%d,%d", c.G, c.QT, c.split, c.core, c.alt);
+  std::fprintf(fh, "\n");
+  std::fclose(fh);
+}
+
+template <class T, class CS>
+static tb_status tune_typed(Plan& p, tb_dtype io, long long nrhs, hipStream_t stream,
+                            std::vector<LaunchCfg>* best, int* trials) {
+  using C = typename CplxOf<T>::type;
+  long long ndim = 1;
+  for (int k = 0; k < p.d; ++k) ndim *= p.n;
+  const size_t bytes = (size_t)(nrhs * ndim) * sizeof(C);
+  if (p.max_device_bytes && p.device_bytes + 2 * bytes > p.max_device_bytes)
+    return fail(TB_ERR_OOM, "autotune buffers exceed the plan's device memory cap");
+  void* bin = nullptr;
+  void* bout = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    if (bin) (void)hipFree(bin);
+    if (bout) (void)hipFree(bout);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  tb_status st = TB_OK;
+  auto check = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess && st == TB_OK) {
+      (void)hipGetLastError();
+      st = fail(TB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    }
+  };
+  check(hipMalloc(&bin, bytes), "autotune input");
+  check(hipMalloc(&bout, bytes), "autotune output");
+  check(hipEventCreate(&e0), "hipEventCreate");
+  check(hipEventCreate(&e1), "hipEventCreate");
+  const bool was_timing = p.timing;
+  p.timing = false;
+  best->assign(2 * steps_per_direction(p), LaunchCfg{});
+  for (int dir = 0; dir < 2 && st == TB_OK; ++dir) {
+    std::vector<Step> steps;
+    st = build_steps<T, CS>(p, bin, bout, nrhs, dir == 1, p.cores[io], stream, &steps);
+    if (st != TB_OK) break;
+    check(hipMemsetAsync(bin, 0, bytes, stream), "hipMemsetAsync");
+    check(hipMemsetAsync(p.ws.base, 0, p.ws.bytes, stream), "hipMemsetAsync");
+    for (size_t i = 0; i < steps.size() && st == TB_OK; ++i) {
+      const auto cands = steps[i].core ? core_candidates(nrhs, io) : stage_candidates(nrhs, steps[i].fanout);
+      float best_ms = 1e30f;
+      LaunchCfg pick{};
+      for (const LaunchCfg& c : cands) {
+        if (steps[i].run(c) != TB_OK) {  // does not fit this launch
+          (void)hipGetLastError();
+          continue;
+        }
+        float ms = 1e30f;
+        for (int r = 0; r < kTuneReps && st == TB_OK; ++r) {
+          check(hipEventRecord(e0, stream), "hipEventRecord");
+          st = st == TB_OK ? steps[i].run(c) : st;
+          check(hipEventRecord(e1, stream), "hipEventRecord");
+          check(hipEventSynchronize(e1), "hipEventSynchronize");
+          float t = 0.f;
+          check(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+          ms = std::min(ms, t);
+        }
+        ++*trials;
+        if (ms < best_ms) {
+          best_ms = ms;
+          pick = c;
+        }
+      }
+      if (st == TB_OK && best_ms >= 1e29f) st = fail(TB_ERR_UNSUPPORTED, "no launch configuration fits");
+      (*best)[dir * steps_per_direction(p) + i] = pick;
+    }
+  }
+  p.timing = was_timing;
+  if (st == TB_OK) check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  release();
+  return st;
+}
+
+tb_status run_autotune(Plan& p, long long nrhs, tb_dtype io, const char* cache, hipStream_t stream,
+                       int* trials) {
+  if (nrhs < 1 || nrhs > (1 << 20)) return fail(TB_ERR_INVALID_ARG, "nrhs must be in [1, 2^20]");
+  if (io < TB_C128 || io > TB_CBF16) return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
+  if (!p.cores[io]) return fail(TB_ERR_INVALID_ARG, "the plan holds no cores of the requested precision");
+  int count = 0;
+  const uint64_t sig = plan_signature(p);
+  const size_t nslots = 2 * (size_t)steps_per_direction(p);
+  std::vector<LaunchCfg> best;
+  if (!(cache && read_cache(cache, sig, io, nrhs, nslots, &best))) {
+    tb_status st = TB_OK;
+    switch (io) {
+      case TB_C128: st = tune_typed<double, double2>(p, io, nrhs, stream, &best, &count); break;
+      case TB_C64: st = tune_typed<float, float2>(p, io, nrhs, stream, &best, &count); break;
+      case TB_CBF16: st = tune_typed<float, unsigned>(p, io, nrhs, stream, &best, &count); break;
+    }
+    TB_TRY(st);
+    if (cache) append_cache(cache, sig, io, nrhs, best);
+  }
+  drop_graphs_for(&p);  // captured graphs hold the previous configurations
+  p.tuned[{(int)io, nrhs}] = best;
+  if (trials) *trials = count;
+  return TB_OK;
 }
 
 tb_status prepare_workspace(Plan& p, long long nrhs, tb_dtype io) {
@@ -1507,6 +2177,39 @@ extern "C" tb_status tb_apply_batched(int nplans, const tb_plan* plans, const vo
 }
 
 extern "C" tb_status tb_batched_reset(void) { return tb::batched_reset(); }
+
+extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io, int slot,
+                                        const tb_launch_cfg* cfg) {
+  tb::Plan* p = reinterpret_cast<tb::Plan*>(ph);
+  if (!p || !cfg) return tb::fail(TB_ERR_INVALID_ARG, "null plan or configuration");
+  if (nrhs < 1 || nrhs > (1 << 20)) return tb::fail(TB_ERR_INVALID_ARG, "nrhs must be in [1, 2^20]");
+  if (io < TB_C128 || io > TB_CBF16) return tb::fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
+  const int nslots = 2 * tb::steps_per_direction(*p);
+  if (slot < 0 || slot >= nslots) return tb::fail(TB_ERR_INVALID_ARG, "launch slot out of range");
+  const int g = cfg->outputs_per_thread, q = cfg->rhs_tile;
+  if (!(g == 0 || g == 1 || g == 8) || !(q == 0 || q == 1 || q == 2 || q == 4 || q == 8) ||
+      cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 3 ||
+      cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 1)
+    return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");
+  auto& v = p->tuned[{(int)io, nrhs}];
+  if ((int)v.size() != nslots) v.assign(nslots, tb::LaunchCfg{});
+  tb::LaunchCfg c;
+  c.G = g;
+  c.QT = q;
+  c.split = cfg->whole_blocks;
+  c.core = cfg->core_kernel;
+  c.alt = cfg->fanin_in_turn;
+  v[slot] = c;
+  tb::drop_graphs_for(p);
+  return TB_OK;
+}
+
+extern "C" tb_status tb_plan_autotune(tb_plan ph, long long nrhs, tb_dtype io, const char* cache_path,
+                                      void* hip_stream, int* trials) {
+  tb::Plan* p = reinterpret_cast<tb::Plan*>(ph);
+  if (!p) return tb::fail(TB_ERR_INVALID_ARG, "null plan");
+  return tb::run_autotune(*p, nrhs, io, cache_path, static_cast<hipStream_t>(hip_stream), trials);
+}
 
 extern "C" tb_status tb_apply(tb_plan ph, const void* f, void* u, long long nrhs, tb_dtype io,
                               void* hip_stream) {

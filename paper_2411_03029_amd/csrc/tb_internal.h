@@ -6,7 +6,9 @@
 
 #include <complex>
 #include <cstdint>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "tb.h"
@@ -89,6 +91,15 @@ struct Workspace {
   size_t bytes = 0;
 };
 
+// Launch configuration of one apply kernel (0 = the built-in heuristic).
+struct LaunchCfg {
+  int G = 0;      // transfer: outputs per thread along the new mode (1 or 8)
+  int QT = 0;     // transfer: right-hand sides per workgroup (1, 2, 4, 8)
+  int split = 0;  // transfer: 1 = one workgroup per block (no slicing)
+  int core = 0;   // core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = MFMA
+  int alt = 0;    // fan-in: 1 = children in turn, mode 0 in registers
+};
+
 struct Plan {
   int kind = 0, d = 0, leaf = 8, L = 0, Lt = 0, Ls = 0;
   long long n = 0;
@@ -127,6 +138,9 @@ struct Plan {
   std::vector<void*> allocations;
   bool timing = false;
   std::vector<StageEvent> events;
+  // autotuned launch configurations per (tb_dtype, nrhs): one entry per
+  // kernel launch of the forward sequence followed by the adjoint one
+  std::map<std::pair<int, long long>, std::vector<LaunchCfg>> tuned;
 
   ~Plan();
 };
@@ -143,6 +157,8 @@ tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs,
                     tb_dtype io, bool adjoint, hipStream_t stream);
 tb_status run_construct_ids(Plan& p, hipStream_t stream);
 tb_status prepare_workspace(Plan& p, long long nrhs, tb_dtype io);
+tb_status run_autotune(Plan& p, long long nrhs, tb_dtype io, const char* cache, hipStream_t stream,
+                       int* trials);
 void drop_graphs_for(const Plan* p);
 
 inline int ipow2(int e) { return 1 << e; }
