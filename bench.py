@@ -1,18 +1,30 @@
 """Benchmark: tensor butterfly apply throughput on one MI355X.
 
-Workload (default): the 3-D Helmholtz Green's function between two unit cubes
-whose centres are 2 apart along x1, n = 64 per direction (262144 points per
-cube), 4 points per wavelength (omega = pi n / 2), requested accuracy 1e-4,
-one complex N(0,1) right-hand side.  One step = tb_apply + tb_apply_adjoint
-in complex FP32 with FP32 accumulation, on a plan built on the GPU.
+Workloads (``--workload``):
 
-Printed (one JSON line): n^d * nrhs points per second of forward + adjoint,
-the same for the plain FP64 apply of the same plan (one RHS per call, no
-batching), the relative errors of both against the exact operator, the
-roofline of the dominant kernel (the core contraction) and the CPU oracle's
-throughput on the host cores.
+helmholtz_cubes_n64 (default)
+    The 3-D Helmholtz Green's function between two unit cubes whose centres
+    are 2 apart along x1, n = 64 per direction (262144 points per cube), 4
+    points per wavelength (omega = pi n / 2), requested accuracy 1e-4, one
+    complex N(0,1) right-hand side.  One step = tb_apply + tb_apply_adjoint in
+    complex FP32 with FP32 accumulation, on a plan built and autotuned on the
+    GPU.  Also printed: the plain FP64 apply of the same plan, the errors of
+    both against the exact operator, the roofline of the dominant kernel (the
+    core contraction, HBM-bound) and the CPU oracle on the host cores.
+uneven_mix_bf16
+    Eight 2-D Fourier operators (n in {64, 128, 256}, accuracy 1e-6) and four
+    Helmholtz cube operators (n in {32, 64}, 1e-4), each with a seeded number
+    of right-hand sides in [16, 128]; one step = tb_apply_batched forward +
+    adjoint (one HIP graph each) with BF16 cores, beside FP32 and FP64 runs of
+    the same plans; matrix-core utilisation of the core contractions.
+helmholtz_cubes_n128_lsq
+    Helmholtz cubes at n = 128 (2097152 points per cube), 64 right-hand
+    sides; one step of gradient descent on ||K f - b||^2 with b = K f_true +
+    noise, f_true sums of Gaussian bumps (r = K f - b, g = K^H r, f -= eta g).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Each run prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -32,12 +44,6 @@ METRIC = ("tb_apply n^d·RHS points/s (fwd+adjoint) vs FP64 plain apply at "
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "core_fwd_helmholtz_n64_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2411_03029_amd", "csrc", "apply.hip")
-
-WORKLOADS = {
-    # name: (kind, d, n, tol, nrhs)
-    "helmholtz_cubes_n64": ("helmholtz", 3, 64, 1e-4, 1),
-}
-
 
 def kernel_hash() -> str:
     with open(KERNEL_SOURCE, "rb") as fh:
@@ -181,44 +187,57 @@ def summarize(trace_dir, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, c
     return 0
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="helmholtz_cubes_n64", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
-                    help="only run a plain device copy of BYTES (counter calibration)")
-    ap.add_argument("--summarize", nargs=5, metavar="DIR",
-                    help="write profiles/ from rocprofv3 CSV dirs: trace fetch write "
-                         "copy_fetch copy_write")
-    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
-    ap.add_argument("--commands-json", default="{}")
-    args = ap.parse_args()
-    if args.calibrate_copy:
-        return calibrate_copy(args.calibrate_copy)
-    if args.summarize:
-        return summarize(*args.summarize, args.copy_bytes, args.workload,
-                         json.loads(args.commands_json))
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
-        return 2
+def _stage_ms(plan) -> dict:
+    return {k: (ms, c) for k, (ms, c) in plan.stage_times().items() if c}
 
+
+def _stage_flops(info, stage: str, nrhs: int) -> float:
+    """Algorithmic flops of one stage family (8 real flops per complex
+    multiply-add, oracle mode order, true ranks) for nrhs right-hand sides."""
+    fwd = {"src_leaf": 0, "src_transfer": 1, "core": 2, "tgt_transfer": 3, "tgt_leaf": 4}
+    mirror = {"tgt_leaf_adj": "src_leaf", "tgt_transfer_adj": "src_transfer",
+              "core_adj": "core", "src_transfer_adj": "tgt_transfer",
+              "src_leaf_adj": "tgt_leaf"}
+    key = mirror.get(stage, stage)
+    return 8.0 * info["stage_cmacs"][fwd[key]] * nrhs
+
+
+def _relerr(a, b) -> float:
     import numpy as np
-    import torch
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
-    import paper_2411_03029_amd as tb
-    from paper_2411_03029_amd import inputs
 
-    kind, d, n, tol, nrhs = WORKLOADS[args.workload]
-    torch.cuda.set_device(0)
+def _exact_op(kind, d, n):
+    from oracle import kernels
+    kid = {"fourier": kernels.FOURIER, "helmholtz": kernels.HELMHOLTZ,
+           "radon": kernels.RADON}[kind]
+    om = kernels.helmholtz_omega(n) if kid == kernels.HELMHOLTZ else 0.0
+    return kernels.Operator(kid, d, n, omega=om)
+
+
+def _line(args, metric, value, unit, ms_per_step, dtype, config, **extra) -> dict:
+    line = {
+        "metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": config,
+    }
+    line.update(extra)
+    return line
+
+
+def run_single(args, tb, inputs, torch, np) -> dict:
+    """Helmholtz cubes n = 64, one right-hand side (the default workload)."""
+    kind, d, n, tol, nrhs = "helmholtz", 3, 64, 1e-4, 1
     t0 = time.perf_counter()
     plan = tb.construct(kind, d, n, tol, store=("c64", "c128"))
     torch.cuda.synchronize()
     construct_s = time.perf_counter() - t0
     info = plan.info()
+    t0 = time.perf_counter()
+    for dt in ("c64", "c128"):
+        plan.autotune(nrhs, dtype=dt)
+    autotune_s = time.perf_counter() - t0
 
     f_host = inputs.rhs_batch(n, d, nrhs, config=2)
     x64 = torch.from_numpy(f_host).to("cuda")
@@ -275,37 +294,275 @@ def main() -> int:
     if not args.no_cpu_baseline:
         cpu_base, errors = cpu_baseline_leg(kind, d, n, tol, f_host, gpu_out)
 
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "points/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1000 * t32 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "operator": kind, "d": d, "n": n,
-                   "tol": tol, "nrhs": nrhs, "apply": "complex FP32, FP32 accumulation",
-                   "step": "tb_apply + tb_apply_adjoint"},
-        "fp64_plain": {"value": value64, "ms_per_step": 1000 * t64 / args.steps},
-        "speedup_vs_fp64_plain": value / value64,
-        "accuracy": errors,
-        "accuracy_gate_1e-4": (None if errors is None else
-                               all(e["fwd"] <= 1e-4 and e["adj"] <= 1e-4 for e in errors.values())),
-        "roofline": roofline,
-        "stage_avg_us": stage_us,
-        "cpu_baseline": cpu_base,
-        "construct_s": round(construct_s, 3),
-        "plan": {k: info[k] for k in ("L", "Lt", "Ls", "r_min", "r_max", "n_ids", "n_pairs",
-                                      "core_entries", "factor_entries", "apply_cmacs",
-                                      "eps_id")},
+    return _line(
+        args, METRIC, value, "points/s", 1000 * t32 / args.steps, "f32",
+        {"workload": args.workload, "operator": kind, "d": d, "n": n, "tol": tol, "nrhs": nrhs,
+         "apply": "complex FP32, FP32 accumulation", "step": "tb_apply + tb_apply_adjoint"},
+        fp64_plain={"value": value64, "ms_per_step": 1000 * t64 / args.steps},
+        speedup_vs_fp64_plain=value / value64,
+        accuracy=errors,
+        **{"accuracy_gate_1e-4": (None if errors is None else
+                                  all(e["fwd"] <= 1e-4 and e["adj"] <= 1e-4
+                                      for e in errors.values()))},
+        roofline=roofline, stage_avg_us=stage_us, cpu_baseline=cpu_base,
+        construct_s=round(construct_s, 3), autotune_s=round(autotune_s, 3),
+        plan={k: info[k] for k in ("L", "Lt", "Ls", "r_min", "r_max", "n_ids", "n_pairs",
+                                   "core_entries", "factor_entries", "apply_cmacs", "eps_id")})
+
+
+MIX = ([("fourier", 2, n, 1e-6) for n in (64, 128, 256, 64, 128, 256, 64, 128)] +
+       [("helmholtz", 3, n, 1e-4) for n in (32, 64, 32, 64)])
+
+
+def run_mix(args, tb, inputs, torch, np) -> dict:
+    """Uneven multi-operator mix: 8 Fourier (d = 2) and 4 Helmholtz (d = 3)
+    operators with 16..128 right-hand sides each, one HIP graph per
+    direction (tb_apply_batched), BF16 cores with FP32 accumulation."""
+    from oracle import dense
+    counts = [int(c) for c in inputs.uneven_rhs_counts(len(MIX))]
+    t0 = time.perf_counter()
+    plans = [tb.construct(k, d, n, tol, store=("cbf16", "c64", "c128")) for k, d, n, tol in MIX]
+    torch.cuda.synchronize()
+    construct_s = time.perf_counter() - t0
+    infos = [p.info() for p in plans]
+    t0 = time.perf_counter()
+    for p, m in zip(plans, counts):
+        for dt in ("cbf16", "c64", "c128"):
+            p.autotune(m, dtype=dt)
+    autotune_s = time.perf_counter() - t0
+    f_host = [inputs.rhs_batch(n, d, m, config=40 + i) for i, ((_, d, n, _), m) in
+              enumerate(zip(MIX, counts))]
+    points = sum(m * n ** d for (_, d, n, _), m in zip(MIX, counts))
+
+    def buffers(cdt):
+        xs = [torch.from_numpy(f).to("cuda", cdt) for f in f_host]
+        return xs, [torch.empty_like(x) for x in xs], [torch.empty_like(x) for x in xs]
+
+    def timed(dt, cdt, steps, warmup):
+        xs, us, vs = buffers(cdt)
+        for _ in range(max(warmup, 1)):
+            tb.apply_batched(plans, xs, us, dtype=dt)
+            tb.apply_batched(plans, us, vs, adjoint=True, dtype=dt)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            tb.apply_batched(plans, xs, us, dtype=dt)
+            tb.apply_batched(plans, us, vs, adjoint=True, dtype=dt)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, xs, us
+
+    t_bf, _, _ = timed("cbf16", torch.complex64, args.steps, args.warmup)
+    t_32, _, _ = timed("c64", torch.complex64, args.steps, args.warmup)
+    t_64, _, _ = timed("c128", torch.complex128, max(1, args.steps // 4), args.warmup)
+    s64 = max(1, args.steps // 4)
+
+    # accuracy against the exact operators on the first and last right-hand sides
+    acc = {}
+    for dt, cdt in (("cbf16", torch.complex64), ("c64", torch.complex64)):
+        xs = [torch.from_numpy(f).to("cuda", cdt) for f in f_host]
+        us = tb.apply_batched(plans, xs, dtype=dt)
+        vs = tb.apply_batched(plans, xs, adjoint=True, dtype=dt)
+        torch.cuda.synchronize()
+        worst_f = worst_a = 0.0
+        for i, (k, d, n, _) in enumerate(MIX):
+            sel = [0, counts[i] - 1]
+            op = _exact_op(k, d, n)
+            u = us[i].cpu().numpy().astype(np.complex128)[sel]
+            v = vs[i].cpu().numpy().astype(np.complex128)[sel]
+            worst_f = max(worst_f, _relerr(u, dense.apply_exact(op, f_host[i][sel])))
+            worst_a = max(worst_a, _relerr(v, dense.adjoint_exact(op, f_host[i][sel])))
+        acc[dt] = {"fwd_max": worst_f, "adj_max": worst_a}
+
+    # per-kernel times from HIP events on single-plan applies of the same
+    # (tuned) launches; matrix-core utilisation of the core contractions
+    xs, us, vs = buffers(torch.complex64)
+    fam = {}
+    core_flops = core_ms = 0.0
+    for p, info, x, u, v, m in zip(plans, infos, xs, us, vs, counts):
+        p.set_timing(True)
+        p.apply(x, out=u, dtype="cbf16")
+        p.apply_adjoint(u, out=v, dtype="cbf16")
+        torch.cuda.synchronize()
+        for st, (ms, c) in _stage_ms(p).items():
+            f = _stage_flops(info, st, m)
+            a = fam.setdefault(st, [0.0, 0.0, 0])
+            a[0] += ms
+            a[1] += f
+            a[2] += c
+            if st in ("core", "core_adj"):
+                core_flops += f
+                core_ms += ms
+        p.set_timing(False)
+    core_tf = core_flops / (core_ms * 1e-3) / 1e12
+    mfma_peak = 157.3
+    roofline = {
+        "bound": "mfma", "achieved": round(core_tf, 2), "peak": mfma_peak, "unit": "TFLOP/s",
+        "frac": round(core_tf / mfma_peak, 4), "traffic": None,
+        "kernel": "core_fwd_mfma + core_adj_mfma (BF16 cores widened to FP32, "
+                  "v_mfma_f32_16x16x4f32, complex as four real products)",
+        "flops_per_step": core_flops, "ms_per_step_events": round(core_ms, 3),
     }
+    stage_ms = {k: {"ms": round(v[0], 3), "launches": v[2],
+                    "TFLOP/s": round(v[1] / (v[0] * 1e-3) / 1e12, 2)} for k, v in fam.items()}
+    return _line(
+        args, "tb_apply_batched n^d·RHS points/s (fwd+adjoint), uneven multi-operator mix",
+        points * args.steps / t_bf, "points/s", 1000 * t_bf / args.steps, "bf16",
+        {"workload": args.workload, "operators": [f"{k} d={d} n={n} tol={t}" for k, d, n, t in MIX],
+         "nrhs": counts, "apply": "BF16 cores, FP32 inputs and accumulation",
+         "step": "tb_apply_batched forward + adjoint (one HIP graph each)"},
+        fp32={"value": points * args.steps / t_32, "ms_per_step": 1000 * t_32 / args.steps},
+        fp64={"value": points * s64 / t_64, "ms_per_step": 1000 * t_64 / s64},
+        accuracy=acc, roofline=roofline, stage_ms_per_step=stage_ms,
+        construct_s=round(construct_s, 3), autotune_s=round(autotune_s, 3), cpu_baseline=None)
+
+
+def _bumps_on_device(n, seeds, torch):
+    """inputs.gaussian_bumps evaluated on the GPU (same random draws)."""
+    import numpy as np
+    g = torch.arange(n, device="cuda", dtype=torch.float64) / n
+    X, Y, Z = torch.meshgrid(g, g, g, indexing="ij")
+    out = torch.zeros((len(seeds), n, n, n), dtype=torch.complex128, device="cuda")
+    for q, seed in enumerate(seeds):
+        rng = np.random.default_rng(seed)
+        c = rng.random((16, 3))
+        sig = rng.uniform(0.05, 0.2, 16)
+        amp = (rng.standard_normal(16) + 1j * rng.standard_normal(16)) / np.sqrt(2)
+        for m in range(16):
+            r2 = (X - c[m, 0]) ** 2 + (Y - c[m, 1]) ** 2 + (Z - c[m, 2]) ** 2
+            out[q] += complex(amp[m]) * torch.exp(-r2 / (2 * sig[m] ** 2))
+    return out
+
+
+def run_lsq(args, tb, inputs, torch, np) -> dict:
+    """Least squares with the Helmholtz cubes at n = 128 and 64 right-hand
+    sides: one step = r = K f - b, g = K^H r, f -= eta g (FP32)."""
+    from oracle import dense
+    kind, d, n, tol, nrhs = "helmholtz", 3, 128, 1e-4, 64
+    t0 = time.perf_counter()
+    plan = tb.construct(kind, d, n, tol, store=("c64",))
+    torch.cuda.synchronize()
+    construct_s = time.perf_counter() - t0
+    info = plan.info()
+    t0 = time.perf_counter()
+    plan.autotune(nrhs, dtype="c64")
+    autotune_s = time.perf_counter() - t0
+    ftrue = _bumps_on_device(n, [5000 + q for q in range(nrhs)], torch)
+    b = plan.apply(ftrue.to(torch.complex64))
+    noise = torch.from_numpy(inputs.complex_normal(tuple(b.shape), 55) / np.sqrt(2)).to("cuda", b.dtype)
+    b = b + 1e-3 * b.abs().mean() * noise
+    # step size from the operator norm (power iteration on K^H K)
+    x = torch.ones_like(b)
+    for _ in range(8):
+        x = plan.apply_adjoint(plan.apply(x))
+        x = x / x.abs().norm()
+    eta = 0.5 / float(plan.apply(x).abs().norm() ** 2 / x.abs().norm() ** 2)
+    f = torch.zeros_like(b)
+    r = torch.empty_like(b)
+    g = torch.empty_like(b)
+
+    def step():
+        plan.apply(f, out=r)
+        r.sub_(b)
+        plan.apply_adjoint(r, out=g)
+        f.sub_(eta * g)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    loss0 = float((plan.apply(f) - b).abs().pow(2).sum())
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t
+    loss1 = float((plan.apply(f) - b).abs().pow(2).sum())
+
+    # accuracy of K f_true against the exact operator (FFT convolution), 2 RHS
+    sel = [0, nrhs - 1]
+    op = _exact_op(kind, d, n)
+    ft = ftrue[sel].cpu().numpy()
+    u = plan.apply(ftrue[sel].to(torch.complex64)).cpu().numpy().astype(np.complex128)
+    v = plan.apply_adjoint(ftrue[sel].to(torch.complex64)).cpu().numpy().astype(np.complex128)
+    acc = {"c64": {"fwd": _relerr(u, dense.apply_exact(op, ft)),
+                   "adj": _relerr(v, dense.adjoint_exact(op, ft))}}
+
+    # kernel times (HIP events) of one step's applies
+    plan.set_timing(True)
+    plan.apply(f, out=r)
+    plan.apply_adjoint(r, out=g)
+    torch.cuda.synchronize()
+    st = _stage_ms(plan)
+    plan.set_timing(False)
+    per = {k: {"ms": round(ms, 3), "launches": c,
+               "TFLOP/s": round(_stage_flops(info, k, nrhs) / (ms * 1e-3) / 1e12, 2)}
+           for k, (ms, c) in st.items()}
+    core_flops = _stage_flops(info, "core", nrhs) + _stage_flops(info, "core_adj", nrhs)
+    core_ms = st["core"][0] + st["core_adj"][0]
+    core_tf = core_flops / (core_ms * 1e-3) / 1e12
+    dom = max(st, key=lambda k: st[k][0])
+    dom_tf = _stage_flops(info, dom, nrhs) / (st[dom][0] * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu" if "core" not in dom else "mfma",
+        "achieved": round(dom_tf, 2), "peak": 157.3, "unit": "TFLOP/s",
+        "frac": round(dom_tf / 157.3, 4), "traffic": None,
+        "kernel": f"{dom} (largest share of the step)",
+        "core_mfma_TFLOPs": round(core_tf, 2), "core_mfma_frac": round(core_tf / 157.3, 4),
+    }
+    return _line(
+        args, "least-squares gradient steps, n^d·RHS points/s (K f - b, K^H r)",
+        nrhs * n ** d * args.steps / t, "points/s", 1000 * t / args.steps, "f32",
+        {"workload": args.workload, "operator": kind, "d": d, "n": n, "tol": tol, "nrhs": nrhs,
+         "apply": "complex FP32, FP32 accumulation",
+         "step": "tb_apply + tb_apply_adjoint + two axpys"},
+        loss={"before": loss0, "after": loss1}, accuracy=acc, roofline=roofline,
+        stage_ms_per_step=per, construct_s=round(construct_s, 3),
+        autotune_s=round(autotune_s, 3), cpu_baseline=None,
+        plan={k: info[k] for k in ("L", "Lt", "Ls", "r_min", "r_max", "n_ids", "n_pairs",
+                                   "core_entries", "factor_entries", "apply_cmacs", "eps_id")})
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="helmholtz_cubes_n64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--summarize", nargs=5, metavar="DIR",
+                    help="write profiles/ from rocprofv3 CSV dirs: trace fetch write "
+                         "copy_fetch copy_write")
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--commands-json", default="{}")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        return calibrate_copy(args.calibrate_copy)
+    if args.summarize:
+        return summarize(*args.summarize, args.copy_bytes, args.workload,
+                         json.loads(args.commands_json))
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path, "
+              "run it with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2411_03029_amd as tb
+    from paper_2411_03029_amd import inputs
+
+    torch.cuda.set_device(0)
+    line = WORKLOADS[args.workload](args, tb, inputs, torch, np)
     print(json.dumps(line), flush=True)
     return 0
+
+
+WORKLOADS = {
+    "helmholtz_cubes_n64": run_single,
+    "uneven_mix_bf16": run_mix,
+    "helmholtz_cubes_n128_lsq": run_lsq,
+}
 
 
 if __name__ == "__main__":

@@ -113,6 +113,10 @@ typedef struct {
   unsigned store_mask;
   size_t device_bytes;        /* factor + core memory held by the plan      */
   double construct_ms;        /* wall time of tb_construct (0 after load)   */
+  long long stage_cmacs[5];   /* apply_cmacs split by forward stage: source
+                                 leaf, source transfers (all levels), core,
+                                 target transfers, target leaf; the adjoint
+                                 stage mirroring each has the same count    */
 } tb_plan_info_t;
 
 /* Build the factorisation on the GPU (Algorithm 1).

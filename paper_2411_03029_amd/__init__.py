@@ -84,7 +84,9 @@ class Plan:
     def info(self) -> dict:
         info = _lib.TbPlanInfo()
         _lib.check(_lib.load().tb_plan_info(self._h, ctypes.byref(info)))
-        return {name: getattr(info, name) for name, _ in info._fields_}
+        out = {name: getattr(info, name) for name, _ in info._fields_}
+        out["stage_cmacs"] = list(out["stage_cmacs"])
+        return out
 
     @property
     def n(self) -> int:

@@ -214,14 +214,17 @@ tb_status finalize_plan(Plan& p, hipStream_t stream) {
   return TB_OK;
 }
 
-long long apply_cmacs(const Plan& p) {
+long long apply_cmacs(const Plan& p, long long* per_stage) {
   // exact complex multiply-adds of one apply per RHS, from true ranks and
-  // the mode-by-mode order used by the oracle (modes 0..d-1)
+  // the mode-by-mode order used by the oracle (modes 0..d-1); per_stage
+  // (5 entries, nullable) receives the split by forward stage
   const int d = p.d;
   long long total = 0;
+  long long split[5] = {0, 0, 0, 0, 0};
   auto side = [&](const std::vector<Level>& lv, bool source) {
     for (size_t l = 0; l < lv.size(); ++l) {
       const Level& L = lv[l];
+      const long long before = total;
       for (int it = 0; it < L.nitems; ++it) {
         long long in_len[kMaxD], out_len[kMaxD];
         for (int k = 0; k < d; ++k) {
@@ -248,13 +251,19 @@ long long apply_cmacs(const Plan& p) {
           cur[k] = source ? out_len[k] : in_len[k];
         }
       }
+      const int slot = source ? (l == 0 ? 0 : 1) : (l == 0 ? 4 : 3);
+      split[slot] += total - before;
     }
   };
   side(p.src, true);
   side(p.tgt, false);
+  const long long before_core = total;
   for (long long pr = 0; pr < p.npairs; ++pr)
     total += (long long)p.pair_meta[(size_t)pr * kPairMeta] *
              p.pair_meta[(size_t)pr * kPairMeta + 1];
+  split[2] = total - before_core;
+  if (per_stage)
+    for (int i = 0; i < 5; ++i) per_stage[i] = split[i];
   return total;
 }
 
@@ -371,7 +380,7 @@ extern "C" tb_status tb_plan_info(tb_plan ph, tb_plan_info_t* info) {
     info->core_rows += p.pair_meta[(size_t)pr * kPairMeta];
     info->core_cols += p.pair_meta[(size_t)pr * kPairMeta + 1];
   }
-  info->apply_cmacs = apply_cmacs(p);
+  info->apply_cmacs = apply_cmacs(p, info->stage_cmacs);
   info->omega = p.omega;
   info->tol = p.tol;
   info->eps_id = p.eps_id;

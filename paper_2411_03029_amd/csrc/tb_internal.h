@@ -149,7 +149,7 @@ struct Plan {
 tb_status dev_alloc(Plan& p, void** ptr, size_t bytes);
 tb_status finalize_plan(Plan& p, hipStream_t stream);  // pads + uploads factors
 tb_status build_core_tables(Plan& p);
-long long apply_cmacs(const Plan& p);
+long long apply_cmacs(const Plan& p, long long* per_stage = nullptr);
 
 // kernels launched by host code
 tb_status launch_core_eval(Plan& p, hipStream_t stream, const double2* host_cores);

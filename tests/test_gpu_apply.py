@@ -163,3 +163,14 @@ def test_batched_rhs_matrix_cores(name, nrhs, tmp_path):
         for q in range(nrhs):
             assert relerr(u[q], ue[q]) <= tol, (dt, q, relerr(u[q], ue[q]))
             assert relerr(v[q], ve[q]) <= tol, (dt, q, relerr(v[q], ve[q]))
+
+
+def test_stage_multiply_add_split(tmp_path):
+    # the per-stage split of the multiply-add count adds up, and the core
+    # share is the sum of R_T R_S over the pairs, i.e. the core entries
+    torch_gpu()
+    for name in ("helm3_n32", "radon2_n32"):
+        info = gpu_plan(name, tmp_path).info()
+        assert sum(info["stage_cmacs"]) == info["apply_cmacs"]
+        assert info["stage_cmacs"][2] == info["core_entries"]
+        assert min(info["stage_cmacs"]) > 0
