@@ -191,6 +191,8 @@ typedef struct {
   int whole_blocks;       /* transfer stages: 1 = one workgroup per block (no slices) */
   int core_kernel;        /* core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = matrix cores */
   int fanin_in_turn;      /* fan-in stages: 1 = children in turn, first mode in registers */
+  int transfer_mfma;      /* transfer levels (not the leaves), FP32 / BF16 applies: 1 = mode
+                             products on the matrix cores, one block per workgroup */
 } tb_launch_cfg;
 
 /* Set the configuration of launch `slot` for applies of p with exactly this

@@ -1307,6 +1307,368 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// ----------------------------------------------- MFMA transfer stages --
+// A mode product of a transfer block, out[a][col] = sum_j M[a][j] in[j][col]
+// (complex; a < nA new-mode entries, j < K contracted entries, col over the
+// other modes and the right-hand sides), as one real product on
+// v_mfma_f32_16x16x4f32: with the real index k = 2 j + p (p = 0 real part,
+// 1 imaginary part) the A fragment holds
+//   rows 0..7  (real parts of outputs a):      Mr[a][j] (p = 0), -Mi[a][j] (p = 1)
+//   rows 8..15 (imaginary parts of the same a): Mi[a][j] (p = 0),  Mr[a][j] (p = 1)
+// and the B fragment the parts p of in[j][col] (b(j, col, p) returns it).  Lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register i of lane l
+// is D[4 (l / 16) + i][l % 16].  A row tile covers 8 outputs, a column tile
+// 16 columns; kXT column tiles share each A fragment.
+constexpr int kXT = 4;       // column tiles per pass
+constexpr int kXItems = 4;   // persistent (row tile, column group) items per wave
+
+// B element (j, col, part p) = src[colofs(col) + jofs(j) + p] (float
+// offsets; colofs < 0 marks a zero column, e.g. a right-hand side past the
+// end): the column part is computed once per tile, the j part once per step.
+template <class MF, class T, class CF, class JF>
+__device__ __forceinline__ void xmfma(v4f (&acc)[kXT], int rt, int ct0, int K, int nA, int ncols, MF m,
+                                      const T* __restrict__ src, CF colofs, JF jofs) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, kk = lane >> 4, p = kk & 1;
+  const int a = rt * 8 + (r & 7);
+  const bool im_row = r >= 8;
+  long long co[kXT];
+#pragma unroll
+  for (int t = 0; t < kXT; ++t) {
+    const int col = (ct0 + t) * 16 + r;
+    co[t] = col < ncols ? colofs(col) : -1;
+  }
+  const int nks = (K + 1) >> 1;
+  for (int ks = 0; ks < nks; ++ks) {
+    const int j = 2 * ks + (kk >> 1);
+    const bool jv = j < K;
+    float av = 0.f;
+    long long jo = 0;
+    if (jv) {
+      jo = jofs(j) + p;
+      if (a < nA) {
+        const float2 mv = m(a, j);
+        av = im_row ? (p ? mv.x : mv.y) : (p ? -mv.y : mv.x);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kXT; ++t) {
+      const float bv = (jv && co[t] >= 0) ? src[co[t] + jo] : 0.f;
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+    }
+  }
+}
+
+// w(a, col, part, value) for every valid output of the tiles in acc
+template <class WF>
+__device__ __forceinline__ void xstore(const v4f (&acc)[kXT], int rt, int ct0, int nA, int ncols, WF w) {
+  const int lane = threadIdx.x & 63;
+  const int kk = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int t = 0; t < kXT; ++t) {
+    const int col = (ct0 + t) * 16 + c;
+    if (col >= ncols) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = 4 * kk + i;
+      const int a = rt * 8 + (row & 7);
+      if (a < nA) w(a, col, row >> 3, acc[t][i]);
+    }
+  }
+}
+
+__device__ __forceinline__ void xzero(v4f (&acc)[kXT]) {
+#pragma unroll
+  for (int t = 0; t < kXT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+}
+
+// all (row tile, column group) items of a product, spread over the waves
+template <class MF, class T, class CF, class JF, class WF>
+__device__ __forceinline__ void xproduct(int K, int nA, int ncols, MF m, const T* src, CF colofs, JF jofs,
+                                         WF w) {
+  const int wave = threadIdx.x >> 6;
+  const int nrt = (nA + 7) >> 3;
+  const int ngrp = ((ncols + 15) / 16 + kXT - 1) / kXT;
+  for (int it = wave; it < nrt * ngrp; it += kThreads / 64) {
+    const int rt = it % nrt, ct0 = (it / nrt) * kXT;
+    v4f acc[kXT];
+    xzero(acc);
+    xmfma(acc, rt, ct0, K, nA, ncols, m, src, colofs, jofs);
+    xstore(acc, rt, ct0, nA, ncols, w);
+  }
+}
+
+// Fan-out (transfer levels: the coarse side is a workspace tensor with the
+// right-hand side innermost) on the matrix cores, one block per workgroup.
+// Columns of each product: the not-yet-contracted modes, then q fastest.
+template <int D, int QT>
+__global__ void __launch_bounds__(kThreads)
+    stage_fanout_mfma(StageArgs a, const float2* __restrict__ coarse, float2* __restrict__ fine,
+                      const float2* __restrict__ mats) {
+  extern __shared__ unsigned char smem_raw[];
+  float2* sm = reinterpret_cast<float2*>(smem_raw);
+  const StageBid sb = stage_bid(a, QT);
+  const int fi = sb.item_blk / a.nblk;
+  int beta[D];
+  unflatten_blk<D>(sb.item_blk % a.nblk, a.nb, beta);
+  int r[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) r[k] = a.rank_f[((long long)fi * D + k) * a.nb + beta[k]];
+  const int citem = parent_of<D>(fi, a.lvl);
+  Seg sg[D];
+  coarse_segs<D>(a, citem, beta, sg);
+  const int q0 = sb.q0;
+  const int Qa = min(QT, a.nrhs - q0);
+  CoarseAddr<D> ca;
+  ca.init(a, citem, beta, q0);
+  long long fs[D];
+  const long long fb = fine_base<D>(a, fi, beta, q0, fs);
+  const float2* mbase = mats + (long long)fi * a.mat_item_stride;
+  float2* mk[D];
+  int off = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    mk[k] = sm + off;
+    const float2* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
+    const int ck = sg[k].c;
+    for (int i = threadIdx.x; i < r[k] * ck; i += kThreads) {
+      const int row = i / ck, j = i % ck;
+      float2 v = src[row * a.A[k] + sg[k].pos(j)];
+      if (a.conj) v.y = -v.y;
+      mk[k][i] = v;
+    }
+    off += a.R[k] * a.A[k];
+  }
+  float* y1 = reinterpret_cast<float*>(sm + off);
+  const int c0 = sg[0].c, c1 = sg[1].c;
+  __syncthreads();
+  const float* cf = reinterpret_cast<const float*>(coarse);
+  if constexpr (D == 2) {
+    // y1[a0][col], col = j1 QT + q
+    xproduct(
+        c0, r[0], c1 * QT, [&](int a0, int j) { return mk[0][a0 * c0 + j]; }, cf,
+        [&](int col) -> long long {
+          const int q = col % QT, j1 = col / QT;
+          if (q >= Qa) return -1;
+          return 2 * (ca.base + sg[1].pos(j1) * ca.stride[1] + q);
+        },
+        [&](int j) -> long long { return 2 * (sg[0].pos(j) * ca.stride[0]); },
+        [&](int a0, int col, int part, float v) { y1[2 * (a0 * (c1 * QT) + col) + part] = v; });
+    __syncthreads();
+    // fine[a0][a1][q], col = a0 QT + q
+    const int n1 = c1 * QT;
+    xproduct(
+        c1, r[1], r[0] * QT, [&](int a1, int j) { return mk[1][a1 * c1 + j]; }, (const float*)y1,
+        [&](int col) -> long long {
+          const int q = col % QT, a0 = col / QT;
+          return 2 * (a0 * n1 + q);
+        },
+        [&](int j) -> long long { return 2 * (j * QT); },
+        [&](int a1, int col, int part, float v) {
+          const int q = col % QT, a0 = col / QT;
+          if (q < Qa) reinterpret_cast<float*>(fine + fb + a0 * fs[0] + a1 * fs[1] + q)[part] = v;
+        });
+  } else {
+    const int c2 = sg[2].c;
+    const int n1 = c1 * c2 * QT;
+    float* y2 = y1 + 2 * a.R[0] * a.A[1] * a.A[2] * QT;
+    // y1[a0][col], col = (j1 c2 + j2) QT + q
+    xproduct(
+        c0, r[0], n1, [&](int a0, int j) { return mk[0][a0 * c0 + j]; }, cf,
+        [&](int col) -> long long {
+          const int q = col % QT, t = col / QT;
+          if (q >= Qa) return -1;
+          const int j2 = t % c2, j1 = t / c2;
+          return 2 * (ca.base + sg[1].pos(j1) * ca.stride[1] + sg[2].pos(j2) * ca.stride[2] + q);
+        },
+        [&](int j) -> long long { return 2 * (sg[0].pos(j) * ca.stride[0]); },
+        [&](int a0, int col, int part, float v) { y1[2 * (a0 * n1 + col) + part] = v; });
+    __syncthreads();
+    // y2[a0][a1][j2][q] from columns (a0 c2 + j2) QT + q
+    xproduct(
+        c1, r[1], r[0] * c2 * QT, [&](int a1, int j) { return mk[1][a1 * c1 + j]; }, (const float*)y1,
+        [&](int col) -> long long {
+          const int q = col % QT, t = col / QT;
+          const int j2 = t % c2, a0 = t / c2;
+          return 2 * (a0 * n1 + j2 * QT + q);
+        },
+        [&](int j) -> long long { return 2 * (j * c2 * QT); },
+        [&](int a1, int col, int part, float v) {
+          const int q = col % QT, t = col / QT;
+          const int j2 = t % c2, a0 = t / c2;
+          y2[2 * (((a0 * r[1] + a1) * c2 + j2) * QT + q) + part] = v;
+        });
+    __syncthreads();
+    // fine[a0][a1][a2][q] from columns (a0 r1 + a1) QT + q
+    xproduct(
+        c2, r[2], r[0] * r[1] * QT, [&](int a2, int j) { return mk[2][a2 * c2 + j]; }, (const float*)y2,
+        [&](int col) -> long long {
+          const int q = col % QT, t = col / QT;
+          return 2 * (t * c2 * QT + q);
+        },
+        [&](int j) -> long long { return 2 * (j * QT); },
+        [&](int a2, int col, int part, float v) {
+          const int q = col % QT, t = col / QT;
+          const int a1 = t % r[1], a0 = t / r[1];
+          if (q < Qa)
+            reinterpret_cast<float*>(fine + fb + a0 * fs[0] + a1 * fs[1] + a2 * fs[2] + q)[part] = v;
+        });
+  }
+}
+
+// Fan-in (transfer levels) on the matrix cores with the children in turn:
+// per child the modes D-1 .. 1 go through LDS, and the first mode's product
+// accumulates in MFMA registers held across the children; one coarse block
+// per workgroup.
+template <int D, int QT>
+__global__ void __launch_bounds__(kThreads)
+    stage_fanin_mfma(StageArgs a, const float2* __restrict__ fine, float2* __restrict__ coarse,
+                     const float2* __restrict__ mats) {
+  extern __shared__ unsigned char smem_raw[];
+  float2* sm = reinterpret_cast<float2*>(smem_raw);
+  const StageBid sb = stage_bid(a, QT);
+  const int ci = sb.item_blk / a.nblk;
+  int beta[D];
+  unflatten_blk<D>(sb.item_blk % a.nblk, a.nb, beta);
+  Seg sg[D];
+  coarse_segs<D>(a, ci, beta, sg);
+  const int q0 = sb.q0;
+  const int Qa = min(QT, a.nrhs - q0);
+  constexpr int nchild = 1 << D;
+  __shared__ int cfi[kMaxChildren], crk[kMaxChildren][kMaxD];
+  __shared__ long long cfb[kMaxChildren];
+  if (threadIdx.x < nchild) {
+    const int c = threadIdx.x;
+    const int fi = child_of<D>(ci, a.lvl, c);
+    cfi[c] = fi;
+#pragma unroll
+    for (int k = 0; k < D; ++k) crk[c][k] = a.rank_f[((long long)fi * D + k) * a.nb + beta[k]];
+    long long fs_[D];
+    cfb[c] = fine_base<D>(a, fi, beta, q0, fs_);
+  }
+  long long fs[D];
+  (void)fine_base<D>(a, 0, beta, 0, fs);
+  __syncthreads();
+  // every child's matrices, compact: M_k [j][a_k] (r_k x c_k)
+  int msz = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) msz += a.R[k] * a.A[k];
+  for (int c = 0; c < nchild; ++c) {
+    const float2* mbase = mats + (long long)cfi[c] * a.mat_item_stride;
+    int off = c * msz;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const float2* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
+      const int ck = sg[k].c, rk = crk[c][k];
+      for (int i = threadIdx.x; i < rk * ck; i += kThreads) {
+        const int row = i / ck, j = i % ck;
+        float2 v = src[row * a.A[k] + sg[k].pos(j)];
+        if (a.conj) v.y = -v.y;
+        sm[off + i] = v;
+      }
+      off += a.R[k] * a.A[k];
+    }
+  }
+  float* t1 = reinterpret_cast<float*>(sm + nchild * msz);
+  float* t2 = t1 + 2 * a.R[0] * a.R[1] * a.A[D - 1] * QT;
+  const int c0 = sg[0].c, c1 = sg[1].c;
+  const int c2 = D == 3 ? sg[D - 1].c : 1;
+  // output columns: (a1 [, a2]) then q fastest
+  const int ncols = c1 * c2 * QT;
+  const int wave = threadIdx.x >> 6;
+  const int nrt = (c0 + 7) >> 3;
+  const int ngrp = ((ncols + 15) / 16 + kXT - 1) / kXT;
+  const int nitems = nrt * ngrp;
+  v4f acc[kXItems][kXT];
+#pragma unroll
+  for (int i = 0; i < kXItems; ++i) xzero(acc[i]);
+  __syncthreads();
+  for (int c = 0; c < nchild; ++c) {
+    const int r0 = crk[c][0], r1 = crk[c][1];
+    const float2* M0c = sm + c * msz;
+    const float2* M1c = M0c + a.R[0] * a.A[0];
+    const float2* fc = fine + cfb[c];
+    const float* fcf = reinterpret_cast<const float*>(fc);
+    const float* xin;
+    if constexpr (D == 2) {
+      // t1[j0][a1][q] from columns j0 QT + q
+      xproduct(
+          r1, c1, r0 * QT, [&](int a1, int j) { return M1c[j * c1 + a1]; }, fcf,
+          [&](int col) -> long long {
+            const int q = col % QT, j0 = col / QT;
+            if (q >= Qa) return -1;
+            return 2 * (j0 * fs[0] + q);
+          },
+          [&](int j) -> long long { return 2 * (j * fs[1]); },
+          [&](int a1, int col, int part, float v) {
+            const int q = col % QT, j0 = col / QT;
+            t1[2 * ((j0 * c1 + a1) * QT + q) + part] = v;
+          });
+      xin = t1;
+    } else {
+      const int r2 = crk[c][2];
+      const float2* M2c = M1c + a.R[1] * a.A[1];
+      // t1[j0][j1][a2][q] from columns (j0 r1 + j1) QT + q
+      xproduct(
+          r2, c2, r0 * r1 * QT, [&](int a2, int j) { return M2c[j * c2 + a2]; }, fcf,
+          [&](int col) -> long long {
+            const int q = col % QT, t = col / QT;
+            if (q >= Qa) return -1;
+            const int j1 = t % r1, j0 = t / r1;
+            return 2 * (j0 * fs[0] + j1 * fs[1] + q);
+          },
+          [&](int j) -> long long { return 2 * (j * fs[2]); },
+          [&](int a2, int col, int part, float v) {
+            const int q = col % QT, t = col / QT;
+            t1[2 * ((t * c2 + a2) * QT + q) + part] = v;
+          });
+      __syncthreads();
+      // t2[j0][a1][a2][q] from columns (j0 c2 + a2) QT + q
+      xproduct(
+          r1, c1, r0 * c2 * QT, [&](int a1, int j) { return M1c[j * c1 + a1]; }, (const float*)t1,
+          [&](int col) -> long long {
+            const int q = col % QT, t = col / QT;
+            const int a2 = t % c2, j0 = t / c2;
+            return 2 * ((j0 * r1 * c2 + a2) * QT + q);
+          },
+          [&](int j) -> long long { return 2 * (j * c2 * QT); },
+          [&](int a1, int col, int part, float v) {
+            const int q = col % QT, t = col / QT;
+            const int a2 = t % c2, j0 = t / c2;
+            t2[2 * (((j0 * c1 + a1) * c2 + a2) * QT + q) + part] = v;
+          });
+      xin = t2;
+    }
+    __syncthreads();
+    // acc += M0c^T xin: out a0 over columns (a1 [, a2]) QT + q
+#pragma unroll
+    for (int i = 0; i < kXItems; ++i) {
+      const int it = wave + i * (kThreads / 64);
+      if (it < nitems)
+        xmfma(acc[i], it % nrt, (it / nrt) * kXT, r0, c0, ncols,
+              [&](int a0, int j) { return M0c[j * c0 + a0]; }, xin,
+              [&](int col) -> long long { return 2 * col; },
+              [&](int j) -> long long { return 2 * (j * ncols); });
+    }
+    __syncthreads();
+  }
+  CoarseAddr<D> ca;
+  ca.init(a, ci, beta, q0);
+#pragma unroll
+  for (int i = 0; i < kXItems; ++i) {
+    const int it = wave + i * (kThreads / 64);
+    if (it < nitems)
+      xstore(acc[i], it % nrt, (it / nrt) * kXT, c0, ncols, [&](int a0, int col, int part, float v) {
+        const int q = col % QT, t = col / QT;
+        if (q >= Qa) return;
+        long long o = ca.base + sg[0].pos(a0) * ca.stride[0] + q;
+        if (D == 3) o += sg[1].pos(t / c2) * ca.stride[1] + sg[D - 1].pos(t % c2) * ca.stride[D - 1];
+        else o += sg[1].pos(t) * ca.stride[1];
+        reinterpret_cast<float*>(coarse + o)[part] = v;
+      });
+  }
+}
+
 // ------------------------------------------------------------------ host --
 constexpr int kTargetWorkgroups = 2048;  // enough to cover 256 CUs several times
 
@@ -1526,6 +1888,86 @@ static tb_status launch_stage_seq(const Plan& p, StageArgs a, int n_items, const
   return TB_OK;
 }
 
+// LDS elements of the matrix-core transfer kernels (one block, QT
+// right-hand sides; padded extents bound the true ones) and the number of
+// persistent accumulator items of the fan-in.
+static long long xmfma_lds_elems(const StageArgs& a, int d, bool fanout, int QT) {
+  long long msz = 0;
+  for (int k = 0; k < d; ++k) msz += (long long)a.R[k] * a.A[k];
+  if (fanout) {
+    if (d == 2) return msz + (long long)a.R[0] * a.A[1] * QT;
+    return msz + (long long)a.R[0] * a.A[1] * a.A[2] * QT + (long long)a.R[0] * a.R[1] * a.A[2] * QT;
+  }
+  const long long nchild = 1LL << d;
+  if (d == 2) return nchild * msz + (long long)a.R[0] * a.A[1] * QT;
+  return nchild * msz + (long long)a.R[0] * a.R[1] * a.A[2] * QT + (long long)a.R[0] * a.A[1] * a.A[2] * QT;
+}
+
+static long long xmfma_items(const StageArgs& a, int d, int QT) {
+  const long long ncols = (d == 2 ? a.A[1] : (long long)a.A[1] * a.A[2]) * QT;
+  const long long nrt = (a.A[0] + 7) / 8;
+  const long long ngrp = ((ncols + 15) / 16 + kXT - 1) / kXT;
+  return nrt * ngrp;
+}
+
+template <int D, int QT>
+static tb_status launch_xmfma_q(StageArgs a, bool fanout, dim3 grid, size_t lds, const void* in, void* out,
+                                const void* mats, hipStream_t stream) {
+  if (fanout) {
+    TB_TRY(set_lds(stage_fanout_mfma<D, QT>, lds));
+    stage_fanout_mfma<D, QT><<<grid, kThreads, lds, stream>>>(a, (const float2*)in, (float2*)out,
+                                                              (const float2*)mats);
+  } else {
+    TB_TRY(set_lds(stage_fanin_mfma<D, QT>, lds));
+    stage_fanin_mfma<D, QT><<<grid, kThreads, lds, stream>>>(a, (const float2*)in, (float2*)out,
+                                                             (const float2*)mats);
+  }
+  return TB_OK;
+}
+
+template <int D>
+static tb_status launch_xmfma_d(StageArgs a, bool fanout, int QT, dim3 grid, size_t lds, const void* in,
+                                void* out, const void* mats, hipStream_t stream) {
+  switch (QT) {
+    case 1: return launch_xmfma_q<D, 1>(a, fanout, grid, lds, in, out, mats, stream);
+    case 2: return launch_xmfma_q<D, 2>(a, fanout, grid, lds, in, out, mats, stream);
+    case 4: return launch_xmfma_q<D, 4>(a, fanout, grid, lds, in, out, mats, stream);
+    default: return launch_xmfma_q<D, 8>(a, fanout, grid, lds, in, out, mats, stream);
+  }
+}
+
+template <class T>
+static tb_status launch_stage_xmfma(const Plan& p, StageArgs a, bool fanout, int n_items, const void* in,
+                                    void* out, const void* mats, hipStream_t stream, const LaunchCfg& cfg) {
+  if (sizeof(T) != 4) return fail(TB_ERR_UNSUPPORTED, "matrix-core transfers are FP32 only");
+  if (a.coarse_global) return fail(TB_ERR_UNSUPPORTED, "matrix-core transfers cover transfer levels only");
+  const int d = p.d;
+  int limit = 0;
+  TB_TRY(lds_limit(&limit));
+  const long long budget = std::min<long long>(limit, 80 * 1024);
+  const int qcap = cfg.QT > 0 ? cfg.QT : 8;
+  int QT = 1;
+  while (QT * 2 <= qcap && QT * 2 <= a.nrhs) QT *= 2;
+  auto fits = [&](int q, long long cap) {
+    return xmfma_lds_elems(a, d, fanout, q) * (long long)sizeof(float2) <= cap &&
+           (fanout || xmfma_items(a, d, q) <= (long long)kXItems * (kThreads / 64));
+  };
+  while (QT > 1 && !fits(QT, budget)) QT /= 2;
+  if (cfg.QT > 0 && QT != cfg.QT) return fail(TB_ERR_UNSUPPORTED, "RHS tile does not fit this stage");
+  if (!fits(QT, limit)) return fail(TB_ERR_UNSUPPORTED, "block too large for the matrix-core transfer");
+  const size_t lds = (size_t)xmfma_lds_elems(a, d, fanout, QT) * sizeof(float2);
+  a.chunk = fanout ? a.R[0] : a.A[0];
+  a.nsplit = 1;
+  const long long nwg = (long long)n_items * a.nblk * ((a.nrhs + QT - 1) / QT);
+  if (nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many right-hand sides for one launch");
+  dim3 grid((unsigned)nwg);
+  const tb_status st = d == 2 ? launch_xmfma_d<2>(a, fanout, QT, grid, lds, in, out, mats, stream)
+                              : launch_xmfma_d<3>(a, fanout, QT, grid, lds, in, out, mats, stream);
+  TB_TRY(st);
+  TB_HIP_TRY(hipGetLastError());
+  return TB_OK;
+}
+
 template <class T, int D, int G>
 static tb_status launch_stage_g(StageArgs a, bool fanout, bool sm, int QT, dim3 grid, size_t lds,
                                 const void* in, void* out, const void* mats, hipStream_t stream) {
@@ -1553,6 +1995,7 @@ template <class T>
 static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_items, const void* in,
                               void* out, const void* mats, hipStream_t stream, const LaunchCfg& cfg) {
   using C = typename CplxOf<T>::type;
+  if (cfg.mfma == 1) return launch_stage_xmfma<T>(p, a, fanout, n_items, in, out, mats, stream, cfg);
   if (cfg.alt == 1) {
     if (fanout) return fail(TB_ERR_UNSUPPORTED, "no in-turn variant of the fan-out");
     return launch_stage_seq<T>(p, a, n_items, in, out, mats, stream, cfg);
@@ -1824,7 +2267,7 @@ static uint64_t plan_signature(const Plan& p) {
   return h;
 }
 
-static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout) {
+static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout, bool fp32) {
   std::vector<LaunchCfg> out;
   for (int qt : {1, 2, 4, 8}) {
     if (qt > 1 && qt > nrhs) break;
@@ -1840,6 +2283,12 @@ static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout) {
       LaunchCfg c;
       c.QT = qt;
       c.alt = 1;
+      out.push_back(c);
+    }
+    if (fp32) {
+      LaunchCfg c;
+      c.QT = qt;
+      c.mfma = 1;
       out.push_back(c);
     }
   }
@@ -1872,15 +2321,15 @@ static bool read_cache(const char* path, uint64_t sig, int io, long long nrhs, s
     unsigned long long s = 0;
     int fio = 0, n = 0, pos = 0;
     long long fr = 0;
-    if (std::sscanf(line, "tbtune2 %llx %d %lld %d%n", &s, &fio, &fr, &n, &pos) != 4) continue;
+    if (std::sscanf(line, "tbtune3 %llx %d %lld %d%n", &s, &fio, &fr, &n, &pos) != 4) continue;
     if (s != sig || fio != io || fr != nrhs || (size_t)n != nslots) continue;
     std::vector<LaunchCfg> v(n);
     const char* q = line + pos;
     bool ok = true;
     for (int i = 0; i < n && ok; ++i) {
       int used = 0;
-      ok = std::sscanf(q, " %d,%d,%d,%d,%d%n", &v[i].G, &v[i].QT, &v[i].split, &v[i].core, &v[i].alt,
-                       &used) == 5;
+      ok = std::sscanf(q, " %d,%d,%d,%d,%d,%d%n", &v[i].G, &v[i].QT, &v[i].split, &v[i].core, &v[i].alt,
+                       &v[i].mfma, &used) == 6;
       q += used;
     }
     if (ok) {
@@ -1896,8 +2345,9 @@ static void append_cache(const char* path, uint64_t sig, int io, long long nrhs,
                          const std::vector<LaunchCfg>& cfg) {
   FILE* fh = std::fopen(path, "a");
   if (!fh) return;
-  std::fprintf(fh, "tbtune2 %016llx %d %lld %d", (unsigned long long)sig, io, nrhs, (int)cfg.size());
-  for (const LaunchCfg& c : cfg) std::fprintf(fh, " %d,%d,%d,%d,%d", c.G, c.QT, c.split, c.core, c.alt);
+  std::fprintf(fh, "tbtune3 %016llx %d %lld %d", (unsigned long long)sig, io, nrhs, (int)cfg.size());
+  for (const LaunchCfg& c : cfg)
+    std::fprintf(fh, " %d,%d,%d,%d,%d,%d", c.G, c.QT, c.split, c.core, c.alt, c.mfma);
   std::fprintf(fh, "\n");
   std::fclose(fh);
 }
@@ -1941,7 +2391,7 @@ static tb_status tune_typed(Plan& p, tb_dtype io, long long nrhs, hipStream_t st
     check(hipMemsetAsync(bin, 0, bytes, stream), "hipMemsetAsync");
     check(hipMemsetAsync(p.ws.base, 0, p.ws.bytes, stream), "hipMemsetAsync");
     for (size_t i = 0; i < steps.size() && st == TB_OK; ++i) {
-      const auto cands = steps[i].core ? core_candidates(nrhs, io) : stage_candidates(nrhs, steps[i].fanout);
+      const auto cands = steps[i].core ? core_candidates(nrhs, io) : stage_candidates(nrhs, steps[i].fanout, io != TB_C128);
       float best_ms = 1e30f;
       LaunchCfg pick{};
       for (const LaunchCfg& c : cands) {
@@ -2189,7 +2639,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   const int g = cfg->outputs_per_thread, q = cfg->rhs_tile;
   if (!(g == 0 || g == 1 || g == 8) || !(q == 0 || q == 1 || q == 2 || q == 4 || q == 8) ||
       cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 3 ||
-      cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 1)
+      cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 1 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1)
     return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");
   auto& v = p->tuned[{(int)io, nrhs}];
   if ((int)v.size() != nslots) v.assign(nslots, tb::LaunchCfg{});
@@ -2199,6 +2649,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   c.split = cfg->whole_blocks;
   c.core = cfg->core_kernel;
   c.alt = cfg->fanin_in_turn;
+  c.mfma = cfg->transfer_mfma;
   v[slot] = c;
   tb::drop_graphs_for(p);
   return TB_OK;

@@ -98,6 +98,7 @@ struct LaunchCfg {
   int split = 0;  // transfer: 1 = one workgroup per block (no slicing)
   int core = 0;   // core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = MFMA
   int alt = 0;    // fan-in: 1 = children in turn, mode 0 in registers
+  int mfma = 0;   // transfer levels: 1 = mode products on the matrix cores
 };
 
 struct Plan {

@@ -51,7 +51,7 @@ def test_tuned_apply_matches_oracle_and_cache_round_trips(kind, d, n, tol, leaf,
         torch.cuda.synchronize()
         assert torch.equal(u, u2) and torch.equal(v, v2)
     lines = open(cache).read().splitlines()
-    assert len(lines) == 3 and all(l.startswith("tbtune2 ") for l in lines)
+    assert len(lines) == 3 and all(l.startswith("tbtune3 ") for l in lines)
 
 
 def test_autotune_rejects_missing_precision(tmp_path):
@@ -86,6 +86,8 @@ def _candidates(stage, nrhs, dtype):
                 out.append(dict(outputs_per_thread=g, rhs_tile=qt, whole_blocks=whole))
         if not fanout:
             out.append(dict(rhs_tile=qt, fanin_in_turn=1))
+        if dtype != "c128":
+            out.append(dict(rhs_tile=qt, transfer_mfma=1))
     return out
 
 
