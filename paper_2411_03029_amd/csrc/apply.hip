@@ -170,14 +170,18 @@ __device__ __forceinline__ void coarse_segs(const StageArgs& a, int citem, const
 // G = 1 keeps every thread busy on small blocks (one right-hand side);
 // G = 8 cuts loads when right-hand sides fill the workgroup.  The stage
 // kernels take G (kG) as a template parameter; the autotuner picks it.
+// Outputs g >= ng repeat row ng - 1 (an in-bounds read) and are never
+// stored: the inner loop carries no per-output branch.
 template <int G, class C, class MF, class XF>
 __device__ __forceinline__ void gdot(C (&acc)[G], int ng, int nj, MF m, XF x) {
+  int row[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) row[g] = min(g, ng - 1);
 #pragma unroll 2
   for (int j = 0; j < nj; ++j) {
     const C xv = x(j);
 #pragma unroll
-    for (int g = 0; g < G; ++g)
-      if (g < ng) acc[g] = cfma(acc[g], m(g, j), xv);
+    for (int g = 0; g < G; ++g) acc[g] = cfma(acc[g], m(row[g], j), xv);
   }
 }
 
