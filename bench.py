@@ -148,14 +148,13 @@ def _counter_per_dispatch(directory: str, counter: str, name_part: str) -> float
     return sum(vals.values()) / len(vals)
 
 
-def summarize(trace_dir, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes,
-              workload, command) -> int:
-    """Write the committed profile summaries under profiles/ from rocprofv3
-    CSV output: kernel-trace statistics, and the HBM traffic of the forward
-    core kernel scaled by the counters of a plain copy of copy_bytes."""
+def summarize_stats(trace_dir, workload, command) -> int:
+    """profiles/kernel_stats_<workload>.md from rocprofv3 --kernel-trace
+    --stats CSV output (autotuning trials included: they run the same
+    kernels)."""
     stats = _rocprof_rows(trace_dir, "kernel_stats.csv")
     lines = [f"# rocprofv3 kernel statistics: workload {workload}", "",
-             f"command: {command['trace']}", "",
+             f"command: {command}", "",
              "| kernel | calls | total (us) | average (us) | percent |", "|---|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0))):
         name = r["Name"]
@@ -165,6 +164,15 @@ def summarize(trace_dir, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, c
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"kernel_stats_{workload}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    return 0
+
+
+def summarize(trace_dir, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes,
+              workload, command) -> int:
+    """Write the committed profile summaries under profiles/ from rocprofv3
+    CSV output: kernel-trace statistics, and the HBM traffic of the forward
+    core kernel scaled by the counters of a plain copy of copy_bytes."""
+    summarize_stats(trace_dir, workload, command["trace"])
     core = "core_fwd<float, HIP_vector_type<float, 2u>"
     copy_name = "copy"
     f_core = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", core)
@@ -236,7 +244,7 @@ def run_single(args, tb, inputs, torch, np) -> dict:
     info = plan.info()
     t0 = time.perf_counter()
     for dt in ("c64", "c128"):
-        plan.autotune(nrhs, dtype=dt)
+        plan.autotune(nrhs, dtype=dt, cache=args.tune_cache)
     autotune_s = time.perf_counter() - t0
 
     f_host = inputs.rhs_batch(n, d, nrhs, config=2)
@@ -328,7 +336,7 @@ def run_mix(args, tb, inputs, torch, np) -> dict:
     t0 = time.perf_counter()
     for p, m in zip(plans, counts):
         for dt in ("cbf16", "c64", "c128"):
-            p.autotune(m, dtype=dt)
+            p.autotune(m, dtype=dt, cache=args.tune_cache)
     autotune_s = time.perf_counter() - t0
     f_host = [inputs.rhs_batch(n, d, m, config=40 + i) for i, ((_, d, n, _), m) in
               enumerate(zip(MIX, counts))]
@@ -444,7 +452,7 @@ def run_lsq(args, tb, inputs, torch, np) -> dict:
     construct_s = time.perf_counter() - t0
     info = plan.info()
     t0 = time.perf_counter()
-    plan.autotune(nrhs, dtype="c64")
+    plan.autotune(nrhs, dtype="c64", cache=args.tune_cache)
     autotune_s = time.perf_counter() - t0
     ftrue = _bumps_on_device(n, [5000 + q for q in range(nrhs)], torch)
     b = plan.apply(ftrue.to(torch.complex64))
@@ -528,16 +536,22 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="helmholtz_cubes_n64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-cache", default=None, metavar="PATH",
+                    help="autotuner cache file (reused choices skip the timed trials)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--summarize", nargs=5, metavar="DIR",
                     help="write profiles/ from rocprofv3 CSV dirs: trace fetch write "
                          "copy_fetch copy_write")
+    ap.add_argument("--summarize-stats", metavar="DIR",
+                    help="write profiles/kernel_stats_<workload>.md from a rocprofv3 trace dir")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--commands-json", default="{}")
     args = ap.parse_args()
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
+    if args.summarize_stats:
+        return summarize_stats(args.summarize_stats, args.workload, args.commands_json)
     if args.summarize:
         return summarize(*args.summarize, args.copy_bytes, args.workload,
                          json.loads(args.commands_json))
