@@ -297,6 +297,16 @@ def run_single(args, tb, inputs, torch, np) -> dict:
         "adjoint_kernel_GBs": round(core_bytes / avg_core_adj_s / 1e9, 1),
     }
     stage_us = {k: round(1000 * ms / c, 2) for k, (ms, c) in stages.items() if c}
+    # whole apply per direction: every factor and core entry plus reading the
+    # input and writing the output, over the summed stage times of one step
+    fwd = ("src_leaf", "src_transfer", "core", "tgt_transfer", "tgt_leaf")
+    apply_bytes = 8 * (info["factor_entries"] + info["core_entries"] + 2 * n ** d * nrhs)
+    t_fwd = sum(stages[k][0] for k in fwd) / args.steps * 1e-3
+    t_adj = sum(ms for k, (ms, c) in stages.items() if k not in fwd) / args.steps * 1e-3
+    apply_hbm = {"bytes_per_direction": apply_bytes,
+                 "fwd_us": round(t_fwd * 1e6, 1), "adj_us": round(t_adj * 1e6, 1),
+                 "frac_fwd": round(apply_bytes / t_fwd / 1e9 / HBM_PEAK_GBS, 4),
+                 "frac_adj": round(apply_bytes / t_adj / 1e9 / HBM_PEAK_GBS, 4)}
 
     cpu_base, errors = None, None
     if not args.no_cpu_baseline:
@@ -312,7 +322,7 @@ def run_single(args, tb, inputs, torch, np) -> dict:
         **{"accuracy_gate_1e-4": (None if errors is None else
                                   all(e["fwd"] <= 1e-4 and e["adj"] <= 1e-4
                                       for e in errors.values()))},
-        roofline=roofline, stage_avg_us=stage_us, cpu_baseline=cpu_base,
+        roofline=roofline, apply_hbm=apply_hbm, stage_avg_us=stage_us, cpu_baseline=cpu_base,
         construct_s=round(construct_s, 3), autotune_s=round(autotune_s, 3),
         plan={k: info[k] for k in ("L", "Lt", "Ls", "r_min", "r_max", "n_ids", "n_pairs",
                                    "core_entries", "factor_entries", "apply_cmacs", "eps_id")})
