@@ -243,7 +243,7 @@ def run_single(args, tb, inputs, torch, np) -> dict:
     construct_s = time.perf_counter() - t0
     info = plan.info()
     t0 = time.perf_counter()
-    for dt in ("c64", "c128"):
+    for dt in ("c64", "c128", "c64otf"):
         plan.autotune(nrhs, dtype=dt, cache=args.tune_cache)
     autotune_s = time.perf_counter() - t0
 
@@ -253,7 +253,7 @@ def run_single(args, tb, inputs, torch, np) -> dict:
 
     # outputs for the accuracy gate
     gpu_out = {}
-    for name, x, dt in (("c64", x32, "c64"), ("c128", x64, "c128")):
+    for name, x, dt in (("c64", x32, "c64"), ("c128", x64, "c128"), ("c64otf", x32, "c64otf")):
         u = plan.apply(x, dtype=dt)
         v = plan.apply_adjoint(x, dtype=dt)
         torch.cuda.synchronize()
@@ -297,6 +297,19 @@ def run_single(args, tb, inputs, torch, np) -> dict:
         "adjoint_kernel_GBs": round(core_bytes / avg_core_adj_s / 1e9, 1),
     }
     stage_us = {k: round(1000 * ms / c, 2) for k, (ms, c) in stages.items() if c}
+    # the same FP32 apply with the cores evaluated inside the contraction
+    t_otf = time_steps(plan, x32, "c64otf", args.steps, args.warmup, torch)
+    plan.set_timing(True)
+    time_steps(plan, x32, "c64otf", args.steps, 0, torch)
+    st_otf = plan.stage_times()
+    plan.set_timing(False)
+    otf_fwd_s = st_otf["core"][0] / max(st_otf["core"][1], 1) * 1e-3
+    otf_adj_s = st_otf["core_adj"][0] / max(st_otf["core_adj"][1], 1) * 1e-3
+    otf = {"value": points * args.steps / t_otf, "ms_per_step": 1000 * t_otf / args.steps,
+           "core_fwd_us": round(otf_fwd_s * 1e6, 2), "core_adj_us": round(otf_adj_s * 1e6, 2),
+           "core_entries_per_s": info["core_entries"] / otf_fwd_s,
+           "note": "cores K(tbar,sbar) evaluated inside the contraction (FP64 phase, FP32 sin/cos): "
+                   "no stored cores, ALU-bound"}
     # whole apply per direction: every factor and core entry plus reading the
     # input and writing the output, over the summed stage times of one step
     fwd = ("src_leaf", "src_transfer", "core", "tgt_transfer", "tgt_leaf")
@@ -322,7 +335,8 @@ def run_single(args, tb, inputs, torch, np) -> dict:
         **{"accuracy_gate_1e-4": (None if errors is None else
                                   all(e["fwd"] <= 1e-4 and e["adj"] <= 1e-4
                                       for e in errors.values()))},
-        roofline=roofline, apply_hbm=apply_hbm, stage_avg_us=stage_us, cpu_baseline=cpu_base,
+        roofline=roofline, apply_hbm=apply_hbm, stage_avg_us=stage_us, on_the_fly_cores=otf,
+        cpu_baseline=cpu_base,
         construct_s=round(construct_s, 3), autotune_s=round(autotune_s, 3),
         plan={k: info[k] for k in ("L", "Lt", "Ls", "r_min", "r_max", "n_ids", "n_pairs",
                                    "core_entries", "factor_entries", "apply_cmacs", "eps_id")})

@@ -66,12 +66,19 @@ typedef enum {
 
 /* Element type of the apply.  TB_C128: complex128 arrays, FP64 factors,
  * cores and accumulation.  TB_C64: complex64 arrays, FP32 everything.
- * TB_CBF16: complex64 arrays, BF16 cores, FP32 factors and accumulation. */
-typedef enum { TB_C128 = 0, TB_C64 = 1, TB_CBF16 = 2 } tb_dtype;
+ * TB_CBF16: complex64 arrays, BF16 cores, FP32 factors and accumulation.
+ * TB_C64_OTF: complex64 arrays, FP32 factors and accumulation, the cores
+ * K(tbar, sbar) evaluated inside the core contraction from the skeleton
+ * indices (section 2: any entry in O(1)) instead of read from memory: phase
+ * formed and reduced to a fraction of a turn in FP64, sine and cosine in
+ * FP32; available for every plan, stored cores or not. */
+typedef enum { TB_C128 = 0, TB_C64 = 1, TB_CBF16 = 2, TB_C64_OTF = 3 } tb_dtype;
 
 #define TB_STORE_C128 (1u << TB_C128)
 #define TB_STORE_C64 (1u << TB_C64)
 #define TB_STORE_CBF16 (1u << TB_CBF16)
+/* store_mask == TB_STORE_OTF keeps no cores: only TB_C64_OTF applies run. */
+#define TB_STORE_OTF (1u << TB_C64_OTF)
 
 typedef struct tb_plan_s* tb_plan;
 
@@ -86,7 +93,8 @@ typedef struct {
   int proxy_other;      /* samples of every other mode; 0 -> 4*leaf (d = 2)
                            or 4 (d = 3); < 0 -> every index of the node     */
   double id_tol_scale;  /* ID tolerance = id_tol_scale * tol; 0 -> 0.3      */
-  unsigned store_mask;  /* core precisions kept (TB_STORE_*); 0 -> C64      */
+  unsigned store_mask;  /* core precisions kept (TB_STORE_*); 0 -> C64;
+                           TB_STORE_OTF alone keeps none                   */
   int max_rank;         /* > 0: an ID rank above it fails with
                            TB_ERR_NUMERIC; 0 -> no limit                   */
   size_t max_device_bytes; /* > 0: cap on the plan's device memory; a plan

@@ -20,9 +20,10 @@ from ._lib import TBError
 
 KINDS = {"fourier": _lib.TB_KERNEL_FOURIER, "helmholtz": _lib.TB_KERNEL_HELMHOLTZ,
          "radon": _lib.TB_KERNEL_RADON}
-DTYPES = {"c128": _lib.TB_C128, "c64": _lib.TB_C64, "cbf16": _lib.TB_CBF16}
+DTYPES = {"c128": _lib.TB_C128, "c64": _lib.TB_C64, "cbf16": _lib.TB_CBF16,
+          "c64otf": _lib.TB_C64_OTF}
 STORE = {"c128": _lib.TB_STORE_C128, "c64": _lib.TB_STORE_C64,
-         "cbf16": _lib.TB_STORE_CBF16}
+         "cbf16": _lib.TB_STORE_CBF16, "otf": _lib.TB_STORE_OTF}
 
 __all__ = ["construct", "load_plan", "Plan", "TBApply", "TBError",
            "helmholtz_omega"]

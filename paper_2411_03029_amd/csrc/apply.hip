@@ -27,6 +27,7 @@
 #include <cstring>
 #include <functional>
 #include <mutex>
+#include <type_traits>
 
 #include "cplx.h"
 #include "tb_internal.h"
@@ -1112,6 +1113,263 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// -------------------------------------------------- on-the-fly cores --
+// K(tbar, sbar) evaluated inside the core contraction instead of streamed
+// from memory (no stored cores).  Every kernel is exp(2 pi i rev) * amp:
+//   Fourier    rev = -(x . k) / n with x integer and k = j - n/2: an int32
+//              sum reduced exactly modulo n (a power of two), amp = 1;
+//   Helmholtz  rev = omega rho / (2 pi), amp = 1 / rho: the squared
+//              distance n^2 rho^2 is a sum of squares of integer index
+//              differences, exact in FP64, then rho via rsqrt;
+//   Radon      rev = x . k + sqrt(c1(x)^2 k1^2 + c2(x)^2 k2^2), amp = 1, in
+//              FP64 with c1(x)^2, c2(x)^2 precomputed per target point.
+// The fraction of a turn goes to FP32 sine and cosine; the product with F
+// runs in FP32.  A point is four ints (Fourier, Helmholtz: the per-mode
+// grid indices, the source's first index shifted by 2n for the cube
+// offset) or four doubles (Radon: x1, x2, c1^2, c2^2 on the target side,
+// k1, k2 on the source side).
+struct OtfSpec {
+  long long n;
+  double omega_rev;  // omega / (2 pi)
+  double ra, rb, rden;
+  int Rs_sk, Rt_sk;  // row length of the skeleton tables
+};
+
+template <int KIND>
+struct OtfPoint {
+  using V = int4;
+};
+template <>
+struct OtfPoint<TB_KERNEL_RADON> {
+  using V = double4;
+};
+
+template <int KIND, int D>
+__device__ __forceinline__ typename OtfPoint<KIND>::V otf_target(const OtfSpec& o, const int* ti) {
+  if constexpr (KIND == TB_KERNEL_RADON) {
+    const double inv = 1.0 / (double)o.n;
+    const double x1 = ti[0] * inv, x2 = ti[1] * inv;
+    double s1, c1, s2, c2;
+    sincospi(2.0 * x1, &s1, &c1);
+    sincospi(2.0 * x2, &s2, &c2);
+    const double a1 = (o.ra + o.rb * s1 * s2) / o.rden, a2 = (o.ra + o.rb * c1 * c2) / o.rden;
+    return make_double4(x1, x2, a1 * a1, a2 * a2);
+  } else {
+    return make_int4(ti[0], ti[1], D == 3 ? ti[D - 1] : 0, 0);
+  }
+}
+
+template <int KIND, int D>
+__device__ __forceinline__ typename OtfPoint<KIND>::V otf_source(const OtfSpec& o, const int* sj) {
+  const int h = (int)(o.n / 2);
+  if constexpr (KIND == TB_KERNEL_RADON) {
+    return make_double4((double)(sj[0] - h), (double)(sj[1] - h), 0.0, 0.0);
+  } else if constexpr (KIND == TB_KERNEL_FOURIER) {
+    return make_int4(sj[0] - h, sj[1] - h, D == 3 ? sj[D - 1] - h : 0, 0);
+  } else {  // y = j/n + (2, 0, 0): index j_0 + 2n
+    return make_int4(sj[0] + 2 * (int)o.n, sj[1], D == 3 ? sj[D - 1] : 0, 0);
+  }
+}
+
+// 1/sqrt(q), q > 0: the hardware estimate (v_rsq_f64, about 2^-23 relative)
+// and one Newton step, y (3 - q y^2) / 2, which brings it to about 1e-14
+__device__ __forceinline__ double rsqrt64(double q) {
+  double y = __builtin_amdgcn_rsq(q);
+  return y * fma(-0.5 * q * y, y, 1.5);
+}
+
+// entry from target point x and source point y
+template <int KIND, int D>
+__device__ __forceinline__ float2 otf_entry(const OtfSpec& o, const typename OtfPoint<KIND>::V& x,
+                                            const typename OtfPoint<KIND>::V& y) {
+  float f, amp = 1.f;
+  if constexpr (KIND == TB_KERNEL_FOURIER) {
+    int p = x.x * y.x + x.y * y.y;  // |p| < 3 n^2 / 2 < 2^31 for n <= 2^15
+    if (D == 3) p += x.z * y.z;
+    const int nm = (int)o.n - 1;
+    f = (float)((-p) & nm) * (1.f / (float)o.n);  // exact: n is a power of two
+  } else if constexpr (KIND == TB_KERNEL_HELMHOLTZ) {
+    const double d0 = (double)(x.x - y.x), d1 = (double)(x.y - y.y), d2 = (double)(x.z - y.z);
+    const double inv = 1.0 / (double)o.n;
+    const double r2 = fma(d0, d0, fma(d1, d1, d2 * d2)) * (inv * inv);  // exact scaling
+    const double ir = rsqrt64(r2);  // the cubes are apart: r2 >= 1
+    const double rev = o.omega_rev * (r2 * ir);
+    f = (float)(rev - floor(rev));
+    amp = (float)ir;
+  } else {
+    const double q = x.z * y.x * y.x + x.w * y.y * y.y;
+    const double rev = x.x * y.x + x.y * y.y + (q > 0.0 ? q * rsqrt64(q) : 0.0);
+    f = (float)(rev - floor(rev));
+  }
+  // v_sin_f32 / v_cos_f32 take the angle in revolutions
+  return make_float2(amp * __builtin_amdgcn_cosf(f), amp * __builtin_amdgcn_sinf(f));
+}
+
+// per-mode skeleton indices of flat row (or column) index r of a pair
+template <int D>
+__device__ __forceinline__ void otf_index(const int* skel, long long item, int Rsk, const int* rk, int r,
+                                          int* idx) {
+#pragma unroll
+  for (int k = D - 1; k >= 0; --k) {
+    idx[k] = skel[(item * D + k) * Rsk + r % rk[k]];
+    r /= rk[k];
+  }
+}
+
+// G_{t,s}(rows) = K(tbar, sbar)(rows, :) F_{t,s}: 64 rows per workgroup, one
+// per lane, the four waves split the columns and reduce through LDS.
+template <int KIND, int D, int QT>
+__global__ void __launch_bounds__(kThreads)
+    core_fwd_otf(CoreArgs a, OtfSpec o, const int* __restrict__ meta, const int2* __restrict__ units,
+                 const int* __restrict__ sskel, const int* __restrict__ tskel, const float2* __restrict__ F,
+                 float2* __restrict__ G) {
+  using P = typename OtfPoint<KIND>::V;
+  extern __shared__ unsigned char smem_raw[];
+  const int2 u = units[blockIdx.x];
+  const int pair = u.x, r0 = u.y;
+  const int* m = meta + pair * kPairMeta;
+  const int RT = m[0], RS = m[1];
+  int rt[D], rs[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    rt[k] = m[3 + k];
+    rs[k] = m[6 + k];
+  }
+  const long long t = pair / a.nS, s = pair % a.nS;
+  const long long sitem = s * a.nT + t, titem = t * a.nS + s;
+  const int q0 = blockIdx.y * QT;
+  const int Qa = min(QT, a.nrhs - q0);
+  P* yv = reinterpret_cast<P*>(smem_raw);                 // [RS]
+  float2* x = reinterpret_cast<float2*>(yv + RS);          // [RS][QT]
+  float2* red = x + RS * QT;                               // [256][QT]
+  for (int b = threadIdx.x; b < RS; b += kThreads) {
+    int sj[D];
+    otf_index<D>(sskel, sitem, o.Rs_sk, rs, b, sj);
+    yv[b] = otf_source<KIND, D>(o, sj);
+  }
+  for (int idx = threadIdx.x; idx < RS * QT; idx += kThreads) {
+    const int q = idx % QT, b = idx / QT;
+    x[idx] = q < Qa ? F[(sitem * a.Es + padded_pos<D>(b, rs, a.Rs)) * a.nrhs + q0 + q]
+                    : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = r0 + lane;
+  P xv;
+  {
+    int ti[D];
+    otf_index<D>(tskel, titem, o.Rt_sk, rt, min(row, RT - 1), ti);
+    xv = otf_target<KIND, D>(o, ti);
+  }
+  const int per = (RS + 3) / 4;
+  const int j0 = w * per, j1 = min(RS, j0 + per);
+  float2 acc[QT];
+#pragma unroll
+  for (int q = 0; q < QT; ++q) acc[q] = make_float2(0.f, 0.f);
+  for (int j = j0; j < j1; ++j) {
+    const float2 c = otf_entry<KIND, D>(o, xv, yv[j]);
+#pragma unroll
+    for (int q = 0; q < QT; ++q) acc[q] = cfma(acc[q], c, x[j * QT + q]);
+  }
+#pragma unroll
+  for (int q = 0; q < QT; ++q) red[(w * 64 + lane) * QT + q] = acc[q];
+  __syncthreads();
+  if (w == 0 && row < RT) {
+    const long long pos = padded_pos<D>(row, rt, a.Rt);
+#pragma unroll
+    for (int q = 0; q < QT; ++q)
+      if (q < Qa) {
+        float2 sum = red[lane * QT + q];
+        sum = cadd(sum, red[(64 + lane) * QT + q]);
+        sum = cadd(sum, red[(128 + lane) * QT + q]);
+        sum = cadd(sum, red[(192 + lane) * QT + q]);
+        G[(titem * a.Et + pos) * a.nrhs + q0 + q] = sum;
+      }
+  }
+  if (r0 == 0) {  // padding of the output item is written as zeros
+    for (long long p = threadIdx.x; p < a.Et; p += kThreads)
+      if (is_padding<D>(p, rt, a.Rt))
+        for (int q = 0; q < Qa; ++q) G[(titem * a.Et + p) * a.nrhs + q0 + q] = make_float2(0.f, 0.f);
+  }
+}
+
+// F_{t,s}(cols) = K(tbar, sbar)(:, cols)^H G_{t,s}: 64 columns per
+// workgroup, one per lane, the four waves split the rows.
+template <int KIND, int D, int QT>
+__global__ void __launch_bounds__(kThreads)
+    core_adj_otf(CoreArgs a, OtfSpec o, const int* __restrict__ meta, const int2* __restrict__ units,
+                 const int* __restrict__ sskel, const int* __restrict__ tskel, const float2* __restrict__ G,
+                 float2* __restrict__ F) {
+  using P = typename OtfPoint<KIND>::V;
+  extern __shared__ unsigned char smem_raw[];
+  const int2 u = units[blockIdx.x];
+  const int pair = u.x, c0 = u.y;
+  const int* m = meta + pair * kPairMeta;
+  const int RT = m[0], RS = m[1];
+  int rt[D], rs[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    rt[k] = m[3 + k];
+    rs[k] = m[6 + k];
+  }
+  const long long t = pair / a.nS, s = pair % a.nS;
+  const long long sitem = s * a.nT + t, titem = t * a.nS + s;
+  const int q0 = blockIdx.y * QT;
+  const int Qa = min(QT, a.nrhs - q0);
+  P* xr = reinterpret_cast<P*>(smem_raw);                 // [RT]
+  float2* g = reinterpret_cast<float2*>(xr + RT);          // [RT][QT]
+  float2* red = g + RT * QT;                               // [256][QT]
+  for (int b = threadIdx.x; b < RT; b += kThreads) {
+    int ti[D];
+    otf_index<D>(tskel, titem, o.Rt_sk, rt, b, ti);
+    xr[b] = otf_target<KIND, D>(o, ti);
+  }
+  for (int idx = threadIdx.x; idx < RT * QT; idx += kThreads) {
+    const int q = idx % QT, b = idx / QT;
+    g[idx] = q < Qa ? G[(titem * a.Et + padded_pos<D>(b, rt, a.Rt)) * a.nrhs + q0 + q]
+                    : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = c0 + lane;
+  P yv;
+  {
+    int sj[D];
+    otf_index<D>(sskel, sitem, o.Rs_sk, rs, min(col, RS - 1), sj);
+    yv = otf_source<KIND, D>(o, sj);
+  }
+  const int per = (RT + 3) / 4;
+  const int i0 = w * per, i1 = min(RT, i0 + per);
+  float2 acc[QT];
+#pragma unroll
+  for (int q = 0; q < QT; ++q) acc[q] = make_float2(0.f, 0.f);
+  for (int i = i0; i < i1; ++i) {
+    const float2 c = otf_entry<KIND, D>(o, xr[i], yv);
+#pragma unroll
+    for (int q = 0; q < QT; ++q) acc[q] = cfma_conj(acc[q], c, g[i * QT + q]);
+  }
+#pragma unroll
+  for (int q = 0; q < QT; ++q) red[(w * 64 + lane) * QT + q] = acc[q];
+  __syncthreads();
+  if (w == 0 && col < RS) {
+    const long long pos = padded_pos<D>(col, rs, a.Rs);
+#pragma unroll
+    for (int q = 0; q < QT; ++q)
+      if (q < Qa) {
+        float2 sum = red[lane * QT + q];
+        sum = cadd(sum, red[(64 + lane) * QT + q]);
+        sum = cadd(sum, red[(128 + lane) * QT + q]);
+        sum = cadd(sum, red[(192 + lane) * QT + q]);
+        F[(sitem * a.Es + pos) * a.nrhs + q0 + q] = sum;
+      }
+  }
+  if (c0 == 0) {
+    for (long long p = threadIdx.x; p < a.Es; p += kThreads)
+      if (is_padding<D>(p, rs, a.Rs))
+        for (int q = 0; q < Qa; ++q) F[(sitem * a.Es + p) * a.nrhs + q0 + q] = make_float2(0.f, 0.f);
+  }
+}
+
 // --------------------------------------------------------- MFMA cores --
 // Many right-hand sides: the core contraction is a dense complex GEMM per
 // pair, G (R_T x Q) = C (R_T x R_S) F (R_S x Q), run on the matrix cores as
@@ -2126,6 +2384,74 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
                 : launch_core_q<T, CS, 3, 4>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream);
 }
 
+// Core contraction with the cores evaluated on the fly (TB_C64_OTF); cfg.core
+// 1 or 2 picks 1 or 4 right-hand sides per pass.
+static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const void* in, void* out,
+                                 hipStream_t stream, const LaunchCfg& cfg) {
+  const int d = p.d;
+  const Level& st = p.src[p.Lt];
+  const Level& tt = p.tgt[p.Ls];
+  CoreArgs a{};
+  a.nS = p.nS;
+  a.nT = p.nT;
+  a.Es = st.E;
+  a.Et = tt.E;
+  OtfSpec o{};
+  o.n = p.n;
+  o.omega_rev = p.omega / (2.0 * 3.14159265358979323846);
+  o.ra = p.ra;
+  o.rb = p.rb;
+  o.rden = p.rden;
+  for (int k = 0; k < d; ++k) {
+    a.Rs[k] = st.R[k];
+    a.Rt[k] = tt.R[k];
+    o.Rs_sk = std::max(o.Rs_sk, st.R[k]);
+    o.Rt_sk = std::max(o.Rt_sk, tt.R[k]);
+  }
+  a.nrhs = nrhs;
+  int maxRS = 0, maxRT = 0;
+  for (long long pr = 0; pr < p.npairs; ++pr) {
+    maxRT = std::max(maxRT, p.pair_meta[(size_t)pr * kPairMeta]);
+    maxRS = std::max(maxRS, p.pair_meta[(size_t)pr * kPairMeta + 1]);
+  }
+  if (cfg.core == 3) return fail(TB_ERR_UNSUPPORTED, "no matrix-core path for on-the-fly cores");
+  const int QT = (cfg.core == 2 || (cfg.core == 0 && nrhs >= 4)) ? 4 : 1;
+  int limit = 0;
+  TB_TRY(lds_limit(&limit));
+  if (p.kind == TB_KERNEL_FOURIER && p.n > (1 << 15))
+    return fail(TB_ERR_UNSUPPORTED, "on-the-fly Fourier cores need n <= 32768");
+  const int along = adjoint ? maxRT : maxRS;
+  const size_t point = p.kind == TB_KERNEL_RADON ? sizeof(double4) : sizeof(int4);
+  const size_t lds = (size_t)along * point + ((size_t)along + kThreads) * QT * sizeof(float2);
+  if (lds > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "on-the-fly core block exceeds the LDS limit");
+  const std::vector<int2>& units = adjoint ? p.otf_adj_units : p.fwd_units[0];
+  const int2* units_d = adjoint ? p.otf_adj_units_d : p.fwd_units_d[0];
+  dim3 grid((unsigned)units.size(), (unsigned)((nrhs + QT - 1) / QT));
+  auto go = [&](auto kern) -> tb_status {
+    TB_TRY(set_lds(kern, lds));
+    kern<<<grid, kThreads, lds, stream>>>(a, o, p.pair_meta_d, units_d, p.top_src_skel_d, p.top_tgt_skel_d,
+                                          (const float2*)in, (float2*)out);
+    TB_HIP_TRY(hipGetLastError());
+    return TB_OK;
+  };
+  auto by_kind = [&](auto kind_tag) -> tb_status {
+    constexpr int K = decltype(kind_tag)::value;
+    if (d == 2) {
+      if (adjoint) return QT == 4 ? go(core_adj_otf<K, 2, 4>) : go(core_adj_otf<K, 2, 1>);
+      return QT == 4 ? go(core_fwd_otf<K, 2, 4>) : go(core_fwd_otf<K, 2, 1>);
+    }
+    if (adjoint) return QT == 4 ? go(core_adj_otf<K, 3, 4>) : go(core_adj_otf<K, 3, 1>);
+    return QT == 4 ? go(core_fwd_otf<K, 3, 4>) : go(core_fwd_otf<K, 3, 1>);
+  };
+  switch (p.kind) {
+    case TB_KERNEL_FOURIER: return by_kind(std::integral_constant<int, TB_KERNEL_FOURIER>{});
+    case TB_KERNEL_HELMHOLTZ: return by_kind(std::integral_constant<int, TB_KERNEL_HELMHOLTZ>{});
+    default:
+      if (d != 2) return fail(TB_ERR_UNSUPPORTED, "on-the-fly Radon cores are 2-D");
+      return by_kind(std::integral_constant<int, TB_KERNEL_RADON>{});
+  }
+}
+
 // Records an event pair around one stage launch when timing is enabled.
 template <class F>
 static tb_status timed(Plan& p, int stage, hipStream_t stream, F&& launch) {
@@ -2149,7 +2475,8 @@ struct Step {
 
 template <class T, class CS>
 static tb_status build_steps(Plan& p, const void* in, void* out, long long nrhs, bool adjoint,
-                             const void* cores, hipStream_t stream, std::vector<Step>* steps) {
+                             const void* cores, hipStream_t stream, std::vector<Step>* steps,
+                             bool otf = false) {
   using C = typename CplxOf<T>::type;
   const size_t esz = sizeof(C);
   Buffers b = layout(p, nrhs, esz);
@@ -2172,6 +2499,9 @@ static tb_status build_steps(Plan& p, const void* in, void* out, long long nrhs,
   };
   auto core = [&](bool adj, const void* src, void* dst) {
     steps->push_back({adj ? TB_STAGE_CORE_ADJ : TB_STAGE_CORE, true, false, [=](const LaunchCfg& c) {
+                        if constexpr (sizeof(T) == 4) {
+                          if (otf) return launch_core_otf(*pp, adj, rhs, src, dst, stream, c);
+                        }
                         return launch_core<T, CS>(*pp, adj, rhs, cores, src, dst, stream, c);
                       }});
   };
@@ -2205,7 +2535,8 @@ template <class T, class CS>
 static tb_status apply_typed(Plan& p, tb_dtype io, const void* in, void* out, long long nrhs, bool adjoint,
                              const void* cores, hipStream_t stream) {
   std::vector<Step> steps;
-  const tb_status built = build_steps<T, CS>(p, in, out, nrhs, adjoint, cores, stream, &steps);
+  const tb_status built =
+      build_steps<T, CS>(p, in, out, nrhs, adjoint, cores, stream, &steps, io == TB_C64_OTF);
   TB_TRY(built);
   const auto it = p.tuned.find({(int)io, nrhs});
   const LaunchCfg none{};
@@ -2217,12 +2548,19 @@ static tb_status apply_typed(Plan& p, tb_dtype io, const void* in, void* out, lo
   return TB_OK;
 }
 
+static bool valid_io(int io) { return io >= TB_C128 && io <= TB_C64_OTF; }
+
+// on-the-fly applies need no stored cores
+static bool has_cores(const Plan& p, int io) {
+  return io == TB_C64_OTF || (io >= TB_C128 && io <= TB_CBF16 && p.cores[io]);
+}
+
 tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs, tb_dtype io, bool adjoint,
                     hipStream_t stream) {
   if (!in || !out) return fail(TB_ERR_INVALID_ARG, "null input or output pointer");
   if (nrhs < 1 || nrhs > (1 << 20)) return fail(TB_ERR_INVALID_ARG, "nrhs must be in [1, 2^20]");
-  if (io < TB_C128 || io > TB_CBF16) return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
-  if (!p.cores[io])
+  if (!valid_io(io)) return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
+  if (!has_cores(p, io))
     return fail(TB_ERR_INVALID_ARG,
                 "the plan holds no cores of the requested precision (see store_mask)");
   if (in == out) return fail(TB_ERR_INVALID_ARG, "input and output must not alias");
@@ -2230,6 +2568,7 @@ tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs, tb_dtype
     case TB_C128: return apply_typed<double, double2>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
     case TB_C64: return apply_typed<float, float2>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
     case TB_CBF16: return apply_typed<float, unsigned>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
+    case TB_C64_OTF: return apply_typed<float, float2>(p, io, in, out, nrhs, adjoint, nullptr, stream);
   }
   return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
 }
@@ -2308,7 +2647,7 @@ static std::vector<LaunchCfg> core_candidates(long long nrhs, tb_dtype io) {
     c.core = 2;
     out.push_back(c);
   }
-  if (io != TB_C128 && nrhs >= 4) {
+  if (io != TB_C128 && io != TB_C64_OTF && nrhs >= 4) {
     c.core = 3;
     out.push_back(c);
   }
@@ -2390,7 +2729,8 @@ static tb_status tune_typed(Plan& p, tb_dtype io, long long nrhs, hipStream_t st
   best->assign(2 * steps_per_direction(p), LaunchCfg{});
   for (int dir = 0; dir < 2 && st == TB_OK; ++dir) {
     std::vector<Step> steps;
-    st = build_steps<T, CS>(p, bin, bout, nrhs, dir == 1, p.cores[io], stream, &steps);
+    st = build_steps<T, CS>(p, bin, bout, nrhs, dir == 1, io == TB_C64_OTF ? nullptr : p.cores[io], stream,
+                            &steps, io == TB_C64_OTF);
     if (st != TB_OK) break;
     check(hipMemsetAsync(bin, 0, bytes, stream), "hipMemsetAsync");
     check(hipMemsetAsync(p.ws.base, 0, p.ws.bytes, stream), "hipMemsetAsync");
@@ -2432,8 +2772,8 @@ static tb_status tune_typed(Plan& p, tb_dtype io, long long nrhs, hipStream_t st
 tb_status run_autotune(Plan& p, long long nrhs, tb_dtype io, const char* cache, hipStream_t stream,
                        int* trials) {
   if (nrhs < 1 || nrhs > (1 << 20)) return fail(TB_ERR_INVALID_ARG, "nrhs must be in [1, 2^20]");
-  if (io < TB_C128 || io > TB_CBF16) return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
-  if (!p.cores[io]) return fail(TB_ERR_INVALID_ARG, "the plan holds no cores of the requested precision");
+  if (!valid_io(io)) return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
+  if (!has_cores(p, io)) return fail(TB_ERR_INVALID_ARG, "the plan holds no cores of the requested precision");
   int count = 0;
   const uint64_t sig = plan_signature(p);
   const size_t nslots = 2 * (size_t)steps_per_direction(p);
@@ -2444,6 +2784,7 @@ tb_status run_autotune(Plan& p, long long nrhs, tb_dtype io, const char* cache, 
       case TB_C128: st = tune_typed<double, double2>(p, io, nrhs, stream, &best, &count); break;
       case TB_C64: st = tune_typed<float, float2>(p, io, nrhs, stream, &best, &count); break;
       case TB_CBF16: st = tune_typed<float, unsigned>(p, io, nrhs, stream, &best, &count); break;
+      case TB_C64_OTF: st = tune_typed<float, float2>(p, io, nrhs, stream, &best, &count); break;
     }
     TB_TRY(st);
     if (cache) append_cache(cache, sig, io, nrhs, best);
@@ -2578,14 +2919,14 @@ tb_status run_batched(int nplans, const tb_plan* handles, const void* const* in,
                       const long long* nrhs, int adjoint, tb_dtype io, hipStream_t stream) {
   if (nplans < 1 || nplans > 256 || !handles || !in || !out || !nrhs)
     return fail(TB_ERR_INVALID_ARG, "tb_apply_batched: need 1..256 plans and non-null arrays");
-  if (io < TB_C128 || io > TB_CBF16) return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
+  if (!valid_io(io)) return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
   GraphKey key;
   std::vector<Plan*> plans;
   for (int i = 0; i < nplans; ++i) {
     Plan* p = reinterpret_cast<Plan*>(handles[i]);
     if (!p || !in[i] || !out[i]) return fail(TB_ERR_INVALID_ARG, "tb_apply_batched: null plan or array");
     if (nrhs[i] < 1 || nrhs[i] > (1 << 20)) return fail(TB_ERR_INVALID_ARG, "nrhs must be in [1, 2^20]");
-    if (!p->cores[io]) return fail(TB_ERR_INVALID_ARG, "a plan holds no cores of the requested precision");
+    if (!has_cores(*p, io)) return fail(TB_ERR_INVALID_ARG, "a plan holds no cores of the requested precision");
     if (in[i] == out[i]) return fail(TB_ERR_INVALID_ARG, "input and output must not alias");
     for (Plan* q : plans)
       if (q == p) return fail(TB_ERR_INVALID_ARG, "tb_apply_batched: plans must be distinct");
@@ -2637,7 +2978,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   tb::Plan* p = reinterpret_cast<tb::Plan*>(ph);
   if (!p || !cfg) return tb::fail(TB_ERR_INVALID_ARG, "null plan or configuration");
   if (nrhs < 1 || nrhs > (1 << 20)) return tb::fail(TB_ERR_INVALID_ARG, "nrhs must be in [1, 2^20]");
-  if (io < TB_C128 || io > TB_CBF16) return tb::fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
+  if (!tb::valid_io(io)) return tb::fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
   const int nslots = 2 * tb::steps_per_direction(*p);
   if (slot < 0 || slot >= nslots) return tb::fail(TB_ERR_INVALID_ARG, "launch slot out of range");
   const int g = cfg->outputs_per_thread, q = cfg->rhs_tile;

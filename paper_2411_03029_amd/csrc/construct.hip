@@ -436,6 +436,7 @@ tb_status launch_core_eval(Plan& p, hipStream_t stream, const double2* host_core
     }
     return TB_OK;
   }
+  if ((mask & 7u) == 0) return TB_OK;  // no stored cores (on-the-fly applies only)
   CoreEvalArgs a;
   a.ks = spec_of(p);
   a.nS = p.nS;
@@ -676,7 +677,7 @@ extern "C" tb_status tb_construct(tb_kernel kind, int d, long long n, double ome
     if (p.rden == 0.0) return fail(TB_ERR_INVALID_ARG, "radon_den must be nonzero");
   }
   p.store_mask = o.store_mask ? o.store_mask : TB_STORE_C64;
-  if (p.store_mask & ~7u) return fail(TB_ERR_INVALID_ARG, "unknown store_mask bits");
+  if (p.store_mask & ~15u) return fail(TB_ERR_INVALID_ARG, "unknown store_mask bits");
   p.max_device_bytes = o.max_device_bytes;
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   int ndev = 0;

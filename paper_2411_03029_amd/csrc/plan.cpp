@@ -148,6 +148,7 @@ tb_status build_core_tables(Plan& p) {
   p.adj_units.clear();
   p.mfma_fwd_units.clear();
   p.mfma_adj_units.clear();
+  p.otf_adj_units.clear();
   for (long long t = 0; t < p.nT; ++t)
     for (long long s = 0; s < p.nS; ++s) {
       long long pr = t * p.nS + s;
@@ -172,6 +173,7 @@ tb_status build_core_tables(Plan& p) {
       for (int c0 = 0; c0 < RS; c0 += 32) p.adj_units.push_back(make_int2((int)pr, c0));
       for (int r0 = 0; r0 < RT; r0 += 256) p.mfma_fwd_units.push_back(make_int2((int)pr, r0));
       for (int c0 = 0; c0 < RS; c0 += 256) p.mfma_adj_units.push_back(make_int2((int)pr, c0));
+      for (int c0 = 0; c0 < RS; c0 += 64) p.otf_adj_units.push_back(make_int2((int)pr, c0));
     }
   p.core_total = off;
   TB_TRY(upload(p, &p.pair_meta_d, p.pair_meta));
@@ -180,6 +182,7 @@ tb_status build_core_tables(Plan& p) {
   TB_TRY(upload(p, &p.adj_units_d, p.adj_units));
   TB_TRY(upload(p, &p.mfma_fwd_units_d, p.mfma_fwd_units));
   TB_TRY(upload(p, &p.mfma_adj_units_d, p.mfma_adj_units));
+  TB_TRY(upload(p, &p.otf_adj_units_d, p.otf_adj_units));
   // skeleton tables of the two top levels, padded with a valid index
   int Rs = 0, Rt = 0;
   for (int k = 0; k < d; ++k) {
@@ -445,6 +448,7 @@ extern "C" tb_status tb_plan_load(const char* path, const tb_options* opt,
   if (opt) {
     p.store_mask = opt->store_mask ? opt->store_mask : TB_STORE_C64;
     p.max_device_bytes = opt->max_device_bytes;
+    if (p.store_mask & ~15u) return fail(TB_ERR_INVALID_ARG, "unknown store_mask bits");
   }
   const int d = p.d;
   p.src.resize(p.Lt + 1);

@@ -128,6 +128,8 @@ struct Plan {
   std::vector<int2> mfma_fwd_units, mfma_adj_units;
   int2* mfma_fwd_units_d = nullptr;
   int2* mfma_adj_units_d = nullptr;
+  std::vector<int2> otf_adj_units;      // (pair, first column), 64 columns
+  int2* otf_adj_units_d = nullptr;
   // device skeleton tables of the two top levels (core evaluation)
   int* top_src_skel_d = nullptr;     // [item][k][Rs]
   int* top_tgt_skel_d = nullptr;     // [item][k][Rt]

@@ -174,3 +174,29 @@ def test_stage_multiply_add_split(tmp_path):
         assert sum(info["stage_cmacs"]) == info["apply_cmacs"]
         assert info["stage_cmacs"][2] == info["core_entries"]
         assert min(info["stage_cmacs"]) > 0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_on_the_fly_cores_match_oracle(name, tmp_path):
+    # the cores K(tbar, sbar) evaluated inside the contraction (phase reduced
+    # to a fraction of a turn in FP64, sine and cosine in FP32) from the
+    # oracle's skeletons: the oracle's apply to the FP32 bound, per RHS, on a
+    # plan that stores no cores at all
+    torch = torch_gpu()
+    import paper_2411_03029_amd as tb
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path, store=("otf",))
+    n, d = op.n, op.d
+    for nrhs in (1, 5):
+        f = inputs.rhs_batch(n, d, nrhs, config=95)
+        say(f"[gpu] on-the-fly cores {name} nrhs={nrhs}")
+        x = to_dev(f, torch.complex64)
+        u = to_host(plan.apply(x, dtype="c64otf"))
+        v = to_host(plan.apply_adjoint(x, dtype="c64otf"))
+        torch.cuda.synchronize()
+        ue, ve = bf.apply(op, f), bf.apply_adjoint(op, f)
+        for q in range(nrhs):
+            assert relerr(u[q], ue[q]) <= 2e-5, (q, relerr(u[q], ue[q]))
+            assert relerr(v[q], ve[q]) <= 2e-5, (q, relerr(v[q], ve[q]))
+    with pytest.raises(tb.TBError):  # no stored FP32 cores
+        plan.apply(x, dtype="c64")

@@ -73,7 +73,7 @@ def _candidates(stage, nrhs, dtype):
         out = [dict(core_kernel=1)]
         if nrhs >= 2:
             out.append(dict(core_kernel=2))
-        if dtype != "c128" and nrhs >= 4:
+        if dtype not in ("c128", "c64otf") and nrhs >= 4:
             out.append(dict(core_kernel=3))
         return out
     fanout = stage in ("src_leaf", "src_transfer", "tgt_leaf_adj", "tgt_transfer_adj")
@@ -96,6 +96,7 @@ def _candidates(stage, nrhs, dtype):
     (kernels.HELMHOLTZ, 3, 16, 1e-4, 8, 3, "c128"),
     (kernels.RADON, 2, 32, 1e-3, 8, 9, "c64"),
     (kernels.FOURIER, 2, 64, 1e-6, 8, 1, "c64"),
+    (kernels.HELMHOLTZ, 3, 32, 1e-4, 8, 6, "c64otf"),
 ])
 def test_every_launch_candidate_matches_oracle(kind, d, n, tol, leaf, nrhs, dtype, tmp_path):
     # each slot in turn runs each of its candidates (the rest keep the
@@ -107,7 +108,7 @@ def test_every_launch_candidate_matches_oracle(kind, d, n, tol, leaf, nrhs, dtyp
     op = bf.construct(Operator(kind, d, n, omega=om), tol, leaf=leaf)
     path = str(tmp_path / "p.tbplan")
     planio.save_plan(op, path)
-    store = ("c128",) if dtype == "c128" else ("c64",)
+    store = {"c128": ("c128",), "c64": ("c64",), "c64otf": ("otf",)}[dtype]
     bound = 1e-12 if dtype == "c128" else 2e-5
     cdt = torch.complex128 if dtype == "c128" else torch.complex64
     f = inputs.rhs_batch(n, d, nrhs, config=81)
