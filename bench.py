@@ -426,13 +426,19 @@ def run_mix(args, tb, inputs, torch, np) -> dict:
                 core_ms += ms
         p.set_timing(False)
     core_tf = core_flops / (core_ms * 1e-3) / 1e12
-    mfma_peak = 157.3
+    # algorithmic core bytes per step: every BF16 core entry once per
+    # direction plus the FP32 input and output vectors of the contraction
+    core_bytes = sum(2 * (4 * i["core_entries"] + 8 * m * (i["core_rows"] + i["core_cols"]))
+                     for i, m in zip(infos, counts))
+    mfma_peak = 2500.0  # dense BF16 matrix-core peak
     roofline = {
         "bound": "mfma", "achieved": round(core_tf, 2), "peak": mfma_peak, "unit": "TFLOP/s",
         "frac": round(core_tf / mfma_peak, 4), "traffic": None,
-        "kernel": "core_fwd_mfma + core_adj_mfma (BF16 cores widened to FP32, "
-                  "v_mfma_f32_16x16x4f32, complex as four real products)",
+        "kernel": "core_fwd_mfma_bf16 + core_adj_mfma_bf16 (BF16 cores, right-hand sides "
+                  "split into BF16 hi + lo, v_mfma_f32_16x16x32_bf16, FP32 accumulation)",
         "flops_per_step": core_flops, "ms_per_step_events": round(core_ms, 3),
+        "core_hbm_GBs": round(core_bytes / (core_ms * 1e-3) / 1e9, 1),
+        "core_hbm_frac": round(core_bytes / (core_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
     stage_ms = {k: {"ms": round(v[0], 3), "launches": v[2],
                     "TFLOP/s": round(v[1] / (v[0] * 1e-3) / 1e12, 2)} for k, v in fam.items()}

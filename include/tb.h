@@ -197,7 +197,9 @@ typedef struct {
   int outputs_per_thread; /* transfer stages: 1 or 8 */
   int rhs_tile;           /* transfer stages: right-hand sides per workgroup, 1/2/4/8 */
   int whole_blocks;       /* transfer stages: 1 = one workgroup per block (no slices) */
-  int core_kernel;        /* core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = matrix cores */
+  int core_kernel;        /* core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = FP32 matrix
+                             cores; 4 = BF16 matrix cores (BF16 applies; right-hand sides split
+                             into bf16 hi + lo) */
   int fanin_in_turn;      /* fan-in stages: 1 = children in turn, first mode in registers */
   int transfer_mfma;      /* transfer levels (not the leaves), FP32 / BF16 applies: 1 = mode
                              products on the matrix cores, one block per workgroup */

@@ -840,6 +840,18 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // ------------------------------------------------------------------ core --
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  This
+// maps workgroup b of n to work item u so that every XCD gets one contiguous
+// range of items: items that share data (the right-hand-side tiles of one
+// core panel, enumerated next to each other) then meet in the same L2.  A
+// bijection on [0, n) for any n.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  const int x = b % kXcds, i = b / kXcds;
+  const int q = n / kXcds, r = n % kXcds;
+  return x * q + min(x, r) + i;
+}
+
 struct CoreArgs {
   long long nS, nT;              // middle multi-sets per side
   long long Es, Et;              // entries per top-level item (source / target)
@@ -1410,7 +1422,10 @@ __global__ void __launch_bounds__(kThreads)
                   const int* __restrict__ meta, const int2* __restrict__ units,
                   const float2* __restrict__ F, float2* __restrict__ G) {
   __shared__ float2 fs[kMKC * kMQ];
-  const int2 u = units[blockIdx.x];
+  // flattened (unit, RHS tile) with the tile fastest, XCD-contiguous
+  const int nqt = (a.nrhs + kMQ - 1) / kMQ;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int2 u = units[item / nqt];
   const int pair = u.x, r0 = u.y;
   const int* m = meta + pair * kPairMeta;
   const int RT = m[0], RS = m[1], RTp = m[2];
@@ -1422,7 +1437,7 @@ __global__ void __launch_bounds__(kThreads)
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
-  const int q0 = blockIdx.y * kMQ;
+  const int q0 = (item % nqt) * kMQ;
   const int Qa = min(kMQ, a.nrhs - q0);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const CS* cb = cores + core_off[pair];
@@ -1494,7 +1509,10 @@ __global__ void __launch_bounds__(kThreads)
   constexpr int kLd = kMKA + 1;                 // padded column length in LDS
   __shared__ float2 cs_[kCols * kLd];
   __shared__ float2 gs[kMKA * kMQ];
-  const int2 u = units[blockIdx.x];
+  // flattened (unit, RHS tile) with the tile fastest, XCD-contiguous
+  const int nqt = (a.nrhs + kMQ - 1) / kMQ;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int2 u = units[item / nqt];
   const int pair = u.x, c0 = u.y;
   const int* m = meta + pair * kPairMeta;
   const int RT = m[0], RS = m[1], RTp = m[2];
@@ -1506,7 +1524,7 @@ __global__ void __launch_bounds__(kThreads)
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
-  const int q0 = blockIdx.y * kMQ;
+  const int q0 = (item % nqt) * kMQ;
   const int Qa = min(kMQ, a.nrhs - q0);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const CS* cb = cores + core_off[pair];
@@ -1550,6 +1568,238 @@ __global__ void __launch_bounds__(kThreads)
         av.y = -av.y;  // conj(C)
 #pragma unroll
         for (int c = 0; c < 2; ++c) cmfma(accr[i][c], acci[i][c], av, bv[c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) {
+    if (!live[i]) continue;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = c0 + (w + 4 * i) * 16 + 4 * (lane >> 4) + j;
+        const int q = c * 16 + (lane & 15);
+        if (col < RS && q < Qa)
+          F[(sitem * a.Es + padded_pos<D>(col, rs, a.Rs)) * a.nrhs + q0 + q] =
+              make_float2(accr[i][c][j], acci[i][c][j]);
+      }
+  }
+}
+
+// BF16 cores on BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation).  A complex product is one real product per output part
+// with real and imaginary parts interleaved along k: with k' = 2 k + p,
+//   forward  Gr: A = (Cr, -Ci), Gi: A = (Ci, Cr), B = (Fr, Fi);
+//   adjoint  Fr: A = (Cr, Ci),  Fi: A = (-Ci, Cr), B = (Gr, Gi)  (conj(C)).
+// A stored core is one 32-bit word (bf16 re low, bf16 im high), so each A
+// pair is the word itself, the word with a sign bit flipped, or the word
+// with its halves swapped.  The FP32 right-hand sides are split into
+// bf16 hi + lo (two products), so their rounding (about 2^-17) stays far
+// below that of the BF16 cores.  Lane layout: lane l supplies A[l % 16][8 (l
+// / 16) + i] and B[8 (l / 16) + i][l % 16], i = 0..7; accumulator register j
+// holds D[4 (l / 16) + j][l % 16].
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+constexpr int kBK = 64;       // complex k staged per chunk
+constexpr int kBLd = kBK + 4;  // LDS row stride in words: 16-byte aligned, 2-way banked
+
+__device__ __forceinline__ unsigned pack_bf16(float re, float im) {
+  return (unsigned)f32_to_bf16(re) | ((unsigned)f32_to_bf16(im) << 16);
+}
+__device__ __forceinline__ void split_bf16(float2 v, unsigned* hi, unsigned* lo) {
+  const unsigned h = pack_bf16(v.x, v.y);
+  *hi = h;
+  *lo = pack_bf16(v.x - bf16_to_f32((unsigned short)(h & 0xffff)),
+                  v.y - bf16_to_f32((unsigned short)(h >> 16)));
+}
+__device__ __forceinline__ v8bf as_v8bf(uint4 u) { return __builtin_bit_cast(v8bf, u); }
+__device__ __forceinline__ unsigned swap16(unsigned u) { return (u >> 16) | (u << 16); }
+__device__ __forceinline__ v4f mfma_bf16(v8bf a, v8bf b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Forward: 256 rows of one pair (4 waves x kMT 16-row tiles) and kMQ
+// right-hand sides per workgroup; F staged through LDS as bf16 hi/lo,
+// [q][k] so that a lane's 8 k-values are one 16-byte read.
+template <int D>
+__global__ void __launch_bounds__(kThreads)
+    core_fwd_mfma_bf16(CoreArgs a, const unsigned* __restrict__ cores, const long long* __restrict__ core_off,
+                       const int* __restrict__ meta, const int2* __restrict__ units,
+                       const float2* __restrict__ F, float2* __restrict__ G) {
+  __shared__ uint4 fhi[kMQ * kBLd / 4], flo[kMQ * kBLd / 4];
+  // flattened (unit, RHS tile) with the tile fastest, XCD-contiguous
+  const int nqt = (a.nrhs + kMQ - 1) / kMQ;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int2 u = units[item / nqt];
+  const int pair = u.x, r0 = u.y;
+  const int* m = meta + pair * kPairMeta;
+  const int RT = m[0], RS = m[1], RTp = m[2];
+  int rt[D], rs[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    rt[k] = m[3 + k];
+    rs[k] = m[6 + k];
+  }
+  const long long t = pair / a.nS, s = pair % a.nS;
+  const long long sitem = s * a.nT + t, titem = t * a.nS + s;
+  const int q0 = (item % nqt) * kMQ;
+  const int Qa = min(kMQ, a.nrhs - q0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned* cb = cores + core_off[pair];
+  unsigned* fh = reinterpret_cast<unsigned*>(fhi);
+  unsigned* fl = reinterpret_cast<unsigned*>(flo);
+  v4f accr[kMT][2], acci[kMT][2];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      accr[i][c] = v4f{0, 0, 0, 0};
+      acci[i][c] = v4f{0, 0, 0, 0};
+    }
+  int rowc[kMT];
+  bool live[kMT];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) {
+    const int tile0 = r0 + (w + 4 * i) * 16;
+    live[i] = tile0 < RT;
+    rowc[i] = min(tile0 + (lane & 15), RTp - 1);
+  }
+  for (int kc = 0; kc < RS; kc += kBK) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kBK * kMQ; idx += kThreads) {
+      const int kk = idx / kMQ, q = idx % kMQ, k = kc + kk;  // q fastest: coalesced reads
+      const float2 v = (k < RS && q < Qa) ? F[(sitem * a.Es + padded_pos<D>(k, rs, a.Rs)) * a.nrhs + q0 + q]
+                                          : make_float2(0.f, 0.f);
+      split_bf16(v, &fh[q * kBLd + kk], &fl[q * kBLd + kk]);
+    }
+    __syncthreads();
+    const int kend = min(kBK, RS - kc);
+    for (int ks = 0; ks < kend; ks += 16) {
+      const int kl = ks + 4 * (lane >> 4);  // first of this lane's 4 complex k
+      uint4 bh[2], bl[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int q = c * 16 + (lane & 15);
+        bh[c] = fhi[(q * kBLd + kl) / 4];
+        bl[c] = flo[(q * kBLd + kl) / 4];
+      }
+#pragma unroll
+      for (int i = 0; i < kMT; ++i) {
+        if (!live[i]) continue;
+        unsigned cw[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cw[e] = cb[(long long)min(kc + kl + e, RS - 1) * RTp + rowc[i]];
+        const v8bf ar = as_v8bf(make_uint4(cw[0] ^ 0x80000000u, cw[1] ^ 0x80000000u, cw[2] ^ 0x80000000u,
+                                           cw[3] ^ 0x80000000u));
+        const v8bf ai = as_v8bf(make_uint4(swap16(cw[0]), swap16(cw[1]), swap16(cw[2]), swap16(cw[3])));
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          accr[i][c] = mfma_bf16(ar, as_v8bf(bh[c]), accr[i][c]);
+          accr[i][c] = mfma_bf16(ar, as_v8bf(bl[c]), accr[i][c]);
+          acci[i][c] = mfma_bf16(ai, as_v8bf(bh[c]), acci[i][c]);
+          acci[i][c] = mfma_bf16(ai, as_v8bf(bl[c]), acci[i][c]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) {
+    if (!live[i]) continue;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = r0 + (w + 4 * i) * 16 + 4 * (lane >> 4) + j;
+        const int col = c * 16 + (lane & 15);
+        if (row < RT && col < Qa)
+          G[(titem * a.Et + padded_pos<D>(row, rt, a.Rt)) * a.nrhs + q0 + col] =
+              make_float2(accr[i][c][j], acci[i][c][j]);
+      }
+  }
+}
+
+// Adjoint: 256 columns of one pair and kMQ right-hand sides per workgroup;
+// a lane's 4 consecutive rows of its column are one 16-byte load (the cores
+// are column-major), G staged through LDS as bf16 hi/lo, [q][row].
+template <int D>
+__global__ void __launch_bounds__(kThreads)
+    core_adj_mfma_bf16(CoreArgs a, const unsigned* __restrict__ cores, const long long* __restrict__ core_off,
+                       const int* __restrict__ meta, const int2* __restrict__ units,
+                       const float2* __restrict__ G, float2* __restrict__ F) {
+  __shared__ uint4 ghi[kMQ * kBLd / 4], glo[kMQ * kBLd / 4];
+  // flattened (unit, RHS tile) with the tile fastest, XCD-contiguous
+  const int nqt = (a.nrhs + kMQ - 1) / kMQ;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int2 u = units[item / nqt];
+  const int pair = u.x, c0 = u.y;
+  const int* m = meta + pair * kPairMeta;
+  const int RT = m[0], RS = m[1], RTp = m[2];
+  int rt[D], rs[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    rt[k] = m[3 + k];
+    rs[k] = m[6 + k];
+  }
+  const long long t = pair / a.nS, s = pair % a.nS;
+  const long long sitem = s * a.nT + t, titem = t * a.nS + s;
+  const int q0 = (item % nqt) * kMQ;
+  const int Qa = min(kMQ, a.nrhs - q0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned* cb = cores + core_off[pair];
+  unsigned* gh = reinterpret_cast<unsigned*>(ghi);
+  unsigned* gl = reinterpret_cast<unsigned*>(glo);
+  v4f accr[kMT][2], acci[kMT][2];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      accr[i][c] = v4f{0, 0, 0, 0};
+      acci[i][c] = v4f{0, 0, 0, 0};
+    }
+  int colc[kMT];
+  bool live[kMT];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) {
+    const int tile0 = c0 + (w + 4 * i) * 16;
+    live[i] = tile0 < RS;
+    colc[i] = min(tile0 + (lane & 15), RS - 1);
+  }
+  for (int kc = 0; kc < RT; kc += kBK) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kBK * kMQ; idx += kThreads) {
+      const int kk = idx / kMQ, q = idx % kMQ, k = kc + kk;
+      const float2 v = (k < RT && q < Qa) ? G[(titem * a.Et + padded_pos<D>(k, rt, a.Rt)) * a.nrhs + q0 + q]
+                                          : make_float2(0.f, 0.f);
+      split_bf16(v, &gh[q * kBLd + kk], &gl[q * kBLd + kk]);
+    }
+    __syncthreads();
+    const int kend = min(kBK, RT - kc);
+    for (int ks = 0; ks < kend; ks += 16) {
+      const int kl = ks + 4 * (lane >> 4);
+      // rows kc + kl .. + 3: inside the padded column (RTp is a multiple of
+      // 4); past it the staged G is zero, so any finite row does
+      const int kr = min(kc + kl, RTp - 4);
+      uint4 bh[2], bl[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int q = c * 16 + (lane & 15);
+        bh[c] = ghi[(q * kBLd + kl) / 4];
+        bl[c] = glo[(q * kBLd + kl) / 4];
+      }
+#pragma unroll
+      for (int i = 0; i < kMT; ++i) {
+        if (!live[i]) continue;
+        const uint4 cw = *reinterpret_cast<const uint4*>(cb + (long long)colc[i] * RTp + kr);
+        const v8bf ar = as_v8bf(cw);
+        const v8bf ai = as_v8bf(make_uint4(swap16(cw.x) ^ 0x8000u, swap16(cw.y) ^ 0x8000u,
+                                           swap16(cw.z) ^ 0x8000u, swap16(cw.w) ^ 0x8000u));
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          accr[i][c] = mfma_bf16(ar, as_v8bf(bh[c]), accr[i][c]);
+          accr[i][c] = mfma_bf16(ar, as_v8bf(bl[c]), accr[i][c]);
+          acci[i][c] = mfma_bf16(ai, as_v8bf(bh[c]), acci[i][c]);
+          acci[i][c] = mfma_bf16(ai, as_v8bf(bl[c]), acci[i][c]);
+        }
       }
     }
   }
@@ -2331,13 +2581,27 @@ constexpr int kMfmaMinRhs = 8;   // from this many right-hand sides the matrix c
 
 template <class CS, int D>
 static tb_status launch_core_mfma(const Plan& p, const CoreArgs& a, bool adjoint, const void* cores,
-                                  const void* in, void* out, hipStream_t stream) {
+                                  const void* in, void* out, hipStream_t stream, bool bf16_mfma = false) {
   const unsigned gy = (unsigned)((a.nrhs + kMQ - 1) / kMQ);
+  if constexpr (sizeof(CS) == 4) {
+    if (bf16_mfma) {
+      if (!adjoint)
+        core_fwd_mfma_bf16<D><<<dim3((unsigned)p.mfma_fwd_units.size() * gy), kThreads, 0, stream>>>(
+            a, (const unsigned*)cores, p.core_off_d, p.pair_meta_d, p.mfma_fwd_units_d, (const float2*)in,
+            (float2*)out);
+      else
+        core_adj_mfma_bf16<D><<<dim3((unsigned)p.mfma_adj_units.size() * gy), kThreads, 0, stream>>>(
+            a, (const unsigned*)cores, p.core_off_d, p.pair_meta_d, p.mfma_adj_units_d, (const float2*)in,
+            (float2*)out);
+      TB_HIP_TRY(hipGetLastError());
+      return TB_OK;
+    }
+  }
   if (!adjoint)
-    core_fwd_mfma<CS, D><<<dim3((unsigned)p.mfma_fwd_units.size(), gy), kThreads, 0, stream>>>(
+    core_fwd_mfma<CS, D><<<dim3((unsigned)p.mfma_fwd_units.size() * gy), kThreads, 0, stream>>>(
         a, (const CS*)cores, p.core_off_d, p.pair_meta_d, p.mfma_fwd_units_d, (const float2*)in, (float2*)out);
   else
-    core_adj_mfma<CS, D><<<dim3((unsigned)p.mfma_adj_units.size(), gy), kThreads, 0, stream>>>(
+    core_adj_mfma<CS, D><<<dim3((unsigned)p.mfma_adj_units.size() * gy), kThreads, 0, stream>>>(
         a, (const CS*)cores, p.core_off_d, p.pair_meta_d, p.mfma_adj_units_d, (const float2*)in, (float2*)out);
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;
@@ -2363,6 +2627,13 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
   for (long long pr = 0; pr < p.npairs; ++pr) {
     maxRS = std::max(maxRS, p.pair_meta[(size_t)pr * kPairMeta + 1]);
     maxRTp = std::max(maxRTp, p.pair_meta[(size_t)pr * kPairMeta + 2]);
+  }
+  if constexpr (sizeof(CS) == 4) {  // BF16 cores
+    if (cfg.core == 4 || (cfg.core == 0 && nrhs >= kMfmaMinRhs))
+      return d == 2 ? launch_core_mfma<CS, 2>(p, a, adjoint, cores, in, out, stream, true)
+                    : launch_core_mfma<CS, 3>(p, a, adjoint, cores, in, out, stream, true);
+  } else {
+    if (cfg.core == 4) return fail(TB_ERR_UNSUPPORTED, "BF16 matrix cores need BF16 cores");
   }
   if constexpr (sizeof(T) == 4) {
     if (cfg.core == 3 || (cfg.core == 0 && nrhs >= kMfmaMinRhs))
@@ -2574,11 +2845,11 @@ tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs, tb_dtype
 }
 
 // ------------------------------------------------------------ autotuner --
-// For every kernel launch of both directions the candidate configurations
-// are timed (one warm-up, then the best of kTuneReps launches, HIP events)
-// on zero-filled buffers of the requested shape, and the fastest is kept in
-// p.tuned[(io, nrhs)].  Launches are independent of the data, so each slot
-// is tuned in place of its position in the sequence.
+// For every kernel launch of both directions, in sequence order, the
+// candidate configurations are timed (one fitting run, then the best of
+// kTuneReps launches under HIP events, each preceded by the launches before
+// it with their chosen configurations) on zero-filled buffers of the
+// requested shape, and the fastest is kept in p.tuned[(io, nrhs)].
 constexpr int kTuneReps = 3;
 
 static uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
@@ -2649,6 +2920,10 @@ static std::vector<LaunchCfg> core_candidates(long long nrhs, tb_dtype io) {
   }
   if (io != TB_C128 && io != TB_C64_OTF && nrhs >= 4) {
     c.core = 3;
+    out.push_back(c);
+  }
+  if (io == TB_CBF16 && nrhs >= 4) {
+    c.core = 4;
     out.push_back(c);
   }
   return out;
@@ -2734,6 +3009,7 @@ static tb_status tune_typed(Plan& p, tb_dtype io, long long nrhs, hipStream_t st
     if (st != TB_OK) break;
     check(hipMemsetAsync(bin, 0, bytes, stream), "hipMemsetAsync");
     check(hipMemsetAsync(p.ws.base, 0, p.ws.bytes, stream), "hipMemsetAsync");
+    const int base = dir * steps_per_direction(p);
     for (size_t i = 0; i < steps.size() && st == TB_OK; ++i) {
       const auto cands = steps[i].core ? core_candidates(nrhs, io) : stage_candidates(nrhs, steps[i].fanout, io != TB_C128);
       float best_ms = 1e30f;
@@ -2745,6 +3021,10 @@ static tb_status tune_typed(Plan& p, tb_dtype io, long long nrhs, hipStream_t st
         }
         float ms = 1e30f;
         for (int r = 0; r < kTuneReps && st == TB_OK; ++r) {
+          // the launches before this one, with their chosen configurations,
+          // so that the candidate meets the input and cache state of a real
+          // apply rather than its own previous run
+          for (size_t k = 0; k < i && st == TB_OK; ++k) st = steps[k].run((*best)[base + k]);
           check(hipEventRecord(e0, stream), "hipEventRecord");
           st = st == TB_OK ? steps[i].run(c) : st;
           check(hipEventRecord(e1, stream), "hipEventRecord");
@@ -2760,7 +3040,7 @@ static tb_status tune_typed(Plan& p, tb_dtype io, long long nrhs, hipStream_t st
         }
       }
       if (st == TB_OK && best_ms >= 1e29f) st = fail(TB_ERR_UNSUPPORTED, "no launch configuration fits");
-      (*best)[dir * steps_per_direction(p) + i] = pick;
+      (*best)[base + i] = pick;
     }
   }
   p.timing = was_timing;
@@ -2983,7 +3263,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   if (slot < 0 || slot >= nslots) return tb::fail(TB_ERR_INVALID_ARG, "launch slot out of range");
   const int g = cfg->outputs_per_thread, q = cfg->rhs_tile;
   if (!(g == 0 || g == 1 || g == 8) || !(q == 0 || q == 1 || q == 2 || q == 4 || q == 8) ||
-      cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 3 ||
+      cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 4 ||
       cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 1 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1)
     return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");
   auto& v = p->tuned[{(int)io, nrhs}];

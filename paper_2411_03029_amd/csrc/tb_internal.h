@@ -96,7 +96,8 @@ struct LaunchCfg {
   int G = 0;      // transfer: outputs per thread along the new mode (1 or 8)
   int QT = 0;     // transfer: right-hand sides per workgroup (1, 2, 4, 8)
   int split = 0;  // transfer: 1 = one workgroup per block (no slicing)
-  int core = 0;   // core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = MFMA
+  int core = 0;   // core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = FP32 MFMA;
+                  // 4 = BF16 MFMA (BF16 cores)
   int alt = 0;    // fan-in: 1 = children in turn, mode 0 in registers
   int mfma = 0;   // transfer levels: 1 = mode products on the matrix cores
 };

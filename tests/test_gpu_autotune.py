@@ -75,6 +75,8 @@ def _candidates(stage, nrhs, dtype):
             out.append(dict(core_kernel=2))
         if dtype not in ("c128", "c64otf") and nrhs >= 4:
             out.append(dict(core_kernel=3))
+        if dtype == "cbf16" and nrhs >= 4:
+            out.append(dict(core_kernel=4))
         return out
     fanout = stage in ("src_leaf", "src_transfer", "tgt_leaf_adj", "tgt_transfer_adj")
     out = []
@@ -97,6 +99,7 @@ def _candidates(stage, nrhs, dtype):
     (kernels.RADON, 2, 32, 1e-3, 8, 9, "c64"),
     (kernels.FOURIER, 2, 64, 1e-6, 8, 1, "c64"),
     (kernels.HELMHOLTZ, 3, 32, 1e-4, 8, 6, "c64otf"),
+    (kernels.RADON, 2, 32, 1e-3, 8, 20, "cbf16"),
 ])
 def test_every_launch_candidate_matches_oracle(kind, d, n, tol, leaf, nrhs, dtype, tmp_path):
     # each slot in turn runs each of its candidates (the rest keep the
@@ -108,8 +111,8 @@ def test_every_launch_candidate_matches_oracle(kind, d, n, tol, leaf, nrhs, dtyp
     op = bf.construct(Operator(kind, d, n, omega=om), tol, leaf=leaf)
     path = str(tmp_path / "p.tbplan")
     planio.save_plan(op, path)
-    store = {"c128": ("c128",), "c64": ("c64",), "c64otf": ("otf",)}[dtype]
-    bound = 1e-12 if dtype == "c128" else 2e-5
+    store = {"c128": ("c128",), "c64": ("c64",), "c64otf": ("otf",), "cbf16": ("cbf16",)}[dtype]
+    bound = {"c128": 1e-12, "cbf16": 5e-3}.get(dtype, 2e-5)
     cdt = torch.complex128 if dtype == "c128" else torch.complex64
     f = inputs.rhs_batch(n, d, nrhs, config=81)
     x = to_dev(f, cdt)
