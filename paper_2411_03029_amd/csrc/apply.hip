@@ -193,15 +193,30 @@ __device__ __forceinline__ void gzero(C (&acc)[G]) {
 }
 
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+// xcd_item maps workgroup b of n to work item u so that groups of g
+// consecutive items (items that share data: the right-hand-side tiles of
+// one block or core panel) run back to back on one XCD, while successive
+// groups still go round-robin over the XCDs (irregular work stays balanced).
+// The tail that does not fill 8 whole groups keeps the identity map; a
+// bijection on [0, n) for any n and g.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int b, int n, int g) {
+  const int span = kXcds * g;
+  if (g <= 1 || b >= n / span * span) return b;
+  const int x = b % kXcds, i = b / kXcds;  // i-th workgroup on XCD x
+  return ((i / g) * kXcds + x) * g + i % g;
+}
+
 // Workgroup -> (block, slice, right-hand-side tile); the tile index runs
-// fastest so that workgroups sharing cache lines of the q-innermost
-// intermediates are dispatched together.
+// fastest and the enumeration is XCD-contiguous, so that workgroups sharing
+// cache lines of the q-innermost intermediates run in the same L2.
 struct StageBid {
   int item_blk, split, q0;
 };
 __device__ __forceinline__ StageBid stage_bid(const StageArgs& a, int QT) {
   const int nqt = (a.nrhs + QT - 1) / QT;
-  int bid = blockIdx.x;
+  int bid = xcd_item(blockIdx.x, gridDim.x, nqt * a.nsplit);
   StageBid s;
   s.q0 = (bid % nqt) * QT;
   bid /= nqt;
@@ -840,18 +855,6 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // ------------------------------------------------------------------ core --
-// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  This
-// maps workgroup b of n to work item u so that every XCD gets one contiguous
-// range of items: items that share data (the right-hand-side tiles of one
-// core panel, enumerated next to each other) then meet in the same L2.  A
-// bijection on [0, n) for any n.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_item(int b, int n) {
-  const int x = b % kXcds, i = b / kXcds;
-  const int q = n / kXcds, r = n % kXcds;
-  return x * q + min(x, r) + i;
-}
-
 struct CoreArgs {
   long long nS, nT;              // middle multi-sets per side
   long long Es, Et;              // entries per top-level item (source / target)
@@ -1424,7 +1427,7 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ float2 fs[kMKC * kMQ];
   // flattened (unit, RHS tile) with the tile fastest, XCD-contiguous
   const int nqt = (a.nrhs + kMQ - 1) / kMQ;
-  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int item = xcd_item(blockIdx.x, gridDim.x, nqt);
   const int2 u = units[item / nqt];
   const int pair = u.x, r0 = u.y;
   const int* m = meta + pair * kPairMeta;
@@ -1511,7 +1514,7 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ float2 gs[kMKA * kMQ];
   // flattened (unit, RHS tile) with the tile fastest, XCD-contiguous
   const int nqt = (a.nrhs + kMQ - 1) / kMQ;
-  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int item = xcd_item(blockIdx.x, gridDim.x, nqt);
   const int2 u = units[item / nqt];
   const int pair = u.x, c0 = u.y;
   const int* m = meta + pair * kPairMeta;
@@ -1629,7 +1632,7 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ uint4 fhi[kMQ * kBLd / 4], flo[kMQ * kBLd / 4];
   // flattened (unit, RHS tile) with the tile fastest, XCD-contiguous
   const int nqt = (a.nrhs + kMQ - 1) / kMQ;
-  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int item = xcd_item(blockIdx.x, gridDim.x, nqt);
   const int2 u = units[item / nqt];
   const int pair = u.x, r0 = u.y;
   const int* m = meta + pair * kPairMeta;
@@ -1729,7 +1732,7 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ uint4 ghi[kMQ * kBLd / 4], glo[kMQ * kBLd / 4];
   // flattened (unit, RHS tile) with the tile fastest, XCD-contiguous
   const int nqt = (a.nrhs + kMQ - 1) / kMQ;
-  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int item = xcd_item(blockIdx.x, gridDim.x, nqt);
   const int2 u = units[item / nqt];
   const int pair = u.x, c0 = u.y;
   const int* m = meta + pair * kPairMeta;
