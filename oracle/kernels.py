@@ -16,14 +16,20 @@ fourier    K = exp(-2 pi i x.k) with x = i/n (spatial target) and k = j - n/2
            the roles of the two grids swapped and the sign flipped; the phase
            x.k = (i.k)/n is reduced exactly in integers before the
            exponential.
-helmholtz  K = exp(+i w rho)/rho, rho = |x - y|, x = i/n, y = j/n + (2,0,0):
-           two unit cubes whose centres are 2 apart along x1 (section 4.1,
-           with the offset along x1 and the +i w rho sign).
-radon      K = exp(2 pi i (x.k + sqrt(c1(x)^2 k1^2 + c2(x)^2 k2^2))), d = 2,
-           x = i/n, k = j - n/2, c1 = (a + b sin(2 pi x1) sin(2 pi x2))/den,
-           c2 = (a + b cos(2 pi x1) cos(2 pi x2))/den (equation for the 2-D
-           generalized Radon transform in section 4.2; the paper uses
-           a=2, b=1, den=16, the workloads here use den=3).
+helmholtz  K = exp(+i w rho)/rho, rho = |x - y| (the +i w rho sign throughout).
+           d = 3: x = i/n, y = j/n + (2,0,0), two unit cubes whose centres are
+           2 apart along x1 (section 4.1, offset along x1).
+           d = 2: x = (i/n, 0), y = (j/n, 1), two parallel facing unit
+           plates at distance 1 (the example of section 3.2 and the first
+           Green's function test of section 4.1).
+radon      K = exp(2 pi i phi(x, k)), x = i/n, k = j - n/2 (section 4.2).
+           d = 2: phi = x.k + sqrt(c1(x)^2 k1^2 + c2(x)^2 k2^2),
+           c1 = (a + b sin(2 pi x1) sin(2 pi x2))/den,
+           c2 = (a + b cos(2 pi x1) cos(2 pi x2))/den; the paper uses a=2,
+           b=1, den=16, the workloads here den=3 (the default).
+           d = 3: phi = x.k + c(x)|k|,
+           c = (a + b sin(2 pi x1) sin(2 pi x2) sin(2 pi x3))/den with the
+           paper's a=3, b=1, den=100 as the default.
 """
 from __future__ import annotations
 
@@ -46,9 +52,15 @@ class Operator:
     d: int
     n: int
     omega: float = 0.0          # Helmholtz wavenumber (ignored otherwise)
-    radon_a: float = 2.0        # Radon speed constants (ignored otherwise)
-    radon_b: float = 1.0
-    radon_den: float = 3.0
+    radon_a: float | None = None  # Radon constants (ignored otherwise);
+    radon_b: float | None = None  # None: (2, 1, 3) for d = 2, (3, 1, 100)
+    radon_den: float | None = None  # for d = 3
+
+    def __post_init__(self):
+        a, b, den = radon_defaults(self.d)
+        for name, v in (("radon_a", a), ("radon_b", b), ("radon_den", den)):
+            if getattr(self, name) is None:
+                object.__setattr__(self, name, v)
 
     def entries(self, ti: np.ndarray, sj: np.ndarray) -> np.ndarray:
         """K(x^i, y^j) for broadcastable integer arrays of shape (..., d)."""
@@ -62,6 +74,11 @@ class Operator:
             return radon_entries(self.n, ti, sj, self.radon_a, self.radon_b,
                                  self.radon_den)
         raise ValueError(f"unknown kernel kind {self.kind}")
+
+
+def radon_defaults(d: int) -> tuple:
+    """(a, b, den) of the Radon speed function when none are given."""
+    return (2.0, 1.0, 3.0) if d == 2 else (3.0, 1.0, 100.0)
 
 
 def helmholtz_omega(n: int) -> float:
@@ -84,19 +101,31 @@ def fourier_entries(n: int, ti: np.ndarray, sj: np.ndarray) -> np.ndarray:
 def helmholtz_entries(n: int, omega: float, ti: np.ndarray,
                       sj: np.ndarray) -> np.ndarray:
     d = ti.shape[-1]
-    offset = np.zeros(d)
-    offset[0] = 2.0
+    if d == 3:      # cubes: y offset by 2 along x1
+        offset = np.array([2.0, 0.0, 0.0])
+        gap2 = 0.0
+    elif d == 2:    # plates: in-plane coordinates, planes 1 apart
+        offset = np.zeros(2)
+        gap2 = 1.0
+    else:
+        raise ValueError("the Helmholtz geometries here are d = 2 (plates) and 3 (cubes)")
     diff = ti.astype(np.float64) / n - (sj.astype(np.float64) / n + offset)
-    rho = np.sqrt(np.sum(diff * diff, axis=-1))
+    rho = np.sqrt(np.sum(diff * diff, axis=-1) + gap2)
     return np.exp(1j * omega * rho) / rho
 
 
 def radon_entries(n: int, ti: np.ndarray, sj: np.ndarray, a: float, b: float,
                   den: float) -> np.ndarray:
-    if ti.shape[-1] != 2:
-        raise ValueError("the Radon operator here is two-dimensional")
+    d = ti.shape[-1]
     x = ti.astype(np.float64) / n
     k = (sj - n // 2).astype(np.float64)
+    if d == 3:
+        c = (a + b * np.sin(2 * np.pi * x[..., 0]) * np.sin(2 * np.pi * x[..., 1]) *
+             np.sin(2 * np.pi * x[..., 2])) / den
+        phase = np.sum(x * k, axis=-1) + c * np.sqrt(np.sum(k * k, axis=-1))
+        return np.exp(2j * np.pi * phase)
+    if d != 2:
+        raise ValueError("the Radon operators here are d = 2 and 3")
     s1 = np.sin(2 * np.pi * x[..., 0])
     s2 = np.sin(2 * np.pi * x[..., 1])
     c1 = np.cos(2 * np.pi * x[..., 0])

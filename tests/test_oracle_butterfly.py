@@ -49,10 +49,24 @@ def radon32():
     return bf.construct(Operator(kernels.RADON, 2, 32), 1e-3)
 
 
+@pytest.fixture(scope="module")
+def plates64():
+    """Two parallel facing plates (d = 2), n = 64, tol 1e-6."""
+    n = 64
+    return bf.construct(Operator(kernels.HELMHOLTZ, 2, n, omega=kernels.helmholtz_omega(n)), 1e-6)
+
+
+@pytest.fixture(scope="module")
+def radon3_16():
+    """3-D Radon transform, n = 16, leaf 4, tol 1e-3."""
+    return bf.construct(Operator(kernels.RADON, 3, 16), 1e-3, leaf=4)
+
+
 def test_full_rank_limit_is_exact():
     # proxies = whole nodes and eps ~ 0: every ID is exact, so is the product
     for kind, d, n in [(kernels.FOURIER, 2, 16), (kernels.RADON, 2, 16),
-                       (kernels.HELMHOLTZ, 3, 8), (kernels.HELMHOLTZ, 2, 16)]:
+                       (kernels.HELMHOLTZ, 3, 8), (kernels.HELMHOLTZ, 2, 16),
+                       (kernels.RADON, 3, 8)]:
         om = kernels.helmholtz_omega(n) if kind == kernels.HELMHOLTZ else 0.0
         op = Operator(kind, d, n, omega=om)
         plan = bf.construct(op, 1e-13, leaf=4 if n == 8 else 8, p_pair=0,
@@ -89,7 +103,21 @@ def test_radon32_meets_tolerance(radon32):
     assert _relerr(bf.apply_adjoint(radon32, f), dense.adjoint_brute(op, f)) <= 1e-3
 
 
-@pytest.mark.parametrize("which", ["fourier64", "helm32", "radon32"])
+def test_plates64_meets_tolerance(plates64):
+    op = plates64.op
+    f = _rand((2, 64, 64), 4)
+    assert _relerr(bf.apply(plates64, f), dense.apply_helmholtz_fft(op, f)) <= 1e-6
+    assert _relerr(bf.apply_adjoint(plates64, f), dense.adjoint_helmholtz_fft(op, f)) <= 1e-6
+
+
+def test_radon3_meets_tolerance(radon3_16):
+    op = radon3_16.op
+    f = _rand((1, 16, 16, 16), 5)
+    assert _relerr(bf.apply(radon3_16, f), dense.apply_brute(op, f)) <= 1e-3
+    assert _relerr(bf.apply_adjoint(radon3_16, f), dense.adjoint_brute(op, f)) <= 1e-3
+
+
+@pytest.mark.parametrize("which", ["fourier64", "helm32", "radon32", "plates64", "radon3_16"])
 def test_adjoint_identity_and_linearity(which, request):
     plan = request.getfixturevalue(which)
     shape = (1,) + (plan.n,) * plan.d

@@ -132,3 +132,74 @@ def test_probe_error_metric_zero_for_exact_apply():
     op = Operator(kernels.FOURIER, d, n)
     err = dense.probe_error(op, lambda fe: dense.apply_fourier_fft(n, d, fe))
     assert err < 1e-13
+
+
+# ----------------------------------------- parallel plates, 3-D Radon --
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_plates_fft_convolution_equals_brute(n):
+    # plates (d = 2): K depends on the in-plane offset only, so the FFT
+    # convolution route applies; pinned to brute force
+    op = Operator(kernels.HELMHOLTZ, 2, n, omega=kernels.helmholtz_omega(n))
+    f = _rand((2, n, n), 11)
+    np.testing.assert_allclose(dense.apply_helmholtz_fft(op, f),
+                               dense.apply_brute(op, f), rtol=0, atol=1e-10)
+    g = _rand((2, n, n), 12)
+    np.testing.assert_allclose(dense.adjoint_helmholtz_fft(op, g),
+                               dense.adjoint_brute(op, g), rtol=0, atol=1e-10)
+
+
+def test_plates_special_values():
+    # facing points (i = j) are the plate distance 1 apart: K = exp(i omega);
+    # with n = 8, omega = 4 pi and K = 1.  An in-plane offset of (3, 4)/8
+    # gives rho = sqrt(1 + 25/64) = sqrt(89)/8.
+    n = 8
+    om = kernels.helmholtz_omega(n)
+    ti = np.array([[2, 5]])
+    assert kernels.helmholtz_entries(n, om, ti, ti)[0] == pytest.approx(1.0, abs=1e-13)
+    val = kernels.helmholtz_entries(n, om, np.array([[5, 7]]), np.array([[2, 3]]))[0]
+    rho = np.sqrt(89.0) / 8
+    assert abs(val) == pytest.approx(1 / rho, abs=1e-14)
+    assert np.angle(val) == pytest.approx(np.angle(np.exp(1j * om * rho)), abs=1e-12)
+    # translation invariance in the plane
+    a = kernels.helmholtz_entries(n, om, np.array([[1, 2]]), np.array([[6, 0]]))
+    b = kernels.helmholtz_entries(n, om, np.array([[2, 5]]), np.array([[7, 3]]))
+    np.testing.assert_allclose(a, b, atol=1e-14)
+
+
+def test_radon3_special_points():
+    # x = 0: c = a/den = 3/100 and K(0, k) = exp(2 pi i 0.03 |k|); for
+    # |k| = 0 it is 1; with x1 = 0 the speed is still 3/100 at any x2, x3
+    n = 16
+    op = Operator(kernels.RADON, 3, n)
+    assert (op.radon_a, op.radon_b, op.radon_den) == (3.0, 1.0, 100.0)
+    z = np.zeros((1, 3), np.int64)
+    h = n // 2
+    assert op.entries(z, np.array([[h, h, h]]))[0] == pytest.approx(1.0, abs=1e-14)
+    k = np.array([3, -4, 12])   # |k| = 13
+    assert op.entries(z, np.array([h + k]))[0] == pytest.approx(
+        np.exp(2j * np.pi * 0.03 * 13), abs=1e-13)
+    ti = np.array([[0, 5, 11]])
+    x = ti[0] / n
+    assert op.entries(ti, np.array([h + k]))[0] == pytest.approx(
+        np.exp(2j * np.pi * (x @ k + 0.03 * 13)), abs=1e-12)
+
+
+def test_radon3_without_speed_term_is_an_inverse_dft():
+    n, d = 8, 3
+    op = Operator(kernels.RADON, d, n, radon_a=0.0, radon_b=0.0)
+    f = _rand((1, n, n, n), 13)
+    axes = (1, 2, 3)
+    expect = np.fft.ifftn(np.fft.ifftshift(f, axes=axes), axes=axes) * n ** d
+    np.testing.assert_allclose(dense.apply_brute(op, f), expect, atol=1e-10)
+
+
+@pytest.mark.parametrize("kind,d,n", [(kernels.HELMHOLTZ, 2, 8), (kernels.RADON, 3, 4)])
+def test_dense_adjoint_identity_new_operators(kind, d, n):
+    om = kernels.helmholtz_omega(n) if kind == kernels.HELMHOLTZ else 0.0
+    op = Operator(kind, d, n, omega=om)
+    f = _rand((1,) + (n,) * d, 14)
+    g = _rand((1,) + (n,) * d, 15)
+    lhs = np.vdot(g, dense.apply_brute(op, f))
+    rhs = np.vdot(dense.adjoint_brute(op, g), f)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
