@@ -99,7 +99,9 @@ typedef struct {
                            TB_ERR_NUMERIC; 0 -> no limit                   */
   size_t max_device_bytes; /* > 0: cap on the plan's device memory; a plan
                               that needs more fails with TB_ERR_OOM         */
-  int radon_custom;     /* 1: use radon_a/b/den below; 0 -> a=2, b=1, den=3 */
+  int radon_custom;     /* 1: use radon_a/b/den below; 0 -> a=2, b=1, den=3
+                           (d = 2) or the section 4.2 a=3, b=1, den=100
+                           (d = 3)                                         */
   double radon_a, radon_b, radon_den;
 } tb_options;
 
@@ -128,7 +130,13 @@ typedef struct {
 } tb_plan_info_t;
 
 /* Build the factorisation on the GPU (Algorithm 1).
- *   kind, d:  operator (Fourier d in {2,3}; Helmholtz d = 3; Radon d = 2).
+ *   kind, d:  operator, d in {2, 3} for every kind.  Fourier: K =
+ *             exp(-2 pi i x.k), x = i/n, k = j - n/2 (section 4.3).
+ *             Helmholtz: exp(+i omega rho)/rho; d = 3 two unit cubes with
+ *             centres 2 apart along x1, d = 2 two parallel facing unit
+ *             plates 1 apart (section 4.1).  Radon: exp(2 pi i phi), x =
+ *             i/n, k = j - n/2; d = 2 phi = x.k + sqrt(c1^2 k1^2 + c2^2
+ *             k2^2), d = 3 phi = x.k + c |k| (section 4.2 equations).
  *   n:        points per direction; n = leaf * 2^L with L >= 0.
  *   omega:    Helmholtz wavenumber (> 0); ignored for Fourier and Radon.
  *   tol:      requested relative accuracy in (0, 1); every ID runs at

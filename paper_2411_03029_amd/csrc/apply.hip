@@ -1135,9 +1135,12 @@ __global__ void __launch_bounds__(kThreads)
 //              sum reduced exactly modulo n (a power of two), amp = 1;
 //   Helmholtz  rev = omega rho / (2 pi), amp = 1 / rho: the squared
 //              distance n^2 rho^2 is a sum of squares of integer index
-//              differences, exact in FP64, then rho via rsqrt;
-//   Radon      rev = x . k + sqrt(c1(x)^2 k1^2 + c2(x)^2 k2^2), amp = 1, in
-//              FP64 with c1(x)^2, c2(x)^2 precomputed per target point.
+//              differences (plus n^2 for the plates' separation), exact in
+//              FP64, then rho via rsqrt;
+//   Radon      d = 2: rev = x . k + sqrt(c1(x)^2 k1^2 + c2(x)^2 k2^2), with
+//              c1(x)^2, c2(x)^2 precomputed per target point; d = 3: rev =
+//              x . k + c(x) |k| with c per target and |k| per source point;
+//              amp = 1, in FP64.
 // The fraction of a turn goes to FP32 sine and cosine; the product with F
 // runs in FP32.  A point is four ints (Fourier, Helmholtz: the per-mode
 // grid indices, the source's first index shifted by 2n for the cube
@@ -1161,7 +1164,18 @@ struct OtfPoint<TB_KERNEL_RADON> {
 
 template <int KIND, int D>
 __device__ __forceinline__ typename OtfPoint<KIND>::V otf_target(const OtfSpec& o, const int* ti) {
-  if constexpr (KIND == TB_KERNEL_RADON) {
+  if constexpr (KIND == TB_KERNEL_RADON && D == 3) {
+    const double inv = 1.0 / (double)o.n;
+    double x[3], sp = 1.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      x[k] = ti[k] * inv;
+      double sk, ck;
+      sincospi(2.0 * x[k], &sk, &ck);
+      sp *= sk;
+    }
+    return make_double4(x[0], x[1], x[2], (o.ra + o.rb * sp) / o.rden);
+  } else if constexpr (KIND == TB_KERNEL_RADON) {
     const double inv = 1.0 / (double)o.n;
     const double x1 = ti[0] * inv, x2 = ti[1] * inv;
     double s1, c1, s2, c2;
@@ -1177,12 +1191,17 @@ __device__ __forceinline__ typename OtfPoint<KIND>::V otf_target(const OtfSpec& 
 template <int KIND, int D>
 __device__ __forceinline__ typename OtfPoint<KIND>::V otf_source(const OtfSpec& o, const int* sj) {
   const int h = (int)(o.n / 2);
-  if constexpr (KIND == TB_KERNEL_RADON) {
+  if constexpr (KIND == TB_KERNEL_RADON && D == 3) {
+    const double k0 = sj[0] - h, k1 = sj[1] - h, k2 = sj[2] - h;
+    return make_double4(k0, k1, k2, sqrt(k0 * k0 + k1 * k1 + k2 * k2));
+  } else if constexpr (KIND == TB_KERNEL_RADON) {
     return make_double4((double)(sj[0] - h), (double)(sj[1] - h), 0.0, 0.0);
   } else if constexpr (KIND == TB_KERNEL_FOURIER) {
     return make_int4(sj[0] - h, sj[1] - h, D == 3 ? sj[D - 1] - h : 0, 0);
-  } else {  // y = j/n + (2, 0, 0): index j_0 + 2n
-    return make_int4(sj[0] + 2 * (int)o.n, sj[1], D == 3 ? sj[D - 1] : 0, 0);
+  } else if constexpr (D == 3) {  // cubes: y = j/n + (2, 0, 0), index j_0 + 2n
+    return make_int4(sj[0] + 2 * (int)o.n, sj[1], sj[2], 0);
+  } else {  // plates: in-plane indices (the plane distance enters as n^2)
+    return make_int4(sj[0], sj[1], 0, 0);
   }
 }
 
@@ -1206,11 +1225,15 @@ __device__ __forceinline__ float2 otf_entry(const OtfSpec& o, const typename Otf
   } else if constexpr (KIND == TB_KERNEL_HELMHOLTZ) {
     const double d0 = (double)(x.x - y.x), d1 = (double)(x.y - y.y), d2 = (double)(x.z - y.z);
     const double inv = 1.0 / (double)o.n;
-    const double r2 = fma(d0, d0, fma(d1, d1, d2 * d2)) * (inv * inv);  // exact scaling
+    const double gap = D == 2 ? (double)o.n * (double)o.n : 0.0;  // plates: distance 1 = n steps
+    const double r2 = (fma(d0, d0, fma(d1, d1, d2 * d2)) + gap) * (inv * inv);  // exact scaling
     const double ir = rsqrt64(r2);  // the cubes are apart: r2 >= 1
     const double rev = o.omega_rev * (r2 * ir);
     f = (float)(rev - floor(rev));
     amp = (float)ir;
+  } else if constexpr (D == 3) {  // Radon 3-D: x.k + c |k|
+    const double rev = fma(x.x, y.x, fma(x.y, y.y, fma(x.z, y.z, x.w * y.w)));
+    f = (float)(rev - floor(rev));
   } else {
     const double q = x.z * y.x * y.x + x.w * y.y * y.y;
     const double rev = x.x * y.x + x.y * y.y + (q > 0.0 ? q * rsqrt64(q) : 0.0);
@@ -2721,7 +2744,6 @@ static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const vo
     case TB_KERNEL_FOURIER: return by_kind(std::integral_constant<int, TB_KERNEL_FOURIER>{});
     case TB_KERNEL_HELMHOLTZ: return by_kind(std::integral_constant<int, TB_KERNEL_HELMHOLTZ>{});
     default:
-      if (d != 2) return fail(TB_ERR_UNSUPPORTED, "on-the-fly Radon cores are 2-D");
       return by_kind(std::integral_constant<int, TB_KERNEL_RADON>{});
   }
 }

@@ -50,19 +50,35 @@ __device__ double2 entry(const KernelSpec& ks, const int* ti, const int* sj) {
     return make_double2(c, s);
   }
   if (ks.kind == TB_KERNEL_HELMHOLTZ) {
-    // exp(+i omega rho)/rho, x = i/n, y = j/n + (2, 0, 0)
+    // exp(+i omega rho)/rho; d = 3: x = i/n, y = j/n + (2, 0, 0) (cubes);
+    // d = 2: x = (i/n, 0), y = (j/n, 1) (parallel plates 1 apart)
     const double inv = 1.0 / (double)ks.n;
-    double r2 = 0.0;
+    double r2 = ks.d == 2 ? 1.0 : 0.0;
     for (int k = 0; k < ks.d; ++k) {
-      double dx = (double)(ti[k] - sj[k]) * inv - (k == 0 ? 2.0 : 0.0);
+      double dx = (double)(ti[k] - sj[k]) * inv - ((k == 0 && ks.d == 3) ? 2.0 : 0.0);
       r2 += dx * dx;
     }
     const double rho = sqrt(r2);
     sincos(ks.omega * rho, &s, &c);
     return make_double2(c / rho, s / rho);
   }
-  // generalized Radon transform, d = 2
   const double inv = 1.0 / (double)ks.n;
+  if (ks.d == 3) {
+    // 3-D Radon transform: phase x.k + c(x)|k|, c = (a + b s1 s2 s3)/den
+    double ph = 0.0, k2 = 0.0, sp = 1.0;
+    for (int k = 0; k < 3; ++k) {
+      const double x = ti[k] * inv, kk = (double)(sj[k] - ks.n / 2);
+      double sk, ck;
+      sincospi(2.0 * x, &sk, &ck);
+      sp *= sk;
+      ph += x * kk;
+      k2 += kk * kk;
+    }
+    ph += (ks.ra + ks.rb * sp) / ks.rden * sqrt(k2);
+    sincospi(2.0 * ph, &s, &c);
+    return make_double2(c, s);
+  }
+  // generalized Radon transform, d = 2
   const double x1 = ti[0] * inv, x2 = ti[1] * inv;
   const double k1 = (double)(sj[0] - ks.n / 2), k2 = (double)(sj[1] - ks.n / 2);
   double s1, c1, s2, c2;
@@ -644,9 +660,8 @@ extern "C" tb_status tb_construct(tb_kernel kind, int d, long long n, double ome
   if (kind < TB_KERNEL_FOURIER || kind > TB_KERNEL_RADON)
     return fail(TB_ERR_INVALID_ARG, "unknown kernel kind");
   if (d < 1 || d > 8) return fail(TB_ERR_INVALID_ARG, "d must be in [1, 8]");
-  if ((kind == TB_KERNEL_FOURIER && (d < 2 || d > 3)) || (kind == TB_KERNEL_HELMHOLTZ && d != 3) ||
-      (kind == TB_KERNEL_RADON && d != 2))
-    return fail(TB_ERR_UNSUPPORTED, "kernel/dimension pair not built (Fourier d=2,3; Helmholtz d=3; Radon d=2)");
+  if (d < 2 || d > 3)
+    return fail(TB_ERR_UNSUPPORTED, "kernel/dimension pair not built (every kernel has d = 2 and 3)");
   if (!(tol > 0.0 && tol < 1.0)) return fail(TB_ERR_INVALID_ARG, "tol must be in (0, 1)");
   if (kind == TB_KERNEL_HELMHOLTZ && !(omega > 0.0)) return fail(TB_ERR_INVALID_ARG, "omega must be > 0");
   const int leaf = o.leaf_size ? o.leaf_size : 8;
@@ -675,6 +690,10 @@ extern "C" tb_status tb_construct(tb_kernel kind, int d, long long n, double ome
     p.rb = o.radon_b;
     p.rden = o.radon_den;
     if (p.rden == 0.0) return fail(TB_ERR_INVALID_ARG, "radon_den must be nonzero");
+  } else {  // section 4.2 constants for d = 3; the workloads' for d = 2
+    p.ra = d == 3 ? 3.0 : 2.0;
+    p.rb = 1.0;
+    p.rden = d == 3 ? 100.0 : 3.0;
   }
   p.store_mask = o.store_mask ? o.store_mask : TB_STORE_C64;
   if (p.store_mask & ~15u) return fail(TB_ERR_INVALID_ARG, "unknown store_mask bits");

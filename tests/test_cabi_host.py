@@ -53,8 +53,8 @@ def test_status_strings():
     ((_lib.TB_KERNEL_FOURIER, 2, 64, 0.0, 1.5), _lib.TB_ERR_INVALID_ARG),    # tol
     ((_lib.TB_KERNEL_FOURIER, 2, 60, 0.0, 1e-3), _lib.TB_ERR_INVALID_ARG),   # n != 8*2^L
     ((_lib.TB_KERNEL_HELMHOLTZ, 3, 64, 0.0, 1e-3), _lib.TB_ERR_INVALID_ARG), # omega
-    ((_lib.TB_KERNEL_HELMHOLTZ, 2, 64, 1.0, 1e-3), _lib.TB_ERR_UNSUPPORTED), # d
-    ((_lib.TB_KERNEL_RADON, 3, 64, 0.0, 1e-3), _lib.TB_ERR_UNSUPPORTED),     # d
+    ((_lib.TB_KERNEL_HELMHOLTZ, 4, 64, 1.0, 1e-3), _lib.TB_ERR_UNSUPPORTED), # d
+    ((_lib.TB_KERNEL_RADON, 1, 64, 0.0, 1e-3), _lib.TB_ERR_UNSUPPORTED),     # d
     ((7, 2, 64, 0.0, 1e-3), _lib.TB_ERR_INVALID_ARG),                        # kind
 ])
 def test_construct_rejects_bad_arguments(args, status):

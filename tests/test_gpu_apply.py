@@ -30,6 +30,8 @@ CASES = {
     "radon2_n32": (kernels.RADON, 2, 32, 1e-3, 8),
     "radon2_n64_leaf4": (kernels.RADON, 2, 64, 1e-2, 4),
     "helm3_n8_single": (kernels.HELMHOLTZ, 3, 8, 1e-4, 8),   # L = 0
+    "plates2_n64": (kernels.HELMHOLTZ, 2, 64, 1e-6, 8),      # parallel plates
+    "radon3_n16": (kernels.RADON, 3, 16, 1e-3, 4),           # 3-D Radon
 }
 
 _PLANS = {}

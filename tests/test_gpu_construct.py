@@ -33,6 +33,8 @@ def _op(kind, d, n):
     (kernels.HELMHOLTZ, 3, 32, 1e-4, 8),
     (kernels.RADON, 2, 32, 1e-3, 8),
     (kernels.HELMHOLTZ, 3, 16, 1e-4, 8),
+    (kernels.HELMHOLTZ, 2, 64, 1e-6, 8),   # parallel plates
+    (kernels.RADON, 3, 16, 1e-3, 4),       # 3-D Radon
 ])
 def test_gpu_factors_match_oracle(kind, d, n, tol, leaf, tmp_path):
     torch = torch_gpu()
