@@ -207,7 +207,9 @@ typedef struct {
   int whole_blocks;       /* transfer stages: 1 = one workgroup per block (no slices) */
   int core_kernel;        /* core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = FP32 matrix
                              cores; 4 = BF16 matrix cores (BF16 applies; right-hand sides split
-                             into bf16 hi + lo) */
+                             into bf16 hi + lo); 5, 6, 7 = BF16 matrix cores, second form, with
+                             256 x 32, 128 x 64, 128 x 32 (rows x right-hand sides) per
+                             workgroup */
   int fanin_in_turn;      /* fan-in stages: 1 = children in turn, first mode in registers */
   int transfer_mfma;      /* transfer levels (not the leaves), FP32 / BF16 applies: 1 = mode
                              products on the matrix cores, one block per workgroup */

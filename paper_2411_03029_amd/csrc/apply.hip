@@ -1845,6 +1845,211 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// BF16 cores on the matrix cores, second form: one workgroup owns 64 MTW
+// output rows (adjoint: columns) of one pair and NQ = 16 NQT right-hand sides
+// (every wave keeps MTW x NQT complex 16 x 16 tiles).  Each wave
+// owns 16 MTW consecutive rows, so a 16-row tile reads whole cache lines of
+// a core column.  The padded positions of the contracted index and of the
+// workgroup's output rows are tabulated in LDS once, the right-hand sides of
+// the next staged chunk (64 deep, 32 for 128 right-hand sides) are loaded
+// into registers while the current chunk is multiplied, and the core
+// fragments of the next 32 contracted indices are loaded before the
+// products of the current 32.  Same products, in the same order per
+// accumulator, as above: hi and lo parts of the FP32 right-hand sides
+// against the BF16 core words.
+template <int MTW_, int NQT>
+struct Bf16Tile {
+  static constexpr int MTW = MTW_;           // 16-row tiles per wave
+  static constexpr int kRows = 64 * MTW;     // output rows per workgroup
+  static constexpr int NQ = 16 * NQT;        // right-hand sides per workgroup
+  static constexpr int kSub = 256 / kRows;   // workgroups per 256-row unit
+  static constexpr int KC = NQT == 8 ? 32 : 64;        // contracted depth per staged chunk
+  static constexpr int kLd4 = (KC + 4) / 4;            // LDS row stride in uint4 (conflict-free)
+  static constexpr int kTasks = NQ * (KC / 4) / kThreads;  // (q, 4 k) staging tasks per thread
+};
+
+template <int D, bool ADJ, int MTW_, int NQT>
+__global__ void __launch_bounds__(kThreads)
+    core_mfma_bf16_v2(CoreArgs a, const unsigned* __restrict__ cores, const long long* __restrict__ core_off,
+                      const int* __restrict__ meta, const int2* __restrict__ units,
+                      const float2* __restrict__ in, float2* __restrict__ out) {
+  using TL = Bf16Tile<MTW_, NQT>;
+  constexpr int MTW = TL::MTW, NQ = TL::NQ, kRows = TL::kRows, KC = TL::KC, kLd4 = TL::kLd4;
+  __shared__ uint4 bhi[NQ * kLd4], blo[NQ * kLd4];
+  __shared__ int mpos[kRows];
+  extern __shared__ int kpos[];  // padded position of every contracted index
+  // flattened (unit, sub-panel, RHS tile), the tile fastest; the tiles that
+  // share a core panel run back to back on one XCD
+  const int nqt = (a.nrhs + NQ - 1) / NQ;
+  const int item = xcd_item(blockIdx.x, gridDim.x, nqt);
+  const int qt = item % nqt, sub = (item / nqt) % TL::kSub;
+  const int2 u = units[item / (nqt * TL::kSub)];
+  const int pair = u.x;
+  const int m0 = u.y + sub * kRows;
+  const int* m = meta + pair * kPairMeta;
+  const int RT = m[0], RS = m[1], RTp = m[2];
+  const int M = ADJ ? RS : RT, K = ADJ ? RT : RS;
+  if (m0 >= M) return;  // the whole workgroup lies past the pair
+  int mr[D], kr[D], MR[D], KR[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    mr[k] = ADJ ? m[6 + k] : m[3 + k];
+    kr[k] = ADJ ? m[3 + k] : m[6 + k];
+    MR[k] = ADJ ? a.Rs[k] : a.Rt[k];
+    KR[k] = ADJ ? a.Rt[k] : a.Rs[k];
+  }
+  const long long t = pair / a.nS, s = pair % a.nS;
+  const long long sitem = s * a.nT + t, titem = t * a.nS + s;
+  const long long inb = ADJ ? titem * a.Et : sitem * a.Es;
+  const long long outb = ADJ ? sitem * a.Es : titem * a.Et;
+  const int q0 = qt * NQ;
+  const int Qa = min(NQ, a.nrhs - q0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned* cb = cores + core_off[pair];
+  for (int i = threadIdx.x; i < K; i += kThreads) kpos[i] = (int)padded_pos<D>(i, kr, KR);
+  for (int i = threadIdx.x; i < kRows; i += kThreads)
+    mpos[i] = m0 + i < M ? (int)padded_pos<D>(m0 + i, mr, MR) : 0;
+  v4f accr[MTW][NQT], acci[MTW][NQT];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int c = 0; c < NQT; ++c) {
+      accr[i][c] = v4f{0, 0, 0, 0};
+      acci[i][c] = v4f{0, 0, 0, 0};
+    }
+  const int wrow = m0 + w * 16 * MTW;  // first row of this wave
+  int mcl[MTW];                        // this lane's (clamped) row or column
+  bool live[MTW];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    live[i] = wrow + 16 * i < M;
+    mcl[i] = ADJ ? min(wrow + 16 * i + (lane & 15), RS - 1) : min(wrow + 16 * i + (lane & 15), RTp - 1);
+  }
+  // core words of this lane for the 4 contracted indices k .. k + 3 of tile i
+  auto load_a = [&](uint4 (&aw)[MTW], int k) {
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+      if (!live[i]) continue;
+      if constexpr (ADJ) {
+        // rows k .. k + 3 lie inside the padded column (RTp is a multiple
+        // of 4); past it the staged right-hand side is zero, so any
+        // in-bounds row does
+        aw[i] = *reinterpret_cast<const uint4*>(cb + (long long)mcl[i] * RTp + min(k, RTp - 4));
+      } else {
+        aw[i].x = cb[(long long)min(k, K - 1) * RTp + mcl[i]];
+        aw[i].y = cb[(long long)min(k + 1, K - 1) * RTp + mcl[i]];
+        aw[i].z = cb[(long long)min(k + 2, K - 1) * RTp + mcl[i]];
+        aw[i].w = cb[(long long)min(k + 3, K - 1) * RTp + mcl[i]];
+      }
+    }
+  };
+  // staging: task j of this thread is right-hand side q = idx % NQ and the
+  // contracted indices 4 (idx / NQ) .. + 3 of the chunk (q fastest: each
+  // read of a k row is contiguous over q)
+  float2 fv[TL::kTasks][4];
+  __syncthreads();  // kpos, mpos
+  auto fetch_b = [&](int kc) {
+#pragma unroll
+    for (int j = 0; j < TL::kTasks; ++j) {
+      const int idx = threadIdx.x + j * kThreads;
+      const int q = idx % NQ, k4 = idx / NQ;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = kc + 4 * k4 + e;
+        fv[j][e] = (k < K && q < Qa) ? in[(inb + kpos[k]) * a.nrhs + q0 + q] : make_float2(0.f, 0.f);
+      }
+    }
+  };
+  auto store_b = [&]() {
+#pragma unroll
+    for (int j = 0; j < TL::kTasks; ++j) {
+      const int idx = threadIdx.x + j * kThreads;
+      const int q = idx % NQ, k4 = idx / NQ;
+      uint4 h, l;
+      split_bf16(fv[j][0], &h.x, &l.x);
+      split_bf16(fv[j][1], &h.y, &l.y);
+      split_bf16(fv[j][2], &h.z, &l.z);
+      split_bf16(fv[j][3], &h.w, &l.w);
+      bhi[q * kLd4 + k4] = h;
+      blo[q * kLd4 + k4] = l;
+    }
+  };
+  // the core fragments run two 16-deep steps (one 32-deep step) ahead of
+  // the products, across chunk boundaries; the right-hand sides one chunk
+  const int kq = 4 * (lane >> 4);  // this lane's first k of a 16-deep step
+  uint4 acur[2][MTW], anxt[2][MTW];
+  load_a(acur[0], kq);
+  load_a(acur[1], 16 + kq);
+  fetch_b(0);
+  for (int kc = 0; kc < K; kc += KC) {
+    __syncthreads();  // the previous chunk's fragments are read
+    store_b();
+    __syncthreads();
+    if (kc + KC < K) fetch_b(kc + KC);
+    const int kend = min(KC, K - kc);
+    for (int ks = 0; ks < kend; ks += 32) {
+      if (kc + ks + 32 < K) {
+        load_a(anxt[0], kc + ks + 32 + kq);
+        load_a(anxt[1], kc + ks + 48 + kq);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint4 bh[NQT], bl[NQT];
+#pragma unroll
+        for (int c = 0; c < NQT; ++c) {
+          const int q = c * 16 + (lane & 15);
+          bh[c] = bhi[q * kLd4 + (ks + 16 * h + kq) / 4];
+          bl[c] = blo[q * kLd4 + (ks + 16 * h + kq) / 4];
+        }
+#pragma unroll
+        for (int i = 0; i < MTW; ++i) {
+          if (!live[i]) continue;
+          const uint4 cw = acur[h][i];
+          v8bf ar, ai;
+          if constexpr (ADJ) {
+            ar = as_v8bf(cw);
+            ai = as_v8bf(make_uint4(swap16(cw.x) ^ 0x8000u, swap16(cw.y) ^ 0x8000u, swap16(cw.z) ^ 0x8000u,
+                                    swap16(cw.w) ^ 0x8000u));
+          } else {
+            ar = as_v8bf(make_uint4(cw.x ^ 0x80000000u, cw.y ^ 0x80000000u, cw.z ^ 0x80000000u,
+                                    cw.w ^ 0x80000000u));
+            ai = as_v8bf(make_uint4(swap16(cw.x), swap16(cw.y), swap16(cw.z), swap16(cw.w)));
+          }
+#pragma unroll
+          for (int c = 0; c < NQT; ++c) {
+            accr[i][c] = mfma_bf16(ar, as_v8bf(bh[c]), accr[i][c]);
+            acci[i][c] = mfma_bf16(ai, as_v8bf(bh[c]), acci[i][c]);
+          }
+#pragma unroll
+          for (int c = 0; c < NQT; ++c) {
+            accr[i][c] = mfma_bf16(ar, as_v8bf(bl[c]), accr[i][c]);
+            acci[i][c] = mfma_bf16(ai, as_v8bf(bl[c]), acci[i][c]);
+          }
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < MTW; ++i) acur[h][i] = anxt[h][i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < MTW; ++i) {
+    if (!live[i]) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int rl = w * 16 * MTW + 16 * i + 4 * (lane >> 4) + j;  // row within the workgroup
+      if (m0 + rl >= M) continue;
+      float2* dst = out + (outb + mpos[rl]) * a.nrhs + q0;
+#pragma unroll
+      for (int c = 0; c < NQT; ++c) {
+        const int q = c * 16 + (lane & 15);
+        if (q < Qa) dst[q] = make_float2(accr[i][c][j], acci[i][c][j]);
+      }
+    }
+  }
+}
+
 // ----------------------------------------------- MFMA transfer stages --
 // A mode product of a transfer block, out[a][col] = sum_j M[a][j] in[j][col]
 // (complex; a < nA new-mode entries, j < K contracted entries, col over the
@@ -2633,6 +2838,43 @@ static tb_status launch_core_mfma(const Plan& p, const CoreArgs& a, bool adjoint
   return TB_OK;
 }
 
+// BF16 cores, second form (MTW 16-row tiles per wave, NQ = 16 NQT
+// right-hand sides per workgroup): every 256-row (adjoint: 256-column) unit
+// is split into 256 / (64 MTW) workgroups; those past the pair's extent
+// return at once.
+template <int D, bool ADJ, int MTW, int NQT>
+static tb_status launch_core_bf16_v2(const Plan& p, const CoreArgs& a, const void* cores, const void* in,
+                                     void* out, int maxK, hipStream_t stream) {
+  using TL = Bf16Tile<MTW, NQT>;
+  const std::vector<int2>& units = ADJ ? p.mfma_adj_units : p.mfma_fwd_units;
+  const int2* units_d = ADJ ? p.mfma_adj_units_d : p.mfma_fwd_units_d;
+  const long long nqt = (a.nrhs + TL::NQ - 1) / TL::NQ;
+  const long long nblocks = (long long)units.size() * TL::kSub * nqt;
+  if (nblocks > (1LL << 31) - 1) return fail(TB_ERR_UNSUPPORTED, "core grid too large");
+  int limit = 0;
+  TB_TRY(lds_limit(&limit));
+  const size_t lds = (size_t)maxK * sizeof(int);
+  const size_t fixed = 2 * sizeof(uint4) * TL::NQ * TL::kLd4 + sizeof(int) * TL::kRows;
+  if (lds + fixed > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "core position table exceeds LDS");
+  TB_TRY(set_lds(core_mfma_bf16_v2<D, ADJ, MTW, NQT>, lds + fixed));
+  core_mfma_bf16_v2<D, ADJ, MTW, NQT><<<dim3((unsigned)nblocks), kThreads, lds, stream>>>(
+      a, (const unsigned*)cores, p.core_off_d, p.pair_meta_d, units_d, (const float2*)in, (float2*)out);
+  TB_HIP_TRY(hipGetLastError());
+  return TB_OK;
+}
+
+// form: 5 = 256 rows x 32 right-hand sides per workgroup, 6 = 128 x 64,
+// 7 = 128 x 32
+template <int D, bool ADJ>
+static tb_status launch_core_bf16_form(const Plan& p, const CoreArgs& a, int form, const void* cores,
+                                       const void* in, void* out, int maxK, hipStream_t stream) {
+  switch (form) {
+    case 5: return launch_core_bf16_v2<D, ADJ, 4, 2>(p, a, cores, in, out, maxK, stream);
+    case 6: return launch_core_bf16_v2<D, ADJ, 2, 4>(p, a, cores, in, out, maxK, stream);
+    default: return launch_core_bf16_v2<D, ADJ, 2, 2>(p, a, cores, in, out, maxK, stream);
+  }
+}
+
 template <class T, class CS>
 static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* cores, const void* in,
                              void* out, hipStream_t stream, const LaunchCfg& cfg) {
@@ -2655,11 +2897,21 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
     maxRTp = std::max(maxRTp, p.pair_meta[(size_t)pr * kPairMeta + 2]);
   }
   if constexpr (sizeof(CS) == 4) {  // BF16 cores
+    if (cfg.core >= 5 && cfg.core <= 7) {
+      int maxRT = 0;
+      for (long long pr = 0; pr < p.npairs; ++pr) maxRT = std::max(maxRT, p.pair_meta[(size_t)pr * kPairMeta]);
+      const int maxK = adjoint ? maxRT : maxRS;
+      if (d == 2)
+        return adjoint ? launch_core_bf16_form<2, true>(p, a, cfg.core, cores, in, out, maxK, stream)
+                       : launch_core_bf16_form<2, false>(p, a, cfg.core, cores, in, out, maxK, stream);
+      return adjoint ? launch_core_bf16_form<3, true>(p, a, cfg.core, cores, in, out, maxK, stream)
+                     : launch_core_bf16_form<3, false>(p, a, cfg.core, cores, in, out, maxK, stream);
+    }
     if (cfg.core == 4 || (cfg.core == 0 && nrhs >= kMfmaMinRhs))
       return d == 2 ? launch_core_mfma<CS, 2>(p, a, adjoint, cores, in, out, stream, true)
                     : launch_core_mfma<CS, 3>(p, a, adjoint, cores, in, out, stream, true);
   } else {
-    if (cfg.core == 4) return fail(TB_ERR_UNSUPPORTED, "BF16 matrix cores need BF16 cores");
+    if (cfg.core >= 4) return fail(TB_ERR_UNSUPPORTED, "BF16 matrix cores need BF16 cores");
   }
   if constexpr (sizeof(T) == 4) {
     if (cfg.core == 3 || (cfg.core == 0 && nrhs >= kMfmaMinRhs))
@@ -2950,6 +3202,11 @@ static std::vector<LaunchCfg> core_candidates(long long nrhs, tb_dtype io) {
   if (io == TB_CBF16 && nrhs >= 4) {
     c.core = 4;
     out.push_back(c);
+    for (int v = 5; v <= 7; ++v) {  // second form, three workgroup tiles
+      if (v == 6 && nrhs <= 32) continue;  // 64 right-hand sides per workgroup
+      c.core = v;
+      out.push_back(c);
+    }
   }
   return out;
 }
@@ -2964,7 +3221,7 @@ static bool read_cache(const char* path, uint64_t sig, int io, long long nrhs, s
     unsigned long long s = 0;
     int fio = 0, n = 0, pos = 0;
     long long fr = 0;
-    if (std::sscanf(line, "tbtune3 %llx %d %lld %d%n", &s, &fio, &fr, &n, &pos) != 4) continue;
+    if (std::sscanf(line, "tbtune4 %llx %d %lld %d%n", &s, &fio, &fr, &n, &pos) != 4) continue;
     if (s != sig || fio != io || fr != nrhs || (size_t)n != nslots) continue;
     std::vector<LaunchCfg> v(n);
     const char* q = line + pos;
@@ -2988,7 +3245,7 @@ static void append_cache(const char* path, uint64_t sig, int io, long long nrhs,
                          const std::vector<LaunchCfg>& cfg) {
   FILE* fh = std::fopen(path, "a");
   if (!fh) return;
-  std::fprintf(fh, "tbtune3 %016llx %d %lld %d", (unsigned long long)sig, io, nrhs, (int)cfg.size());
+  std::fprintf(fh, "tbtune4 %016llx %d %lld %d", (unsigned long long)sig, io, nrhs, (int)cfg.size());
   for (const LaunchCfg& c : cfg)
     std::fprintf(fh, " %d,%d,%d,%d,%d,%d", c.G, c.QT, c.split, c.core, c.alt, c.mfma);
   std::fprintf(fh, "\n");
@@ -3288,7 +3545,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   if (slot < 0 || slot >= nslots) return tb::fail(TB_ERR_INVALID_ARG, "launch slot out of range");
   const int g = cfg->outputs_per_thread, q = cfg->rhs_tile;
   if (!(g == 0 || g == 1 || g == 8) || !(q == 0 || q == 1 || q == 2 || q == 4 || q == 8) ||
-      cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 4 ||
+      cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 7 ||
       cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 1 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1)
     return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");
   auto& v = p->tuned[{(int)io, nrhs}];

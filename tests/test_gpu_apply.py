@@ -167,6 +167,35 @@ def test_batched_rhs_matrix_cores(name, nrhs, tmp_path):
             assert relerr(v[q], ve[q]) <= tol, (dt, q, relerr(v[q], ve[q]))
 
 
+@pytest.mark.parametrize("name,nrhs", [("helm3_n32", 70), ("radon2_n32", 130), ("fourier2_n64", 9),
+                                       ("radon3_n16", 37)])
+def test_bf16_core_forms_agree(name, nrhs, tmp_path):
+    # the second form of the BF16 matrix-core cores (three workgroup tiles of
+    # 128 or 256 rows and 32 or 64 right-hand sides, padded positions in LDS)
+    # takes the same products in the same order per accumulator as the
+    # first form, so its outputs equal the first form's bit for bit, over
+    # ragged right-hand-side tiles; against the oracle to the BF16 bound
+    torch = torch_gpu()
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path, store=("cbf16",))
+    slots = plan.launch_slots()
+    cf, ca = slots.index("core"), slots.index("core_adj")
+    f = inputs.rhs_batch(op.n, op.d, nrhs, config=99)
+    x = to_dev(f, torch.complex64)
+    outs = {}
+    for form in (4, 5, 6, 7):
+        say(f"[gpu] bf16 core form {form} {name} nrhs={nrhs}")
+        plan.set_launch(nrhs, cf, dtype="cbf16", core_kernel=form)
+        plan.set_launch(nrhs, ca, dtype="cbf16", core_kernel=form)
+        outs[form] = (plan.apply(x, dtype="cbf16"), plan.apply_adjoint(x, dtype="cbf16"))
+        torch.cuda.synchronize()
+    for form in (5, 6, 7):
+        assert torch.equal(outs[form][0], outs[4][0]), ("forward", form)
+        assert torch.equal(outs[form][1], outs[4][1]), ("adjoint", form)
+    assert relerr(to_host(outs[6][0]), bf.apply(op, f)) <= 5e-3
+    assert relerr(to_host(outs[6][1]), bf.apply_adjoint(op, f)) <= 5e-3
+
+
 def test_stage_multiply_add_split(tmp_path):
     # the per-stage split of the multiply-add count adds up, and the core
     # share is the sum of R_T R_S over the pairs, i.e. the core entries

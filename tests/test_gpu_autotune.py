@@ -51,7 +51,7 @@ def test_tuned_apply_matches_oracle_and_cache_round_trips(kind, d, n, tol, leaf,
         torch.cuda.synchronize()
         assert torch.equal(u, u2) and torch.equal(v, v2)
     lines = open(cache).read().splitlines()
-    assert len(lines) == 3 and all(l.startswith("tbtune3 ") for l in lines)
+    assert len(lines) == 3 and all(l.startswith("tbtune4 ") for l in lines)
 
 
 def test_autotune_rejects_missing_precision(tmp_path):
@@ -76,7 +76,7 @@ def _candidates(stage, nrhs, dtype):
         if dtype not in ("c128", "c64otf") and nrhs >= 4:
             out.append(dict(core_kernel=3))
         if dtype == "cbf16" and nrhs >= 4:
-            out.append(dict(core_kernel=4))
+            out += [dict(core_kernel=v) for v in (4, 5, 6, 7)]
         return out
     fanout = stage in ("src_leaf", "src_transfer", "tgt_leaf_adj", "tgt_transfer_adj")
     out = []
