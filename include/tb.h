@@ -213,6 +213,8 @@ typedef struct {
   int fanin_in_turn;      /* fan-in stages: 1 = children in turn, first mode in registers */
   int transfer_mfma;      /* transfer levels (not the leaves), FP32 / BF16 applies: 1 = mode
                              products on the matrix cores, one block per workgroup */
+  int rhs_per_thread;     /* fan-out / fan-in kernels: 1 or 4 right-hand sides per thread
+                             (4 needs a right-hand-side tile of 4 or 8) */
 } tb_launch_cfg;
 
 /* Set the configuration of launch `slot` for applies of p with exactly this

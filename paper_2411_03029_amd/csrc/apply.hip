@@ -192,6 +192,36 @@ __device__ __forceinline__ void gzero(C (&acc)[G]) {
   for (int g = 0; g < G; ++g) acc[g] = czero<C>();
 }
 
+// gdot with V right-hand sides per thread as well (x(j, v) is element j of
+// right-hand side v): each matrix element loaded serves V products.  The
+// order of the sum per output is the one of gdot.
+template <int G, int V, class C, class MF, class XF>
+__device__ __forceinline__ void gdotv(C (&acc)[G][V], int ng, int nj, MF m, XF x) {
+  int row[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) row[g] = min(g, ng - 1);
+#pragma unroll 2
+  for (int j = 0; j < nj; ++j) {
+    C xv[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) xv[v] = x(j, v);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const C mv = m(row[g], j);
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[g][v] = cfma(acc[g][v], mv, xv[v]);
+    }
+  }
+}
+
+template <int G, int V, class C>
+__device__ __forceinline__ void gzero2(C (&acc)[G][V]) {
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[g][v] = czero<C>();
+}
+
 
 // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
 // xcd_item maps workgroup b of n to work item u so that groups of g
@@ -230,12 +260,13 @@ __device__ __forceinline__ StageBid stage_bid(const StageArgs& a, int QT) {
 // over true ranks (rows a_k < r_k) and the coarse block's true entries,
 // for a_0 in this workgroup's slice [lo, lo + na).  Padding is never
 // written or read: every consumer loops over true extents only.
-template <class T, int D, int QT, int kG>
+template <class T, int D, int QT, int kG, int kV>
 __global__ void __launch_bounds__(kThreads)
     stage_fanout(StageArgs a, const typename CplxOf<T>::type* __restrict__ coarse,
                  typename CplxOf<T>::type* __restrict__ fine,
                  const typename CplxOf<T>::type* __restrict__ mats) {
   using C = typename CplxOf<T>::type;
+  constexpr int NQV = QT / kV;  // threads along the right-hand sides
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
   const StageBid sb = stage_bid(a, QT);
@@ -294,116 +325,132 @@ __global__ void __launch_bounds__(kThreads)
   if constexpr (kG > 1) __syncthreads();
   if constexpr (D == 2) {
     // buf1[ai][j1][q] = sum_j0 M0[lo+ai][j0] coarse(j0, j1, q)
-    for (int idx = threadIdx.x; idx < ng0 * c1 * QT; idx += kThreads) {
-      int q, j1, t;
+    for (int idx = threadIdx.x; idx < ng0 * c1 * NQV; idx += kThreads) {
+      int qi, j1, t;
       if (a.coarse_global) {  // mode 1 is contiguous in the caller's array
         j1 = idx % c1;
         t = idx / c1;
-        q = t % QT;
-        t /= QT;
+        qi = t % NQV;
+        t /= NQV;
       } else {
-        q = idx % QT;
-        t = idx / QT;
+        qi = idx % NQV;
+        t = idx / NQV;
         j1 = t % c1;
         t /= c1;
       }
+      const int q = qi * kV;
       const int a0 = t * kG, ng = min(kG, na - a0);
-      C acc[kG];
-      gzero(acc);
+      C acc[kG][kV];
+      gzero2(acc);
       if (q < Qa) {
         const C* src = coarse + ca.base + sg[1].pos(j1) * ca.stride[1] + q * ca.qstride;
-        gdot(acc, ng, c0, [&](int g, int j) { return m0(a0 + g, j); },
-             [&](int j) { return src[sg[0].pos(j) * ca.stride[0]]; });
+        const int vmax = min(kV, Qa - q) - 1;
+        gdotv(acc, ng, c0, [&](int g, int j) { return m0(a0 + g, j); },
+              [&](int j, int v) { return src[sg[0].pos(j) * ca.stride[0] + min(v, vmax) * ca.qstride]; });
       }
 #pragma unroll
       for (int g = 0; g < kG; ++g)
-        if (g < ng) buf1[((a0 + g) * c1 + j1) * QT + q] = acc[g];
+        if (g < ng)
+#pragma unroll
+          for (int v = 0; v < kV; ++v) buf1[((a0 + g) * c1 + j1) * QT + q + v] = acc[g][v];
     }
     __syncthreads();
     // fine[lo+ai][a1][q] = sum_j1 M1[a1][j1] buf1[ai][j1][q]
     const int ng1 = (r[1] + kG - 1) / kG;
-    for (int idx = threadIdx.x; idx < ng1 * na * QT; idx += kThreads) {
-      const int q = idx % QT;
-      int t = idx / QT;
+    for (int idx = threadIdx.x; idx < ng1 * na * NQV; idx += kThreads) {
+      const int q = (idx % NQV) * kV;
+      int t = idx / NQV;
       const int ai = t % na, a1 = (t / na) * kG, ng = min(kG, r[1] - a1);
       if (q >= Qa) continue;
-      C acc[kG];
-      gzero(acc);
+      C acc[kG][kV];
+      gzero2(acc);
       const C* src = buf1 + (ai * c1) * QT + q;
-      gdot(acc, ng, c1, [&](int g, int j) { return mk[1][(a1 + g) * c1 + j]; },
-           [&](int j) { return src[j * QT]; });
+      gdotv(acc, ng, c1, [&](int g, int j) { return mk[1][(a1 + g) * c1 + j]; },
+            [&](int j, int v) { return src[j * QT + v]; });
       C* dst = fine + fb + (lo + ai) * fs[0] + q;
 #pragma unroll
       for (int g = 0; g < kG; ++g)
-        if (g < ng) dst[(a1 + g) * fs[1]] = acc[g];
+        if (g < ng)
+#pragma unroll
+          for (int v = 0; v < kV; ++v)
+            if (v < Qa - q) dst[(a1 + g) * fs[1] + v] = acc[g][v];
     }
   } else {
     const int c2 = sg[2].c;
     C* buf2 = buf1 + a.chunk * a.A[1] * a.A[2] * QT;
     // buf1[ai][j1][j2][q] = sum_j0 M0[lo+ai][j0] coarse(j0, j1, j2, q)
-    for (int idx = threadIdx.x; idx < ng0 * c1 * c2 * QT; idx += kThreads) {
-      int q, j2, t;
+    for (int idx = threadIdx.x; idx < ng0 * c1 * c2 * NQV; idx += kThreads) {
+      int qi, j2, t;
       if (a.coarse_global) {
         j2 = idx % c2;
         t = idx / c2;
-        q = t % QT;
-        t /= QT;
+        qi = t % NQV;
+        t /= NQV;
       } else {
-        q = idx % QT;
-        t = idx / QT;
+        qi = idx % NQV;
+        t = idx / NQV;
         j2 = t % c2;
         t /= c2;
       }
+      const int q = qi * kV;
       const int j1 = t % c1, a0 = (t / c1) * kG, ng = min(kG, na - a0);
-      C acc[kG];
-      gzero(acc);
+      C acc[kG][kV];
+      gzero2(acc);
       if (q < Qa) {
         const C* src = coarse + ca.base + sg[1].pos(j1) * ca.stride[1] + sg[2].pos(j2) * ca.stride[2] +
                        q * ca.qstride;
-        gdot(acc, ng, c0, [&](int g, int j) { return m0(a0 + g, j); },
-             [&](int j) { return src[sg[0].pos(j) * ca.stride[0]]; });
+        const int vmax = min(kV, Qa - q) - 1;
+        gdotv(acc, ng, c0, [&](int g, int j) { return m0(a0 + g, j); },
+              [&](int j, int v) { return src[sg[0].pos(j) * ca.stride[0] + min(v, vmax) * ca.qstride]; });
       }
 #pragma unroll
       for (int g = 0; g < kG; ++g)
-        if (g < ng) buf1[(((a0 + g) * c1 + j1) * c2 + j2) * QT + q] = acc[g];
+        if (g < ng)
+#pragma unroll
+          for (int v = 0; v < kV; ++v) buf1[(((a0 + g) * c1 + j1) * c2 + j2) * QT + q + v] = acc[g][v];
     }
     __syncthreads();
     // buf2[ai][a1][j2][q] = sum_j1 M1[a1][j1] buf1[ai][j1][j2][q]
     const int ng1 = (r[1] + kG - 1) / kG;
-    for (int idx = threadIdx.x; idx < ng1 * na * c2 * QT; idx += kThreads) {
-      const int q = idx % QT;
-      int t = idx / QT;
+    for (int idx = threadIdx.x; idx < ng1 * na * c2 * NQV; idx += kThreads) {
+      const int q = (idx % NQV) * kV;
+      int t = idx / NQV;
       const int j2 = t % c2;
       t /= c2;
       const int ai = t % na, a1 = (t / na) * kG, ng = min(kG, r[1] - a1);
-      C acc[kG];
-      gzero(acc);
+      C acc[kG][kV];
+      gzero2(acc);
       const C* src = buf1 + ((ai * c1) * c2 + j2) * QT + q;
-      gdot(acc, ng, c1, [&](int g, int j) { return mk[1][(a1 + g) * c1 + j]; },
-           [&](int j) { return src[j * c2 * QT]; });
+      gdotv(acc, ng, c1, [&](int g, int j) { return mk[1][(a1 + g) * c1 + j]; },
+            [&](int j, int v) { return src[j * c2 * QT + v]; });
 #pragma unroll
       for (int g = 0; g < kG; ++g)
-        if (g < ng) buf2[((ai * r[1] + a1 + g) * c2 + j2) * QT + q] = acc[g];
+        if (g < ng)
+#pragma unroll
+          for (int v = 0; v < kV; ++v) buf2[((ai * r[1] + a1 + g) * c2 + j2) * QT + q + v] = acc[g][v];
     }
     __syncthreads();
     // fine[lo+ai][a1][a2][q] = sum_j2 M2[a2][j2] buf2[ai][a1][j2][q]
     const int ng2 = (r[2] + kG - 1) / kG;
-    for (int idx = threadIdx.x; idx < ng2 * na * r[1] * QT; idx += kThreads) {
-      const int q = idx % QT;
-      int t = idx / QT;
+    for (int idx = threadIdx.x; idx < ng2 * na * r[1] * NQV; idx += kThreads) {
+      const int q = (idx % NQV) * kV;
+      int t = idx / NQV;
       const int a1 = t % r[1];
       t /= r[1];
       const int ai = t % na, a2 = (t / na) * kG, ng = min(kG, r[2] - a2);
       if (q >= Qa) continue;
-      C acc[kG];
-      gzero(acc);
+      C acc[kG][kV];
+      gzero2(acc);
       const C* src = buf2 + ((ai * r[1] + a1) * c2) * QT + q;
-      gdot(acc, ng, c2, [&](int g, int j) { return mk[2][(a2 + g) * c2 + j]; },
-           [&](int j) { return src[j * QT]; });
+      gdotv(acc, ng, c2, [&](int g, int j) { return mk[2][(a2 + g) * c2 + j]; },
+            [&](int j, int v) { return src[j * QT + v]; });
       C* dst = fine + fb + (lo + ai) * fs[0] + a1 * fs[1] + q;
 #pragma unroll
       for (int g = 0; g < kG; ++g)
-        if (g < ng) dst[(a2 + g) * fs[2]] = acc[g];
+        if (g < ng)
+#pragma unroll
+          for (int v = 0; v < kV; ++v)
+            if (v < Qa - q) dst[(a2 + g) * fs[2] + v] = acc[g][v];
     }
   }
 }
@@ -415,12 +462,13 @@ __global__ void __launch_bounds__(kThreads)
 // children are processed together: two barriers per workgroup.
 constexpr int kMaxChildren = 1 << kMaxD;
 
-template <class T, int D, int QT, bool SM, int kG>
+template <class T, int D, int QT, bool SM, int kG, int kV>
 __global__ void __launch_bounds__(kThreads)
     stage_fanin(StageArgs a, const typename CplxOf<T>::type* __restrict__ fine,
                 typename CplxOf<T>::type* __restrict__ coarse,
                 const typename CplxOf<T>::type* __restrict__ mats) {
   using C = typename CplxOf<T>::type;
+  constexpr int NQV = QT / kV;  // threads along the right-hand sides
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
   const StageBid sb = stage_bid(a, QT);
@@ -516,55 +564,62 @@ __global__ void __launch_bounds__(kThreads)
   if constexpr (D == 2) {
     // buf1[c][ai][j1][q] = sum_j0 M0_c[j0][pos(lo+ai)] fine_c(j0, j1, q), j1 < r1(c)
     const int per_c = na * R1 * QT;
-    for (int idx = threadIdx.x; idx < nchild * ng0 * R1 * QT; idx += kThreads) {
-      const int q = idx % QT;
-      int t = idx / QT;
+    for (int idx = threadIdx.x; idx < nchild * ng0 * R1 * NQV; idx += kThreads) {
+      const int q = (idx % NQV) * kV;
+      int t = idx / NQV;
       const int j1 = t % R1;
       t /= R1;
       const int a0 = (t % ng0) * kG, c = t / ng0, ng = min(kG, na - a0);
       if (j1 >= crk[c][1]) continue;
-      C acc[kG];
-      gzero(acc);
+      C acc[kG][kV];
+      gzero2(acc);
       if (q < Qa) {
         const C* src = fine + cfb[c] + j1 * fs[1] + q;
-        gdot(acc, ng, crk[c][0], [&](int g, int j) { return mat0(c, a0 + g, j); },
-             [&](int j) { return src[j * fs[0]]; });
+        const int vmax = min(kV, Qa - q) - 1;
+        gdotv(acc, ng, crk[c][0], [&](int g, int j) { return mat0(c, a0 + g, j); },
+              [&](int j, int v) { return src[j * fs[0] + min(v, vmax)]; });
       }
 #pragma unroll
       for (int g = 0; g < kG; ++g)
-        if (g < ng) buf1[c * per_c + ((a0 + g) * R1 + j1) * QT + q] = acc[g];
+        if (g < ng)
+#pragma unroll
+          for (int v = 0; v < kV; ++v) buf1[c * per_c + ((a0 + g) * R1 + j1) * QT + q + v] = acc[g][v];
     }
     __syncthreads();
     CoarseAddr<D> ca;
     ca.init(a, ci, beta, q0);
     // coarse[lo+ai][j1o][q] = sum_c sum_j1 M1_c[j1][j1o] buf1[c][ai][j1][q]
     const int ng1 = (c1 + kG - 1) / kG;
-    for (int idx = threadIdx.x; idx < ng1 * na * QT; idx += kThreads) {
-      int q, ai, t;
+    for (int idx = threadIdx.x; idx < ng1 * na * NQV; idx += kThreads) {
+      int qi, ai, t;
       if (a.coarse_global) {
         ai = idx % na;
         t = idx / na;
-        q = t % QT;
-        t /= QT;
+        qi = t % NQV;
+        t /= NQV;
       } else {
-        q = idx % QT;
-        t = idx / QT;
+        qi = idx % NQV;
+        t = idx / NQV;
         ai = t % na;
         t /= na;
       }
+      const int q = qi * kV;
       const int j1o = t * kG, ng = min(kG, c1 - j1o);
       if (q >= Qa) continue;
-      C acc[kG];
-      gzero(acc);
+      C acc[kG][kV];
+      gzero2(acc);
       for (int c = 0; c < nchild; ++c) {
         const C* src = buf1 + c * per_c + (ai * R1) * QT + q;
-        gdot(acc, ng, crk[c][1], [&](int g, int j) { return mat(c, 1, j, j1o + g); },
-             [&](int j) { return src[j * QT]; });
+        gdotv(acc, ng, crk[c][1], [&](int g, int j) { return mat(c, 1, j, j1o + g); },
+              [&](int j, int v) { return src[j * QT + v]; });
       }
       C* dst = coarse + ca.base + sg[0].pos(lo + ai) * ca.stride[0] + q * ca.qstride;
 #pragma unroll
       for (int g = 0; g < kG; ++g)
-        if (g < ng) dst[sg[1].pos(j1o + g) * ca.stride[1]] = acc[g];
+        if (g < ng)
+#pragma unroll
+          for (int v = 0; v < kV; ++v)
+            if (v < Qa - q) dst[sg[1].pos(j1o + g) * ca.stride[1] + v * ca.qstride] = acc[g][v];
     }
   } else {
     const int R2 = a.R[2];
@@ -573,79 +628,90 @@ __global__ void __launch_bounds__(kThreads)
     const int per_c2 = na * a.A[1] * R2 * QT;
     C* buf2 = buf1 + nchild * per_c1;
     // buf1[c][ai][j1][j2][q] = sum_j0 M0_c[j0][pos(lo+ai)] fine_c(j0, j1, j2, q)
-    for (int idx = threadIdx.x; idx < nchild * ng0 * R1 * R2 * QT; idx += kThreads) {
-      const int q = idx % QT;
-      int t = idx / QT;
+    for (int idx = threadIdx.x; idx < nchild * ng0 * R1 * R2 * NQV; idx += kThreads) {
+      const int q = (idx % NQV) * kV;
+      int t = idx / NQV;
       const int j2 = t % R2;
       t /= R2;
       const int j1 = t % R1;
       t /= R1;
       const int a0 = (t % ng0) * kG, c = t / ng0, ng = min(kG, na - a0);
       if (j1 >= crk[c][1] || j2 >= crk[c][2]) continue;
-      C acc[kG];
-      gzero(acc);
+      C acc[kG][kV];
+      gzero2(acc);
       if (q < Qa) {
         const C* src = fine + cfb[c] + j1 * fs[1] + j2 * fs[2] + q;
-        gdot(acc, ng, crk[c][0], [&](int g, int j) { return mat0(c, a0 + g, j); },
-             [&](int j) { return src[j * fs[0]]; });
+        const int vmax = min(kV, Qa - q) - 1;
+        gdotv(acc, ng, crk[c][0], [&](int g, int j) { return mat0(c, a0 + g, j); },
+              [&](int j, int v) { return src[j * fs[0] + min(v, vmax)]; });
       }
 #pragma unroll
       for (int g = 0; g < kG; ++g)
-        if (g < ng) buf1[c * per_c1 + (((a0 + g) * R1 + j1) * R2 + j2) * QT + q] = acc[g];
+        if (g < ng)
+#pragma unroll
+          for (int v = 0; v < kV; ++v)
+            buf1[c * per_c1 + (((a0 + g) * R1 + j1) * R2 + j2) * QT + q + v] = acc[g][v];
     }
     __syncthreads();
     // buf2[c][ai][j1o][j2][q] = sum_j1 M1_c[j1][j1o] buf1[c][ai][j1][j2][q]
     const int ng1 = (c1 + kG - 1) / kG;
-    for (int idx = threadIdx.x; idx < nchild * ng1 * na * R2 * QT; idx += kThreads) {
-      const int q = idx % QT;
-      int t = idx / QT;
+    for (int idx = threadIdx.x; idx < nchild * ng1 * na * R2 * NQV; idx += kThreads) {
+      const int q = (idx % NQV) * kV;
+      int t = idx / NQV;
       const int j2 = t % R2;
       t /= R2;
       const int ai = t % na;
       t /= na;
       const int j1o = (t % ng1) * kG, c = t / ng1, ng = min(kG, c1 - j1o);
       if (j2 >= crk[c][2]) continue;
-      C acc[kG];
-      gzero(acc);
+      C acc[kG][kV];
+      gzero2(acc);
       const C* src = buf1 + c * per_c1 + ((ai * R1) * R2 + j2) * QT + q;
-      gdot(acc, ng, crk[c][1], [&](int g, int j) { return mat(c, 1, j, j1o + g); },
-           [&](int j) { return src[j * R2 * QT]; });
+      gdotv(acc, ng, crk[c][1], [&](int g, int j) { return mat(c, 1, j, j1o + g); },
+            [&](int j, int v) { return src[j * R2 * QT + v]; });
 #pragma unroll
       for (int g = 0; g < kG; ++g)
-        if (g < ng) buf2[c * per_c2 + ((ai * a.A[1] + j1o + g) * R2 + j2) * QT + q] = acc[g];
+        if (g < ng)
+#pragma unroll
+          for (int v = 0; v < kV; ++v)
+            buf2[c * per_c2 + ((ai * a.A[1] + j1o + g) * R2 + j2) * QT + q + v] = acc[g][v];
     }
     __syncthreads();
     CoarseAddr<D> ca;
     ca.init(a, ci, beta, q0);
     // coarse[lo+ai][j1o][j2o][q] = sum_c sum_j2 M2_c[j2][j2o] buf2[c][ai][j1o][j2][q]
     const int ng2 = (c2 + kG - 1) / kG;
-    for (int idx = threadIdx.x; idx < ng2 * na * c1 * QT; idx += kThreads) {
-      int q, j1o, t;
+    for (int idx = threadIdx.x; idx < ng2 * na * c1 * NQV; idx += kThreads) {
+      int qi, j1o, t;
       if (a.coarse_global) {
         j1o = idx % c1;
         t = idx / c1;
-        q = t % QT;
-        t /= QT;
+        qi = t % NQV;
+        t /= NQV;
       } else {
-        q = idx % QT;
-        t = idx / QT;
+        qi = idx % NQV;
+        t = idx / NQV;
         j1o = t % c1;
         t /= c1;
       }
+      const int q = qi * kV;
       const int ai = t % na, j2o = (t / na) * kG, ng = min(kG, c2 - j2o);
       if (q >= Qa) continue;
-      C acc[kG];
-      gzero(acc);
+      C acc[kG][kV];
+      gzero2(acc);
       for (int c = 0; c < nchild; ++c) {
         const C* src = buf2 + c * per_c2 + ((ai * a.A[1] + j1o) * R2) * QT + q;
-        gdot(acc, ng, crk[c][2], [&](int g, int j) { return mat(c, 2, j, j2o + g); },
-             [&](int j) { return src[j * QT]; });
+        gdotv(acc, ng, crk[c][2], [&](int g, int j) { return mat(c, 2, j, j2o + g); },
+              [&](int j, int v) { return src[j * QT + v]; });
       }
       C* dst = coarse + ca.base + sg[0].pos(lo + ai) * ca.stride[0] + sg[1].pos(j1o) * ca.stride[1] +
                q * ca.qstride;
 #pragma unroll
       for (int g = 0; g < kG; ++g)
-        if (g < ng) dst[sg[2].pos(j2o + g) * ca.stride[2]] = acc[g];
+        if (g < ng)
+#pragma unroll
+          for (int v = 0; v < kV; ++v)
+            if (v < Qa - q) dst[sg[2].pos(j2o + g) * ca.stride[2] + v * ca.qstride] = acc[g][v];
     }
   }
 }
@@ -2524,25 +2590,27 @@ static StageArgs stage_args(const Plan& p, const Level& fine, const Level* coars
   return a;
 }
 
-template <class T, int D, int QT, int G>
+template <class T, int D, int QT, int G, int V>
 static tb_status launch_fanout(StageArgs a, dim3 grid, size_t lds, const void* in, void* out,
                                const void* mats, hipStream_t stream) {
   using C = typename CplxOf<T>::type;
-  TB_TRY(set_lds(stage_fanout<T, D, QT, G>, lds));
-  stage_fanout<T, D, QT, G><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+  TB_TRY(set_lds(stage_fanout<T, D, QT, G, V>, lds));
+  stage_fanout<T, D, QT, G, V><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
   return TB_OK;
 }
 
-template <class T, int D, int QT, int G>
+template <class T, int D, int QT, int G, int V>
 static tb_status launch_fanin(StageArgs a, bool sm, dim3 grid, size_t lds, const void* in, void* out,
                               const void* mats, hipStream_t stream) {
   using C = typename CplxOf<T>::type;
   if (sm) {
-    TB_TRY(set_lds(stage_fanin<T, D, QT, true, G>, lds));
-    stage_fanin<T, D, QT, true, G><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+    TB_TRY(set_lds(stage_fanin<T, D, QT, true, G, V>, lds));
+    stage_fanin<T, D, QT, true, G, V><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out,
+                                                                      (const C*)mats);
   } else {
-    TB_TRY(set_lds(stage_fanin<T, D, QT, false, G>, lds));
-    stage_fanin<T, D, QT, false, G><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+    TB_TRY(set_lds(stage_fanin<T, D, QT, false, G, V>, lds));
+    stage_fanin<T, D, QT, false, G, V><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out,
+                                                                       (const C*)mats);
   }
   return TB_OK;
 }
@@ -2712,21 +2780,28 @@ static tb_status launch_stage_xmfma(const Plan& p, StageArgs a, bool fanout, int
 }
 
 template <class T, int D, int G>
-static tb_status launch_stage_g(StageArgs a, bool fanout, bool sm, int QT, dim3 grid, size_t lds,
+static tb_status launch_stage_g(StageArgs a, bool fanout, bool sm, int QT, int V, dim3 grid, size_t lds,
                                 const void* in, void* out, const void* mats, hipStream_t stream) {
+  if (V == 4) {  // four right-hand sides per thread: tiles of 4 or 8
+    if (fanout)
+      return QT == 4 ? launch_fanout<T, D, 4, G, 4>(a, grid, lds, in, out, mats, stream)
+                     : launch_fanout<T, D, 8, G, 4>(a, grid, lds, in, out, mats, stream);
+    return QT == 4 ? launch_fanin<T, D, 4, G, 4>(a, sm, grid, lds, in, out, mats, stream)
+                   : launch_fanin<T, D, 8, G, 4>(a, sm, grid, lds, in, out, mats, stream);
+  }
   if (fanout) {
     switch (QT) {
-      case 1: return launch_fanout<T, D, 1, G>(a, grid, lds, in, out, mats, stream);
-      case 2: return launch_fanout<T, D, 2, G>(a, grid, lds, in, out, mats, stream);
-      case 4: return launch_fanout<T, D, 4, G>(a, grid, lds, in, out, mats, stream);
-      default: return launch_fanout<T, D, 8, G>(a, grid, lds, in, out, mats, stream);
+      case 1: return launch_fanout<T, D, 1, G, 1>(a, grid, lds, in, out, mats, stream);
+      case 2: return launch_fanout<T, D, 2, G, 1>(a, grid, lds, in, out, mats, stream);
+      case 4: return launch_fanout<T, D, 4, G, 1>(a, grid, lds, in, out, mats, stream);
+      default: return launch_fanout<T, D, 8, G, 1>(a, grid, lds, in, out, mats, stream);
     }
   }
   switch (QT) {
-    case 1: return launch_fanin<T, D, 1, G>(a, sm, grid, lds, in, out, mats, stream);
-    case 2: return launch_fanin<T, D, 2, G>(a, sm, grid, lds, in, out, mats, stream);
-    case 4: return launch_fanin<T, D, 4, G>(a, sm, grid, lds, in, out, mats, stream);
-    default: return launch_fanin<T, D, 8, G>(a, sm, grid, lds, in, out, mats, stream);
+    case 1: return launch_fanin<T, D, 1, G, 1>(a, sm, grid, lds, in, out, mats, stream);
+    case 2: return launch_fanin<T, D, 2, G, 1>(a, sm, grid, lds, in, out, mats, stream);
+    case 4: return launch_fanin<T, D, 4, G, 1>(a, sm, grid, lds, in, out, mats, stream);
+    default: return launch_fanin<T, D, 8, G, 1>(a, sm, grid, lds, in, out, mats, stream);
   }
 }
 
@@ -2771,13 +2846,15 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
   if (nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many right-hand sides for one launch");
   dim3 grid((unsigned)nwg);
   const int G = cfg.G > 0 ? cfg.G : (QT >= 4 ? 8 : 1);
+  const int V = cfg.V > 0 ? cfg.V : 1;
+  if (V != 1 && (V != 4 || QT < 4)) return fail(TB_ERR_UNSUPPORTED, "RHS per thread needs a tile of 4 or 8");
   tb_status st;
   if (G == 8)
-    st = d == 2 ? launch_stage_g<T, 2, 8>(a, fanout, sm, QT, grid, lds, in, out, mats, stream)
-                : launch_stage_g<T, 3, 8>(a, fanout, sm, QT, grid, lds, in, out, mats, stream);
+    st = d == 2 ? launch_stage_g<T, 2, 8>(a, fanout, sm, QT, V, grid, lds, in, out, mats, stream)
+                : launch_stage_g<T, 3, 8>(a, fanout, sm, QT, V, grid, lds, in, out, mats, stream);
   else
-    st = d == 2 ? launch_stage_g<T, 2, 1>(a, fanout, sm, QT, grid, lds, in, out, mats, stream)
-                : launch_stage_g<T, 3, 1>(a, fanout, sm, QT, grid, lds, in, out, mats, stream);
+    st = d == 2 ? launch_stage_g<T, 2, 1>(a, fanout, sm, QT, V, grid, lds, in, out, mats, stream)
+                : launch_stage_g<T, 3, 1>(a, fanout, sm, QT, V, grid, lds, in, out, mats, stream);
   TB_TRY(st);
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;
@@ -3163,13 +3240,16 @@ static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout, bool
   for (int qt : {1, 2, 4, 8}) {
     if (qt > 1 && qt > nrhs) break;
     for (int g : {1, 8})
-      for (int split : {0, 1}) {
-        LaunchCfg c;
-        c.G = g;
-        c.QT = qt;
-        c.split = split;
-        out.push_back(c);
-      }
+      for (int split : {0, 1})
+        for (int v : {1, 4}) {
+          if (v == 4 && qt < 4) continue;  // four right-hand sides per thread
+          LaunchCfg c;
+          c.G = g;
+          c.QT = qt;
+          c.split = split;
+          c.V = v;
+          out.push_back(c);
+        }
     if (!fanout) {
       LaunchCfg c;
       c.QT = qt;
@@ -3221,15 +3301,15 @@ static bool read_cache(const char* path, uint64_t sig, int io, long long nrhs, s
     unsigned long long s = 0;
     int fio = 0, n = 0, pos = 0;
     long long fr = 0;
-    if (std::sscanf(line, "tbtune4 %llx %d %lld %d%n", &s, &fio, &fr, &n, &pos) != 4) continue;
+    if (std::sscanf(line, "tbtune5 %llx %d %lld %d%n", &s, &fio, &fr, &n, &pos) != 4) continue;
     if (s != sig || fio != io || fr != nrhs || (size_t)n != nslots) continue;
     std::vector<LaunchCfg> v(n);
     const char* q = line + pos;
     bool ok = true;
     for (int i = 0; i < n && ok; ++i) {
       int used = 0;
-      ok = std::sscanf(q, " %d,%d,%d,%d,%d,%d%n", &v[i].G, &v[i].QT, &v[i].split, &v[i].core, &v[i].alt,
-                       &v[i].mfma, &used) == 6;
+      ok = std::sscanf(q, " %d,%d,%d,%d,%d,%d,%d%n", &v[i].G, &v[i].QT, &v[i].split, &v[i].core,
+                       &v[i].alt, &v[i].mfma, &v[i].V, &used) == 7;
       q += used;
     }
     if (ok) {
@@ -3245,9 +3325,9 @@ static void append_cache(const char* path, uint64_t sig, int io, long long nrhs,
                          const std::vector<LaunchCfg>& cfg) {
   FILE* fh = std::fopen(path, "a");
   if (!fh) return;
-  std::fprintf(fh, "tbtune4 %016llx %d %lld %d", (unsigned long long)sig, io, nrhs, (int)cfg.size());
+  std::fprintf(fh, "tbtune5 %016llx %d %lld %d", (unsigned long long)sig, io, nrhs, (int)cfg.size());
   for (const LaunchCfg& c : cfg)
-    std::fprintf(fh, " %d,%d,%d,%d,%d,%d", c.G, c.QT, c.split, c.core, c.alt, c.mfma);
+    std::fprintf(fh, " %d,%d,%d,%d,%d,%d,%d", c.G, c.QT, c.split, c.core, c.alt, c.mfma, c.V);
   std::fprintf(fh, "\n");
   std::fclose(fh);
 }
@@ -3546,7 +3626,8 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   const int g = cfg->outputs_per_thread, q = cfg->rhs_tile;
   if (!(g == 0 || g == 1 || g == 8) || !(q == 0 || q == 1 || q == 2 || q == 4 || q == 8) ||
       cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 7 ||
-      cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 1 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1)
+      cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 1 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1 ||
+      !(cfg->rhs_per_thread == 0 || cfg->rhs_per_thread == 1 || cfg->rhs_per_thread == 4))
     return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");
   auto& v = p->tuned[{(int)io, nrhs}];
   if ((int)v.size() != nslots) v.assign(nslots, tb::LaunchCfg{});
@@ -3557,6 +3638,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   c.core = cfg->core_kernel;
   c.alt = cfg->fanin_in_turn;
   c.mfma = cfg->transfer_mfma;
+  c.V = cfg->rhs_per_thread;
   v[slot] = c;
   tb::drop_graphs_for(p);
   return TB_OK;

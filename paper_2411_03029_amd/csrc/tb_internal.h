@@ -100,6 +100,7 @@ struct LaunchCfg {
                   // 4 = BF16 MFMA (BF16 cores)
   int alt = 0;    // fan-in: 1 = children in turn, mode 0 in registers
   int mfma = 0;   // transfer levels: 1 = mode products on the matrix cores
+  int V = 0;      // transfer: right-hand sides per thread (1 or 4; 4 needs QT >= 4)
 };
 
 struct Plan {

@@ -51,7 +51,7 @@ def test_tuned_apply_matches_oracle_and_cache_round_trips(kind, d, n, tol, leaf,
         torch.cuda.synchronize()
         assert torch.equal(u, u2) and torch.equal(v, v2)
     lines = open(cache).read().splitlines()
-    assert len(lines) == 3 and all(l.startswith("tbtune4 ") for l in lines)
+    assert len(lines) == 3 and all(l.startswith("tbtune5 ") for l in lines)
 
 
 def test_autotune_rejects_missing_precision(tmp_path):
@@ -86,6 +86,9 @@ def _candidates(stage, nrhs, dtype):
         for g in (1, 8):
             for whole in (0, 1):
                 out.append(dict(outputs_per_thread=g, rhs_tile=qt, whole_blocks=whole))
+                if qt >= 4:
+                    out.append(dict(outputs_per_thread=g, rhs_tile=qt, whole_blocks=whole,
+                                    rhs_per_thread=4))
         if not fanout:
             out.append(dict(rhs_tile=qt, fanin_in_turn=1))
         if dtype != "c128":
