@@ -1014,30 +1014,38 @@ __global__ void __launch_bounds__(kThreads)
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
   const int q0 = blockIdx.y * QT;
   const int Qa = min(QT, a.nrhs - q0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = r0 + lane * VR;
+  const int per = (RS + 3) / 4;
+  const int j0 = w * per, j1 = min(RS, j0 + per);
+  // the first kUnroll columns are requested before F is staged, so that the
+  // stream of cores is under way during the staging and its barrier
+  const typename CV::V* col = reinterpret_cast<const typename CV::V*>(cores + core_off[pair] + min(row, RTp - VR));
+  const long long cstride = RTp / VR;   // in vectors
+  typename CV::V vv[kUnroll];
+  const bool first = row < RTp && j0 + kUnroll <= j1;
+  if (first) {
+#pragma unroll
+    for (int uu = 0; uu < kUnroll; ++uu) vv[uu] = col[(long long)(j0 + uu) * cstride];
+  }
   for (int idx = threadIdx.x; idx < RS * QT; idx += kThreads) {
     const int q = idx % QT, b = idx / QT;
     x[idx] = q < Qa ? F[(sitem * a.Es + padded_pos<D>(b, rs, a.Rs)) * a.nrhs + q0 + q] : czero<C>();
   }
   C* red = x + RS * QT;
   __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int row = r0 + lane * VR;
-  const int per = (RS + 3) / 4;
-  const int j0 = w * per, j1 = min(RS, j0 + per);
   C acc[VR][QT];
 #pragma unroll
   for (int v = 0; v < VR; ++v)
 #pragma unroll
     for (int q = 0; q < QT; ++q) acc[v][q] = czero<C>();
   if (row < RTp) {
-    const typename CV::V* col =
-        reinterpret_cast<const typename CV::V*>(cores + core_off[pair] + row);
-    const long long cstride = RTp / VR;   // in vectors
     int j = j0;
     for (; j + kUnroll <= j1; j += kUnroll) {
-      typename CV::V vv[kUnroll];
+      if (j != j0 || !first) {
 #pragma unroll
-      for (int uu = 0; uu < kUnroll; ++uu) vv[uu] = col[(long long)(j + uu) * cstride];
+        for (int uu = 0; uu < kUnroll; ++uu) vv[uu] = col[(long long)(j + uu) * cstride];
+      }
 #pragma unroll
       for (int uu = 0; uu < kUnroll; ++uu) {
         C c[VR];
@@ -1092,13 +1100,15 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-constexpr int kAdjCols = 8;   // columns per wave in the adjoint core kernel
+constexpr int kAdjCols = 8;   // columns per wave and group in the adjoint core kernel
 
-// F_{t,s}(cols) = C_{t,s}(:, cols)^H G_{t,s}.  A workgroup owns 4 kAdjCols
-// columns of one pair; each wave takes kAdjCols of them, its lanes sweep the
-// rows (VR per lane per 16-byte load, kAdjCols loads in flight) and the
-// partial dot products are reduced across the wave at the end.
-template <class T, class CS, int D, int QT>
+// F_{t,s}(cols) = C_{t,s}(:, cols)^H G_{t,s}.  A workgroup owns kGrp groups
+// of 4 kAdjCols columns of one pair (one staging of G serves them all); in
+// each group a wave takes kAdjCols columns, its lanes sweep the rows (VR per
+// lane per 16-byte load, kAdjCols loads in flight) and the partial dot
+// products are reduced across the wave.  The first group's first loads are
+// issued before G is staged.
+template <class T, class CS, int D, int QT, int kGrp>
 __global__ void __launch_bounds__(kThreads)
     core_adj(CoreArgs a, const CS* __restrict__ cores, const long long* __restrict__ core_off,
              const int* __restrict__ meta, const int2* __restrict__ units,
@@ -1122,70 +1132,86 @@ __global__ void __launch_bounds__(kThreads)
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
   const int q0 = blockIdx.y * QT;
   const int Qa = min(QT, a.nrhs - q0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const typename CV::V* base = reinterpret_cast<const typename CV::V*>(cores + core_off[pair]);
+  const long long cstride = RTp / VR;
+  // columns of group g: cb(g) .. cb(g) + ncol(g) - 1; columns past the last
+  // one re-read the last valid column (results unused)
+  auto cb_of = [&](int g) { return c0 + (g * 4 + w) * kAdjCols; };
+  auto ncol_of = [&](int g) { return max(0, min(kAdjCols, RS - cb_of(g))); };
+  auto colp = [&](int g, int i) {
+    const int nc = ncol_of(g);
+    return base + (long long)(min(cb_of(g) + min(i, max(nc - 1, 0)), RS - 1)) * cstride;
+  };
+  typename CV::V vv[kAdjCols];
+  const bool first = ncol_of(0) > 0 && lane * VR < RTp;
+  if (first) {
+#pragma unroll
+    for (int i = 0; i < kAdjCols; ++i) vv[i] = colp(0, i)[lane];
+  }
   for (int idx = threadIdx.x; idx < RTp * QT; idx += kThreads) {
     const int q = idx % QT, r = idx / QT;
     y[idx] = (r < RT && q < Qa) ? G[(titem * a.Et + padded_pos<D>(r, rt, a.Rt)) * a.nrhs + q0 + q]
                                 : czero<C>();
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int cb = c0 + w * kAdjCols;
-  const int ncol = max(0, min(kAdjCols, RS - cb));
-  C acc[kAdjCols][QT];
+#pragma unroll 1
+  for (int g = 0; g < kGrp; ++g) {
+    const int cb = cb_of(g), ncol = ncol_of(g);
+    C acc[kAdjCols][QT];
 #pragma unroll
-  for (int i = 0; i < kAdjCols; ++i)
+    for (int i = 0; i < kAdjCols; ++i)
 #pragma unroll
-    for (int q = 0; q < QT; ++q) acc[i][q] = czero<C>();
-  const typename CV::V* base = reinterpret_cast<const typename CV::V*>(cores + core_off[pair]);
-  const long long cstride = RTp / VR;
-  // columns past the last one re-read the last valid column (results unused)
-  const typename CV::V* cp[kAdjCols];
+      for (int q = 0; q < QT; ++q) acc[i][q] = czero<C>();
+    const typename CV::V* cp[kAdjCols];
 #pragma unroll
-  for (int i = 0; i < kAdjCols; ++i) cp[i] = base + (long long)(cb + min(i, max(ncol - 1, 0))) * cstride;
-  if (ncol > 0) {
-    for (int rb = lane * VR; rb < RTp; rb += 64 * VR) {
-      typename CV::V vv[kAdjCols];
+    for (int i = 0; i < kAdjCols; ++i) cp[i] = colp(g, i);
+    if (ncol > 0) {
+      for (int rb = lane * VR; rb < RTp; rb += 64 * VR) {
+        if (g != 0 || rb != lane * VR || !first) {
 #pragma unroll
-      for (int i = 0; i < kAdjCols; ++i) vv[i] = cp[i][rb / VR];
-      C yv[VR][QT];
-#pragma unroll
-      for (int v = 0; v < VR; ++v)
-#pragma unroll
-        for (int q = 0; q < QT; ++q) yv[v][q] = y[(rb + v) * QT + q];
-#pragma unroll
-      for (int i = 0; i < kAdjCols; ++i) {
-        C c[VR];
-        CV::get(vv[i], c);
+          for (int i = 0; i < kAdjCols; ++i) vv[i] = cp[i][rb / VR];
+        }
+        C yv[VR][QT];
 #pragma unroll
         for (int v = 0; v < VR; ++v)
 #pragma unroll
-          for (int q = 0; q < QT; ++q) acc[i][q] = cfma_conj(acc[i][q], c[v], yv[v][q]);
+          for (int q = 0; q < QT; ++q) yv[v][q] = y[(rb + v) * QT + q];
+#pragma unroll
+        for (int i = 0; i < kAdjCols; ++i) {
+          C c[VR];
+          CV::get(vv[i], c);
+#pragma unroll
+          for (int v = 0; v < VR; ++v)
+#pragma unroll
+            for (int q = 0; q < QT; ++q) acc[i][q] = cfma_conj(acc[i][q], c[v], yv[v][q]);
+        }
       }
     }
-  }
-#pragma unroll
-  for (int i = 0; i < kAdjCols; ++i)
-#pragma unroll
-    for (int q = 0; q < QT; ++q) {
-      T re = acc[i][q].x, im = acc[i][q].y;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        re += __shfl_xor(re, o, 64);
-        im += __shfl_xor(im, o, 64);
-      }
-      acc[i][q].x = re;
-      acc[i][q].y = im;
-    }
-  if (lane < ncol) {
-    // lane i writes column cb + i (values are identical across lanes)
 #pragma unroll
     for (int i = 0; i < kAdjCols; ++i)
-      if (i == lane) {
-        const long long pos = padded_pos<D>(cb + i, rs, a.Rs);
 #pragma unroll
-        for (int q = 0; q < QT; ++q)
-          if (q < Qa) F[(sitem * a.Es + pos) * a.nrhs + q0 + q] = acc[i][q];
+      for (int q = 0; q < QT; ++q) {
+        T re = acc[i][q].x, im = acc[i][q].y;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          re += __shfl_xor(re, o, 64);
+          im += __shfl_xor(im, o, 64);
+        }
+        acc[i][q].x = re;
+        acc[i][q].y = im;
       }
+    if (lane < ncol) {
+      // lane i writes column cb + i (values are identical across lanes)
+#pragma unroll
+      for (int i = 0; i < kAdjCols; ++i)
+        if (i == lane) {
+          const long long pos = padded_pos<D>(cb + i, rs, a.Rs);
+#pragma unroll
+          for (int q = 0; q < QT; ++q)
+            if (q < Qa) F[(sitem * a.Es + pos) * a.nrhs + q0 + q] = acc[i][q];
+        }
+    }
   }
   if (c0 == 0) {
     for (long long p = threadIdx.x; p < a.Es; p += kThreads)
@@ -2877,8 +2903,9 @@ static tb_status launch_core_q(const Plan& p, CoreArgs a, bool adjoint, const vo
   } else {
     const size_t lds = (size_t)maxRTp * QT * sizeof(C);
     if (lds > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "core block exceeds the LDS budget");
-    TB_TRY(set_lds(core_adj<T, CS, D, QT>, lds));
-    core_adj<T, CS, D, QT><<<dim3((unsigned)p.adj_units.size(), gy), kThreads, lds, stream>>>(
+    // 64-column panels (two column groups per workgroup)
+    TB_TRY(set_lds(core_adj<T, CS, D, QT, 2>, lds));
+    core_adj<T, CS, D, QT, 2><<<dim3((unsigned)p.adj_units.size(), gy), kThreads, lds, stream>>>(
         a, (const CS*)cores, p.core_off_d, p.pair_meta_d, p.adj_units_d, (const C*)in, (C*)out);
   }
   TB_HIP_TRY(hipGetLastError());
@@ -3050,8 +3077,8 @@ static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const vo
   const size_t point = p.kind == TB_KERNEL_RADON ? sizeof(double4) : sizeof(int4);
   const size_t lds = (size_t)along * point + ((size_t)along + kThreads) * QT * sizeof(float2);
   if (lds > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "on-the-fly core block exceeds the LDS limit");
-  const std::vector<int2>& units = adjoint ? p.otf_adj_units : p.fwd_units[0];
-  const int2* units_d = adjoint ? p.otf_adj_units_d : p.fwd_units_d[0];
+  const std::vector<int2>& units = adjoint ? p.adj_units : p.fwd_units[0];
+  const int2* units_d = adjoint ? p.adj_units_d : p.fwd_units_d[0];
   dim3 grid((unsigned)units.size(), (unsigned)((nrhs + QT - 1) / QT));
   auto go = [&](auto kern) -> tb_status {
     TB_TRY(set_lds(kern, lds));

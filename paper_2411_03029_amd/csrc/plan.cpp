@@ -145,10 +145,9 @@ tb_status build_core_tables(Plan& p) {
   p.core_off.assign((size_t)p.npairs, 0);
   long long off = 0;
   for (auto& v : p.fwd_units) v.clear();
-  p.adj_units.clear();
   p.mfma_fwd_units.clear();
   p.mfma_adj_units.clear();
-  p.otf_adj_units.clear();
+  p.adj_units.clear();
   for (long long t = 0; t < p.nT; ++t)
     for (long long s = 0; s < p.nS; ++s) {
       long long pr = t * p.nS + s;
@@ -170,19 +169,17 @@ tb_status build_core_tables(Plan& p) {
       off += (long long)RTp * RS;
       for (int lv = 0; lv < 3; ++lv)
         for (int r0 = 0; r0 < RT; r0 += 64 << lv) p.fwd_units[lv].push_back(make_int2((int)pr, r0));
-      for (int c0 = 0; c0 < RS; c0 += 32) p.adj_units.push_back(make_int2((int)pr, c0));
       for (int r0 = 0; r0 < RT; r0 += 256) p.mfma_fwd_units.push_back(make_int2((int)pr, r0));
       for (int c0 = 0; c0 < RS; c0 += 256) p.mfma_adj_units.push_back(make_int2((int)pr, c0));
-      for (int c0 = 0; c0 < RS; c0 += 64) p.otf_adj_units.push_back(make_int2((int)pr, c0));
+      for (int c0 = 0; c0 < RS; c0 += 64) p.adj_units.push_back(make_int2((int)pr, c0));
     }
   p.core_total = off;
   TB_TRY(upload(p, &p.pair_meta_d, p.pair_meta));
   TB_TRY(upload(p, &p.core_off_d, p.core_off));
   for (int lv = 0; lv < 3; ++lv) TB_TRY(upload(p, &p.fwd_units_d[lv], p.fwd_units[lv]));
-  TB_TRY(upload(p, &p.adj_units_d, p.adj_units));
   TB_TRY(upload(p, &p.mfma_fwd_units_d, p.mfma_fwd_units));
   TB_TRY(upload(p, &p.mfma_adj_units_d, p.mfma_adj_units));
-  TB_TRY(upload(p, &p.otf_adj_units_d, p.otf_adj_units));
+  TB_TRY(upload(p, &p.adj_units_d, p.adj_units));
   // skeleton tables of the two top levels, padded with a valid index
   int Rs = 0, Rt = 0;
   for (int k = 0; k < d; ++k) {

@@ -122,16 +122,16 @@ struct Plan {
   int* pair_meta_d = nullptr;
   long long* core_off_d = nullptr;
   // core work lists: forward row panels of 64 VR rows (index log2 VR, for
-  // VR = 1, 2, 4 rows per 16-byte load) / adjoint panels of 32 columns
-  std::vector<int2> fwd_units[3], adj_units;
+  // VR = 1, 2, 4 rows per 16-byte load)
+  std::vector<int2> fwd_units[3];
   int2* fwd_units_d[3] = {nullptr, nullptr, nullptr};
-  int2* adj_units_d = nullptr;
   // many right-hand sides (matrix cores): 256-row / 256-column panels
   std::vector<int2> mfma_fwd_units, mfma_adj_units;
   int2* mfma_fwd_units_d = nullptr;
   int2* mfma_adj_units_d = nullptr;
-  std::vector<int2> otf_adj_units;      // (pair, first column), 64 columns
-  int2* otf_adj_units_d = nullptr;
+  // adjoint panels (pair, first column) of 64 columns: vector and on-the-fly
+  std::vector<int2> adj_units;
+  int2* adj_units_d = nullptr;
   // device skeleton tables of the two top levels (core evaluation)
   int* top_src_skel_d = nullptr;     // [item][k][Rs]
   int* top_tgt_skel_d = nullptr;     // [item][k][Rt]
