@@ -210,7 +210,9 @@ typedef struct {
                              into bf16 hi + lo); 5, 6, 7 = BF16 matrix cores, second form, with
                              256 x 32, 128 x 64, 128 x 32 (rows x right-hand sides) per
                              workgroup */
-  int fanin_in_turn;      /* fan-in stages: 1 = children in turn, first mode in registers */
+  int fanin_in_turn;      /* fan-in stages: 1 = children in turn, first mode in registers;
+                             2 = children in turn, first mode first, the coarse slice summed
+                             in LDS (8 outputs per thread) */
   int transfer_mfma;      /* transfer levels (not the leaves), FP32 / BF16 applies: 1 = mode
                              products on the matrix cores, one block per workgroup */
   int rhs_per_thread;     /* fan-out / fan-in kernels: 1 or 4 right-hand sides per thread

@@ -716,6 +716,271 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// ------------------------------------------ fan-in, children in turn (2) --
+// The sum of stage_fanin with the 2^d children taken one after the other and
+// the first mode contracted first, on the slice's rows: one child's
+// intermediates live in LDS at a time, and the slice of the coarse block
+// accumulates in LDS, each entry owned by one thread for all the children,
+// so the order of the sum per output is that of stage_fanin.  It needs far
+// less LDS per right-hand side than stage_fanin, so wider RHS tiles fit.
+template <class T, int D, int QT, int kG, int kV>
+__global__ void __launch_bounds__(kThreads)
+    stage_fanin_turn(StageArgs a, const typename CplxOf<T>::type* __restrict__ fine,
+                     typename CplxOf<T>::type* __restrict__ coarse,
+                     const typename CplxOf<T>::type* __restrict__ mats) {
+  using C = typename CplxOf<T>::type;
+  constexpr int NQV = QT / kV;  // threads along the right-hand sides
+  extern __shared__ unsigned char smem_raw[];
+  C* sm = reinterpret_cast<C*>(smem_raw);
+  const StageBid sb = stage_bid(a, QT);
+  const int ci = sb.item_blk / a.nblk;
+  int beta[D];
+  unflatten_blk<D>(sb.item_blk % a.nblk, a.nb, beta);
+  Seg sg[D];
+  coarse_segs<D>(a, ci, beta, sg);
+  const int lo = sb.split * a.chunk;
+  const int na = min(sg[0].c, lo + a.chunk) - lo;
+  if (na <= 0) return;
+  const int q0 = sb.q0;
+  const int Qa = min(QT, a.nrhs - q0);
+  const int nchild = a.coarse_global ? 1 : (1 << D);
+  __shared__ int cfi[kMaxChildren], crk[kMaxChildren][kMaxD];
+  __shared__ long long cfb[kMaxChildren];
+  if (threadIdx.x < nchild) {
+    const int c = threadIdx.x;
+    const int fi = a.coarse_global ? ci : child_of<D>(ci, a.lvl, c);
+    cfi[c] = fi;
+#pragma unroll
+    for (int k = 0; k < D; ++k) crk[c][k] = a.rank_f[((long long)fi * D + k) * a.nb + beta[k]];
+    long long fs_[D];
+    cfb[c] = fine_base<D>(a, fi, beta, q0, fs_);
+  }
+  long long fs[D];
+  (void)fine_base<D>(a, 0, beta, 0, fs);   // strides only
+  __syncthreads();
+  const int A0 = a.A[0];
+  const int R1 = a.R[1];
+  const int c1 = sg[1].c;
+  // every child's matrices, compact in LDS: M_0[j][lo + ai] transposed to
+  // [ai][j] (na x r_0), then M_k (r_k x c_k, row stride c_k) for k >= 1
+  int msz = a.chunk * a.R[0];
+#pragma unroll
+  for (int k = 1; k < D; ++k) msz += a.R[k] * a.A[k];
+  C* mall = sm;
+  for (int c = 0; c < nchild; ++c) {
+    const C* mbase = mats + (long long)cfi[c] * a.mat_item_stride;
+    int off = c * msz;
+    {
+      const C* src = mbase + a.mat_k_off[0] + (long long)beta[0] * a.R[0] * A0;
+      const int r0 = crk[c][0];
+      for (int i = threadIdx.x; i < na * r0; i += kThreads) {
+        const int ai = i / r0, j = i % r0;
+        C v = src[j * A0 + sg[0].pos(lo + ai)];
+        if (a.conj) v.y = -v.y;
+        mall[off + i] = v;
+      }
+    }
+    off += a.chunk * a.R[0];
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+      const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
+      const int ck = sg[k].c, rk = crk[c][k];
+      for (int i = threadIdx.x; i < rk * ck; i += kThreads) {
+        const int row = i / ck, j = i % ck;
+        C v = src[row * a.A[k] + sg[k].pos(j)];
+        if (a.conj) v.y = -v.y;
+        mall[off + i] = v;
+      }
+      off += a.R[k] * a.A[k];
+    }
+  }
+  C* buf1 = sm + nchild * msz;
+  auto mat0 = [&](int c, int ai, int j) -> C { return mall[c * msz + ai * crk[c][0] + j]; };
+  auto mat = [&](int c, int k, int j, int jo) -> C {
+    const int off = a.chunk * a.R[0] + (k == 1 ? 0 : a.R[1] * a.A[1]);
+    return mall[c * msz + off + j * sg[k].c + jo];
+  };
+  const int ng0 = (na + kG - 1) / kG;
+  CoarseAddr<D> ca;
+  ca.init(a, ci, beta, q0);
+  __syncthreads();  // staged matrices
+  if constexpr (D == 2) {
+    C* accb = buf1 + a.chunk * R1 * QT;  // [ai][j1o][q]
+    const int ng1 = (c1 + kG - 1) / kG;
+    for (int c = 0; c < nchild; ++c) {
+      // buf1[ai][j1][q] = sum_j0 M0_c[j0][pos(lo+ai)] fine_c(j0, j1, q), j1 < r1(c)
+      for (int idx = threadIdx.x; idx < ng0 * R1 * NQV; idx += kThreads) {
+        const int q = (idx % NQV) * kV;
+        int t = idx / NQV;
+        const int j1 = t % R1, a0 = (t / R1) * kG, ng = min(kG, na - a0);
+        if (j1 >= crk[c][1]) continue;
+        C acc[kG][kV];
+        gzero2(acc);
+        if (q < Qa) {
+          const C* src = fine + cfb[c] + j1 * fs[1] + q;
+          const int vmax = min(kV, Qa - q) - 1;
+          gdotv(acc, ng, crk[c][0], [&](int g, int j) { return mat0(c, a0 + g, j); },
+                [&](int j, int v) { return src[j * fs[0] + min(v, vmax)]; });
+        }
+#pragma unroll
+        for (int g = 0; g < kG; ++g)
+          if (g < ng)
+#pragma unroll
+            for (int v = 0; v < kV; ++v) buf1[((a0 + g) * R1 + j1) * QT + q + v] = acc[g][v];
+      }
+      __syncthreads();
+      // coarse[lo+ai][j1o][q] (+)= sum_j1 M1_c[j1][j1o] buf1[ai][j1][q]
+      const bool last = c == nchild - 1;
+      for (int idx = threadIdx.x; idx < ng1 * na * NQV; idx += kThreads) {
+        int qi, ai, t;
+        if (a.coarse_global) {
+          ai = idx % na;
+          t = idx / na;
+          qi = t % NQV;
+          t /= NQV;
+        } else {
+          qi = idx % NQV;
+          t = idx / NQV;
+          ai = t % na;
+          t /= na;
+        }
+        const int q = qi * kV;
+        const int j1o = t * kG, ng = min(kG, c1 - j1o);
+        if (q >= Qa) continue;
+        C acc[kG][kV];
+        C* ab = accb + (ai * a.A[1] + j1o) * QT + q;
+        gzero2(acc);
+        if (c > 0) {
+#pragma unroll
+          for (int g = 0; g < kG; ++g)
+            if (g < ng)
+#pragma unroll
+              for (int v = 0; v < kV; ++v) acc[g][v] = ab[g * QT + v];
+        }
+        const C* src = buf1 + (ai * R1) * QT + q;
+        gdotv(acc, ng, crk[c][1], [&](int g, int j) { return mat(c, 1, j, j1o + g); },
+              [&](int j, int v) { return src[j * QT + v]; });
+        if (!last) {
+#pragma unroll
+          for (int g = 0; g < kG; ++g)
+            if (g < ng)
+#pragma unroll
+              for (int v = 0; v < kV; ++v) ab[g * QT + v] = acc[g][v];
+        } else {
+          C* dst = coarse + ca.base + sg[0].pos(lo + ai) * ca.stride[0] + q * ca.qstride;
+#pragma unroll
+          for (int g = 0; g < kG; ++g)
+            if (g < ng)
+#pragma unroll
+              for (int v = 0; v < kV; ++v)
+                if (v < Qa - q) dst[sg[1].pos(j1o + g) * ca.stride[1] + v * ca.qstride] = acc[g][v];
+        }
+      }
+      __syncthreads();  // buf1 is rewritten by the next child
+    }
+  } else {
+    const int R2 = a.R[2];
+    const int c2 = sg[2].c;
+    C* buf2 = buf1 + a.chunk * R1 * R2 * QT;        // [ai][j1o][j2][q]
+    C* accb = buf2 + a.chunk * a.A[1] * R2 * QT;    // [ai][j1o][j2o][q]
+    const int ng1 = (c1 + kG - 1) / kG;
+    const int ng2 = (c2 + kG - 1) / kG;
+    for (int c = 0; c < nchild; ++c) {
+      // buf1[ai][j1][j2][q] = sum_j0 M0_c[j0][pos(lo+ai)] fine_c(j0, j1, j2, q)
+      for (int idx = threadIdx.x; idx < ng0 * R1 * R2 * NQV; idx += kThreads) {
+        const int q = (idx % NQV) * kV;
+        int t = idx / NQV;
+        const int j2 = t % R2;
+        t /= R2;
+        const int j1 = t % R1, a0 = (t / R1) * kG, ng = min(kG, na - a0);
+        if (j1 >= crk[c][1] || j2 >= crk[c][2]) continue;
+        C acc[kG][kV];
+        gzero2(acc);
+        if (q < Qa) {
+          const C* src = fine + cfb[c] + j1 * fs[1] + j2 * fs[2] + q;
+          const int vmax = min(kV, Qa - q) - 1;
+          gdotv(acc, ng, crk[c][0], [&](int g, int j) { return mat0(c, a0 + g, j); },
+                [&](int j, int v) { return src[j * fs[0] + min(v, vmax)]; });
+        }
+#pragma unroll
+        for (int g = 0; g < kG; ++g)
+          if (g < ng)
+#pragma unroll
+            for (int v = 0; v < kV; ++v) buf1[(((a0 + g) * R1 + j1) * R2 + j2) * QT + q + v] = acc[g][v];
+      }
+      __syncthreads();
+      // buf2[ai][j1o][j2][q] = sum_j1 M1_c[j1][j1o] buf1[ai][j1][j2][q]
+      for (int idx = threadIdx.x; idx < ng1 * na * R2 * NQV; idx += kThreads) {
+        const int q = (idx % NQV) * kV;
+        int t = idx / NQV;
+        const int j2 = t % R2;
+        t /= R2;
+        const int ai = t % na, j1o = (t / na) * kG, ng = min(kG, c1 - j1o);
+        if (j2 >= crk[c][2]) continue;
+        C acc[kG][kV];
+        gzero2(acc);
+        const C* src = buf1 + ((ai * R1) * R2 + j2) * QT + q;
+        gdotv(acc, ng, crk[c][1], [&](int g, int j) { return mat(c, 1, j, j1o + g); },
+              [&](int j, int v) { return src[j * R2 * QT + v]; });
+#pragma unroll
+        for (int g = 0; g < kG; ++g)
+          if (g < ng)
+#pragma unroll
+            for (int v = 0; v < kV; ++v) buf2[((ai * a.A[1] + j1o + g) * R2 + j2) * QT + q + v] = acc[g][v];
+      }
+      __syncthreads();
+      // coarse[lo+ai][j1o][j2o][q] (+)= sum_j2 M2_c[j2][j2o] buf2[ai][j1o][j2][q]
+      const bool last = c == nchild - 1;
+      for (int idx = threadIdx.x; idx < ng2 * na * c1 * NQV; idx += kThreads) {
+        int qi, j1o, t;
+        if (a.coarse_global) {
+          j1o = idx % c1;
+          t = idx / c1;
+          qi = t % NQV;
+          t /= NQV;
+        } else {
+          qi = idx % NQV;
+          t = idx / NQV;
+          j1o = t % c1;
+          t /= c1;
+        }
+        const int q = qi * kV;
+        const int ai = t % na, j2o = (t / na) * kG, ng = min(kG, c2 - j2o);
+        if (q >= Qa) continue;
+        C acc[kG][kV];
+        C* ab = accb + ((ai * a.A[1] + j1o) * a.A[2] + j2o) * QT + q;
+        gzero2(acc);
+        if (c > 0) {
+#pragma unroll
+          for (int g = 0; g < kG; ++g)
+            if (g < ng)
+#pragma unroll
+              for (int v = 0; v < kV; ++v) acc[g][v] = ab[g * QT + v];
+        }
+        const C* src = buf2 + ((ai * a.A[1] + j1o) * R2) * QT + q;
+        gdotv(acc, ng, crk[c][2], [&](int g, int j) { return mat(c, 2, j, j2o + g); },
+              [&](int j, int v) { return src[j * QT + v]; });
+        if (!last) {
+#pragma unroll
+          for (int g = 0; g < kG; ++g)
+            if (g < ng)
+#pragma unroll
+              for (int v = 0; v < kV; ++v) ab[g * QT + v] = acc[g][v];
+        } else {
+          C* dst = coarse + ca.base + sg[0].pos(lo + ai) * ca.stride[0] + sg[1].pos(j1o) * ca.stride[1] +
+                   q * ca.qstride;
+#pragma unroll
+          for (int g = 0; g < kG; ++g)
+            if (g < ng)
+#pragma unroll
+              for (int v = 0; v < kV; ++v)
+                if (v < Qa - q) dst[sg[2].pos(j2o + g) * ca.stride[2] + v * ca.qstride] = acc[g][v];
+        }
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------ fan-in, in turn --
 // The same sum as stage_fanin, with the 2^d children taken one after the
 // other: per child the modes D-1 .. 1 are contracted through LDS (one
@@ -2831,6 +3096,82 @@ static tb_status launch_stage_g(StageArgs a, bool fanout, bool sm, int QT, int V
   }
 }
 
+// LDS elements of stage_fanin_turn for a slice of `chunk` rows and QT
+// right-hand sides (padded extents bound the true ones).
+static long long turn_lds_elems(const StageArgs& a, int d, int chunk, int QT) {
+  const long long nchild = a.coarse_global ? 1 : (1LL << d);
+  long long msz = (long long)chunk * a.R[0];
+  for (int k = 1; k < d; ++k) msz += (long long)a.R[k] * a.A[k];
+  long long e = nchild * msz;
+  if (d == 2) return e + (long long)chunk * (a.R[1] + a.A[1]) * QT;
+  return e + (long long)chunk *
+                 ((long long)a.R[1] * a.R[2] + (long long)a.A[1] * a.R[2] + (long long)a.A[1] * a.A[2]) * QT;
+}
+
+template <class T, int D, int QT, int V>
+static tb_status launch_fanin_turn(StageArgs a, dim3 grid, size_t lds, const void* in, void* out,
+                                   const void* mats, hipStream_t stream) {
+  using C = typename CplxOf<T>::type;
+  TB_TRY(set_lds(stage_fanin_turn<T, D, QT, 8, V>, lds));
+  stage_fanin_turn<T, D, QT, 8, V><<<grid, kThreads, lds, stream>>>(a, (const C*)in, (C*)out,
+                                                                   (const C*)mats);
+  return TB_OK;
+}
+
+template <class T, int D>
+static tb_status launch_turn_q(StageArgs a, int QT, int V, dim3 grid, size_t lds, const void* in, void* out,
+                               const void* mats, hipStream_t stream) {
+  if (V == 4)
+    return QT == 4 ? launch_fanin_turn<T, D, 4, 4>(a, grid, lds, in, out, mats, stream)
+                   : launch_fanin_turn<T, D, 8, 4>(a, grid, lds, in, out, mats, stream);
+  switch (QT) {
+    case 1: return launch_fanin_turn<T, D, 1, 1>(a, grid, lds, in, out, mats, stream);
+    case 2: return launch_fanin_turn<T, D, 2, 1>(a, grid, lds, in, out, mats, stream);
+    case 4: return launch_fanin_turn<T, D, 4, 1>(a, grid, lds, in, out, mats, stream);
+    default: return launch_fanin_turn<T, D, 8, 1>(a, grid, lds, in, out, mats, stream);
+  }
+}
+
+// Fan-in with the children in turn and the first mode first
+// (stage_fanin_turn; 8 outputs per thread): the same tile and slice choices
+// as launch_stage, with its own LDS size.
+template <class T>
+static tb_status launch_stage_turn(const Plan& p, StageArgs a, int n_items, const void* in, void* out,
+                                   const void* mats, hipStream_t stream, const LaunchCfg& cfg) {
+  using C = typename CplxOf<T>::type;
+  const int d = p.d;
+  int limit = 0;
+  TB_TRY(lds_limit(&limit));
+  const long long budget = std::min<long long>(limit, 80 * 1024);
+  const long long blocks = (long long)n_items * a.nblk;
+  const int dim = a.A[0];
+  const int qcap = cfg.QT > 0 ? cfg.QT : 8;
+  int QT = 1;
+  while (QT * 2 <= qcap && QT * 2 <= a.nrhs) QT *= 2;
+  while (QT > 1 && turn_lds_elems(a, d, 1, QT) * (long long)sizeof(C) > budget) QT /= 2;
+  if (cfg.QT > 0 && QT != cfg.QT) return fail(TB_ERR_UNSUPPORTED, "RHS tile does not fit this stage");
+  if (cfg.G != 0 && cfg.G != 8) return fail(TB_ERR_UNSUPPORTED, "the in-turn fan-in takes 8 outputs per thread");
+  const int V = cfg.V > 0 ? cfg.V : 1;
+  if (V != 1 && (V != 4 || QT < 4)) return fail(TB_ERR_UNSUPPORTED, "RHS per thread needs a tile of 4 or 8");
+  int chunk = cfg.split == 1
+                  ? dim
+                  : (int)std::max<long long>(1, (dim * blocks + kTargetWorkgroups - 1) / kTargetWorkgroups);
+  chunk = std::min(chunk, dim);
+  while (chunk > 1 && turn_lds_elems(a, d, chunk, QT) * (long long)sizeof(C) > budget) --chunk;
+  const size_t lds = (size_t)turn_lds_elems(a, d, chunk, QT) * sizeof(C);
+  if (lds > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "in-turn fan-in exceeds the LDS limit");
+  a.chunk = chunk;
+  a.nsplit = (dim + chunk - 1) / chunk;
+  const long long nwg = blocks * a.nsplit * ((a.nrhs + QT - 1) / QT);
+  if (nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many right-hand sides for one launch");
+  dim3 grid((unsigned)nwg);
+  const tb_status st = d == 2 ? launch_turn_q<T, 2>(a, QT, V, grid, lds, in, out, mats, stream)
+                              : launch_turn_q<T, 3>(a, QT, V, grid, lds, in, out, mats, stream);
+  TB_TRY(st);
+  TB_HIP_TRY(hipGetLastError());
+  return TB_OK;
+}
+
 // One transfer launch.  cfg fields left at 0 take the heuristic: the
 // largest RHS tile QT <= 8 that fits the LDS budget, G = 8 from QT = 4 on,
 // and slices of the first mode until about kTargetWorkgroups workgroups
@@ -2840,9 +3181,10 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
                               void* out, const void* mats, hipStream_t stream, const LaunchCfg& cfg) {
   using C = typename CplxOf<T>::type;
   if (cfg.mfma == 1) return launch_stage_xmfma<T>(p, a, fanout, n_items, in, out, mats, stream, cfg);
-  if (cfg.alt == 1) {
+  if (cfg.alt == 1 || cfg.alt == 2) {
     if (fanout) return fail(TB_ERR_UNSUPPORTED, "no in-turn variant of the fan-out");
-    return launch_stage_seq<T>(p, a, n_items, in, out, mats, stream, cfg);
+    return cfg.alt == 1 ? launch_stage_seq<T>(p, a, n_items, in, out, mats, stream, cfg)
+                        : launch_stage_turn<T>(p, a, n_items, in, out, mats, stream, cfg);
   }
   const int d = p.d;
   int limit = 0;
@@ -3282,6 +3624,15 @@ static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout, bool
       c.QT = qt;
       c.alt = 1;
       out.push_back(c);
+      for (int v : {1, 4}) {  // children in turn, first mode first
+        if (v == 4 && qt < 4) continue;
+        LaunchCfg t;
+        t.QT = qt;
+        t.G = 8;
+        t.alt = 2;
+        t.V = v;
+        out.push_back(t);
+      }
     }
     if (fp32) {
       LaunchCfg c;
@@ -3653,7 +4004,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   const int g = cfg->outputs_per_thread, q = cfg->rhs_tile;
   if (!(g == 0 || g == 1 || g == 8) || !(q == 0 || q == 1 || q == 2 || q == 4 || q == 8) ||
       cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 7 ||
-      cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 1 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1 ||
+      cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 2 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1 ||
       !(cfg->rhs_per_thread == 0 || cfg->rhs_per_thread == 1 || cfg->rhs_per_thread == 4))
     return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");
   auto& v = p->tuned[{(int)io, nrhs}];

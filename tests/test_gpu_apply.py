@@ -196,6 +196,35 @@ def test_bf16_core_forms_agree(name, nrhs, tmp_path):
     assert relerr(to_host(outs[6][1]), bf.apply_adjoint(op, f)) <= 5e-3
 
 
+@pytest.mark.parametrize("name,nrhs", [("helm3_n32", 13), ("radon2_n32", 11), ("fourier3_n16", 9)])
+def test_fanin_forms_agree(name, nrhs, tmp_path):
+    # the fan-in with the children in turn and the first mode first sums
+    # each output in the order of the all-children fan-in (children outer,
+    # contracted index inner), so with the same RHS tile and outputs per
+    # thread both give the same bits, over ragged RHS tiles and 1 or 4
+    # right-hand sides per thread
+    torch = torch_gpu()
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path, store=("c64",))
+    slots = plan.launch_slots()
+    fanin = [i for i, st in enumerate(slots)
+             if st in ("tgt_transfer", "tgt_leaf", "src_transfer_adj", "src_leaf_adj")]
+    nfwd = len(slots) // 2
+    x = to_dev(inputs.rhs_batch(op.n, op.d, nrhs, config=93), torch.complex64)
+    for v in (1, 4):
+        outs = []
+        for turn in (0, 2):
+            say(f"[gpu] fan-in form {turn} {name} nrhs={nrhs} rhs/thread={v}")
+            for i in fanin:
+                plan.set_launch(nrhs, i, outputs_per_thread=8, rhs_tile=4, fanin_in_turn=turn,
+                                rhs_per_thread=v)
+            outs.append((plan.apply(x), plan.apply_adjoint(x)))
+            torch.cuda.synchronize()
+        assert torch.equal(outs[0][0], outs[1][0]), ("forward", v)
+        assert torch.equal(outs[0][1], outs[1][1]), ("adjoint", v)
+    assert any(i < nfwd for i in fanin) and any(i >= nfwd for i in fanin)
+
+
 def test_stage_multiply_add_split(tmp_path):
     # the per-stage split of the multiply-add count adds up, and the core
     # share is the sum of R_T R_S over the pairs, i.e. the core entries

@@ -91,6 +91,9 @@ def _candidates(stage, nrhs, dtype):
                                     rhs_per_thread=4))
         if not fanout:
             out.append(dict(rhs_tile=qt, fanin_in_turn=1))
+            out.append(dict(rhs_tile=qt, fanin_in_turn=2, outputs_per_thread=8))
+            if qt >= 4:
+                out.append(dict(rhs_tile=qt, fanin_in_turn=2, outputs_per_thread=8, rhs_per_thread=4))
         if dtype != "c128":
             out.append(dict(rhs_tile=qt, transfer_mfma=1))
     return out
