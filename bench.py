@@ -238,12 +238,12 @@ def run_single(args, tb, inputs, torch, np) -> dict:
     """Helmholtz cubes n = 64, one right-hand side (the default workload)."""
     kind, d, n, tol, nrhs = "helmholtz", 3, 64, 1e-4, 1
     t0 = time.perf_counter()
-    plan = tb.construct(kind, d, n, tol, store=("c64", "c128"))
+    plan = tb.construct(kind, d, n, tol, store=("c64", "c128", "cq16"))
     torch.cuda.synchronize()
     construct_s = time.perf_counter() - t0
     info = plan.info()
     t0 = time.perf_counter()
-    for dt in ("c64", "c128", "c64otf"):
+    for dt in ("c64", "c128", "c64otf", "cq16"):
         plan.autotune(nrhs, dtype=dt, cache=args.tune_cache)
     autotune_s = time.perf_counter() - t0
 
@@ -253,7 +253,8 @@ def run_single(args, tb, inputs, torch, np) -> dict:
 
     # outputs for the accuracy gate
     gpu_out = {}
-    for name, x, dt in (("c64", x32, "c64"), ("c128", x64, "c128"), ("c64otf", x32, "c64otf")):
+    for name, x, dt in (("c64", x32, "c64"), ("c128", x64, "c128"), ("c64otf", x32, "c64otf"),
+                        ("cq16", x32, "cq16")):
         u = plan.apply(x, dtype=dt)
         v = plan.apply_adjoint(x, dtype=dt)
         torch.cuda.synchronize()
@@ -310,6 +311,22 @@ def run_single(args, tb, inputs, torch, np) -> dict:
            "core_entries_per_s": info["core_entries"] / otf_fwd_s,
            "note": "cores K(tbar,sbar) evaluated inside the contraction (FP64 phase, FP32 sin/cos): "
                    "no stored cores, ALU-bound"}
+    # the same FP32 apply with the cores stored as block-scaled 16-bit fixed
+    # point (4 bytes per entry, one FP32 scale per column)
+    t_q16 = time_steps(plan, x32, "cq16", args.steps, args.warmup, torch)
+    plan.set_timing(True)
+    time_steps(plan, x32, "cq16", args.steps, 0, torch)
+    st_q = plan.stage_times()
+    plan.set_timing(False)
+    q_fwd_s = st_q["core"][0] / max(st_q["core"][1], 1) * 1e-3
+    q_adj_s = st_q["core_adj"][0] / max(st_q["core_adj"][1], 1) * 1e-3
+    q_bytes = 4 * info["core_entries"] + 4 * info["core_cols"] + 8 * nrhs * (info["core_rows"] + info["core_cols"])
+    q16 = {"value": points * args.steps / t_q16, "ms_per_step": 1000 * t_q16 / args.steps,
+           "core_fwd_us": round(q_fwd_s * 1e6, 2), "core_adj_us": round(q_adj_s * 1e6, 2),
+           "core_bytes_per_launch": q_bytes,
+           "core_fwd_GBs": round(q_bytes / q_fwd_s / 1e9, 1), "core_adj_GBs": round(q_bytes / q_adj_s / 1e9, 1),
+           "note": "cores as block-scaled 16-bit fixed point, decoded inside the contraction; "
+                   "FP32 factors and accumulation"}
     # whole apply per direction: every factor and core entry plus reading the
     # input and writing the output, over the summed stage times of one step
     fwd = ("src_leaf", "src_transfer", "core", "tgt_transfer", "tgt_leaf")
@@ -333,9 +350,10 @@ def run_single(args, tb, inputs, torch, np) -> dict:
         speedup_vs_fp64_plain=value / value64,
         accuracy=errors,
         **{"accuracy_gate_1e-4": (None if errors is None else
-                                  all(e["fwd"] <= 1e-4 and e["adj"] <= 1e-4
-                                      for e in errors.values()))},
+                                  all(errors[k]["fwd"] <= 1e-4 and errors[k]["adj"] <= 1e-4
+                                      for k in ("c64", "c128", "c64otf")))},
         roofline=roofline, apply_hbm=apply_hbm, stage_avg_us=stage_us, on_the_fly_cores=otf,
+        q16_cores=q16,
         cpu_baseline=cpu_base,
         construct_s=round(construct_s, 3), autotune_s=round(autotune_s, 3),
         plan={k: info[k] for k in ("L", "Lt", "Ls", "r_min", "r_max", "n_ids", "n_pairs",

@@ -71,14 +71,22 @@ typedef enum {
  * K(tbar, sbar) evaluated inside the core contraction from the skeleton
  * indices (section 2: any entry in O(1)) instead of read from memory: phase
  * formed and reduced to a fraction of a turn in FP64, sine and cosine in
- * FP32; available for every plan, stored cores or not. */
-typedef enum { TB_C128 = 0, TB_C64 = 1, TB_CBF16 = 2, TB_C64_OTF = 3 } tb_dtype;
+ * FP32; available for every plan, stored cores or not.
+ * TB_CQ16: complex64 arrays, FP32 factors and accumulation, cores stored
+ * compressed as block-scaled 16-bit fixed point (a fixed-rate core codec in
+ * the spirit of the paper's ZFP-compressed cores, section 5): one FP32 scale
+ * per core column (its largest real or imaginary magnitude / 32767) and two
+ * int16 per entry, 4 bytes per complex entry; decoded inside the core
+ * contraction.  Per entry the error is at most half a step, 2^-16 of the
+ * column's largest part. */
+typedef enum { TB_C128 = 0, TB_C64 = 1, TB_CBF16 = 2, TB_C64_OTF = 3, TB_CQ16 = 4 } tb_dtype;
 
 #define TB_STORE_C128 (1u << TB_C128)
 #define TB_STORE_C64 (1u << TB_C64)
 #define TB_STORE_CBF16 (1u << TB_CBF16)
 /* store_mask == TB_STORE_OTF keeps no cores: only TB_C64_OTF applies run. */
 #define TB_STORE_OTF (1u << TB_C64_OTF)
+#define TB_STORE_CQ16 (1u << TB_CQ16)
 
 typedef struct tb_plan_s* tb_plan;
 

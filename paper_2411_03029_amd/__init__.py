@@ -21,9 +21,9 @@ from ._lib import TBError
 KINDS = {"fourier": _lib.TB_KERNEL_FOURIER, "helmholtz": _lib.TB_KERNEL_HELMHOLTZ,
          "radon": _lib.TB_KERNEL_RADON}
 DTYPES = {"c128": _lib.TB_C128, "c64": _lib.TB_C64, "cbf16": _lib.TB_CBF16,
-          "c64otf": _lib.TB_C64_OTF}
+          "c64otf": _lib.TB_C64_OTF, "cq16": _lib.TB_CQ16}
 STORE = {"c128": _lib.TB_STORE_C128, "c64": _lib.TB_STORE_C64,
-         "cbf16": _lib.TB_STORE_CBF16, "otf": _lib.TB_STORE_OTF}
+         "cbf16": _lib.TB_STORE_CBF16, "otf": _lib.TB_STORE_OTF, "cq16": _lib.TB_STORE_CQ16}
 
 __all__ = ["construct", "load_plan", "Plan", "TBApply", "TBError",
            "helmholtz_omega"]

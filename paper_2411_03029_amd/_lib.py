@@ -15,8 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libtb.so")
 TB_OK, TB_ERR_INVALID_ARG, TB_ERR_UNSUPPORTED, TB_ERR_OOM, TB_ERR_HIP, \
     TB_ERR_NUMERIC, TB_ERR_IO = range(7)
 TB_KERNEL_FOURIER, TB_KERNEL_HELMHOLTZ, TB_KERNEL_RADON = range(3)
-TB_C128, TB_C64, TB_CBF16, TB_C64_OTF = range(4)
-TB_STORE_C128, TB_STORE_C64, TB_STORE_CBF16, TB_STORE_OTF = 1, 2, 4, 8
+TB_C128, TB_C64, TB_CBF16, TB_C64_OTF, TB_CQ16 = range(5)
+TB_STORE_C128, TB_STORE_C64, TB_STORE_CBF16, TB_STORE_OTF, TB_STORE_CQ16 = 1, 2, 4, 8, 16
 
 # every symbol include/tb.h declares
 EXPORTS = ("tb_construct", "tb_apply", "tb_apply_adjoint", "tb_apply_batched",

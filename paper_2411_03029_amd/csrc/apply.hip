@@ -1191,6 +1191,14 @@ struct CoreArgs {
   long long Es, Et;              // entries per top-level item (source / target)
   int Rs[kMaxD], Rt[kMaxD];      // padded ranks of the top levels
   int nrhs;
+  const float* colscale;         // TB_CQ16: scale per core column
+  const long long* col_off;      // TB_CQ16: first column of each pair
+};
+
+// A TB_CQ16 core entry: int16 real part (low half) and imaginary part (high
+// half) of the entry / its column's scale.
+struct Q16 {
+  unsigned w;
 };
 
 // 16-byte vector loads of the stored cores: VR consecutive rows per lane.
@@ -1217,6 +1225,20 @@ struct CoreVec<unsigned> {  // packed (bf16 re, bf16 im)
   using V = uint4;
   __device__ static float2 one(unsigned u) {
     return make_float2(bf16_to_f32((unsigned short)(u & 0xffff)), bf16_to_f32((unsigned short)(u >> 16)));
+  }
+  __device__ static void get(const V& v, float2* c) {
+    c[0] = one(v.x);
+    c[1] = one(v.y);
+    c[2] = one(v.z);
+    c[3] = one(v.w);
+  }
+};
+template <>
+struct CoreVec<Q16> {
+  static constexpr int VR = 4;
+  using V = uint4;
+  __device__ static float2 one(unsigned u) {
+    return make_float2((float)(short)(u & 0xffffu), (float)(short)(u >> 16));
   }
   __device__ static void get(const V& v, float2* c) {
     c[0] = one(v.x);
@@ -1295,7 +1317,13 @@ __global__ void __launch_bounds__(kThreads)
   }
   for (int idx = threadIdx.x; idx < RS * QT; idx += kThreads) {
     const int q = idx % QT, b = idx / QT;
-    x[idx] = q < Qa ? F[(sitem * a.Es + padded_pos<D>(b, rs, a.Rs)) * a.nrhs + q0 + q] : czero<C>();
+    C v = q < Qa ? F[(sitem * a.Es + padded_pos<D>(b, rs, a.Rs)) * a.nrhs + q0 + q] : czero<C>();
+    if constexpr (std::is_same<CS, Q16>::value) {  // C = Q S: the column scales go with F
+      const T sc = a.colscale[a.col_off[pair] + b];
+      v.x *= sc;
+      v.y *= sc;
+    }
+    x[idx] = v;
   }
   C* red = x + RS * QT;
   __syncthreads();
@@ -1472,9 +1500,18 @@ __global__ void __launch_bounds__(kThreads)
       for (int i = 0; i < kAdjCols; ++i)
         if (i == lane) {
           const long long pos = padded_pos<D>(cb + i, rs, a.Rs);
+          T sc = T(1);
+          if constexpr (std::is_same<CS, Q16>::value) sc = a.colscale[a.col_off[pair] + cb + i];
 #pragma unroll
           for (int q = 0; q < QT; ++q)
-            if (q < Qa) F[(sitem * a.Es + pos) * a.nrhs + q0 + q] = acc[i][q];
+            if (q < Qa) {
+              C v = acc[i][q];
+              if constexpr (std::is_same<CS, Q16>::value) {
+                v.x *= sc;
+                v.y *= sc;
+              }
+              F[(sitem * a.Es + pos) * a.nrhs + q0 + q] = v;
+            }
         }
     }
   }
@@ -3337,12 +3374,16 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
     a.Rt[k] = tt.R[k];
   }
   a.nrhs = nrhs;
+  a.colscale = p.core_scale;
+  a.col_off = p.col_off_d;
   int maxRS = 0, maxRTp = 0;
   for (long long pr = 0; pr < p.npairs; ++pr) {
     maxRS = std::max(maxRS, p.pair_meta[(size_t)pr * kPairMeta + 1]);
     maxRTp = std::max(maxRTp, p.pair_meta[(size_t)pr * kPairMeta + 2]);
   }
-  if constexpr (sizeof(CS) == 4) {  // BF16 cores
+  constexpr bool kQ16 = std::is_same<CS, Q16>::value;  // vector kernels only
+  if (kQ16 && cfg.core >= 3) return fail(TB_ERR_UNSUPPORTED, "16-bit cores run on the vector core kernels");
+  if constexpr (std::is_same<CS, unsigned>::value) {  // BF16 cores
     if (cfg.core >= 5 && cfg.core <= 7) {
       int maxRT = 0;
       for (long long pr = 0; pr < p.npairs; ++pr) maxRT = std::max(maxRT, p.pair_meta[(size_t)pr * kPairMeta]);
@@ -3359,7 +3400,7 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
   } else {
     if (cfg.core >= 4) return fail(TB_ERR_UNSUPPORTED, "BF16 matrix cores need BF16 cores");
   }
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 4 && !kQ16) {
     if (cfg.core == 3 || (cfg.core == 0 && nrhs >= kMfmaMinRhs))
       return d == 2 ? launch_core_mfma<CS, 2>(p, a, adjoint, cores, in, out, stream)
                     : launch_core_mfma<CS, 3>(p, a, adjoint, cores, in, out, stream);
@@ -3542,11 +3583,11 @@ static tb_status apply_typed(Plan& p, tb_dtype io, const void* in, void* out, lo
   return TB_OK;
 }
 
-static bool valid_io(int io) { return io >= TB_C128 && io <= TB_C64_OTF; }
+static bool valid_io(int io) { return io >= TB_C128 && io <= TB_CQ16; }
 
 // on-the-fly applies need no stored cores
 static bool has_cores(const Plan& p, int io) {
-  return io == TB_C64_OTF || (io >= TB_C128 && io <= TB_CBF16 && p.cores[io]);
+  return io == TB_C64_OTF || (io != TB_C64_OTF && p.cores[io]);
 }
 
 tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs, tb_dtype io, bool adjoint,
@@ -3563,6 +3604,7 @@ tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs, tb_dtype
     case TB_C64: return apply_typed<float, float2>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
     case TB_CBF16: return apply_typed<float, unsigned>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
     case TB_C64_OTF: return apply_typed<float, float2>(p, io, in, out, nrhs, adjoint, nullptr, stream);
+    case TB_CQ16: return apply_typed<float, Q16>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
   }
   return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
 }
@@ -3653,7 +3695,7 @@ static std::vector<LaunchCfg> core_candidates(long long nrhs, tb_dtype io) {
     c.core = 2;
     out.push_back(c);
   }
-  if (io != TB_C128 && io != TB_C64_OTF && nrhs >= 4) {
+  if (io != TB_C128 && io != TB_C64_OTF && io != TB_CQ16 && nrhs >= 4) {
     c.core = 3;
     out.push_back(c);
   }
@@ -3805,6 +3847,7 @@ tb_status run_autotune(Plan& p, long long nrhs, tb_dtype io, const char* cache, 
       case TB_C64: st = tune_typed<float, float2>(p, io, nrhs, stream, &best, &count); break;
       case TB_CBF16: st = tune_typed<float, unsigned>(p, io, nrhs, stream, &best, &count); break;
       case TB_C64_OTF: st = tune_typed<float, float2>(p, io, nrhs, stream, &best, &count); break;
+      case TB_CQ16: st = tune_typed<float, Q16>(p, io, nrhs, stream, &best, &count); break;
     }
     TB_TRY(st);
     if (cache) append_cache(cache, sig, io, nrhs, best);

@@ -417,6 +417,54 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// TB_CQ16 encoding, one wave per core column: the scale is the column's
+// largest real or imaginary magnitude / 32767 (FP32), and every part is
+// rounded to the nearest multiple of it (an int16); real part in the low
+// half of the word, imaginary part in the high half.  Padding rows hold 0.
+__device__ __forceinline__ unsigned q16_pack(double re, double im, float s) {
+  int qr = 0, qi = 0;
+  if (s > 0.f) {
+    qr = (int)rint(re / (double)s);
+    qi = (int)rint(im / (double)s);
+    qr = max(-32767, min(32767, qr));
+    qi = max(-32767, min(32767, qi));
+  }
+  return (unsigned)(unsigned short)(short)qr | ((unsigned)(unsigned short)(short)qi << 16);
+}
+
+template <class S>
+__global__ void __launch_bounds__(256)
+    core_encode_q16(const int* __restrict__ meta, const long long* __restrict__ off,
+                    const long long* __restrict__ col_off, const S* __restrict__ src,
+                    unsigned* __restrict__ q, float* __restrict__ scale) {
+  const int pair = blockIdx.x;
+  const int col = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int* m = meta + pair * kPairMeta;
+  const int RS = m[1], RTp = m[2];
+  if (col >= RS) return;  // whole wave; the kernel has no barrier
+  const long long b = off[pair] + (long long)col * RTp;
+  double mx = 0.0;
+  for (int r = lane; r < RTp; r += 64)
+    mx = fmax(mx, fmax(fabs((double)src[b + r].x), fabs((double)src[b + r].y)));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  const float s = (float)(mx / 32767.0);
+  for (int r = lane; r < RTp; r += 64) q[b + r] = q16_pack((double)src[b + r].x, (double)src[b + r].y, s);
+  if (lane == 0) scale[col_off[pair] + col] = s;
+}
+
+static unsigned q16_pack_host(double re, double im, float s) {
+  long qr = 0, qi = 0;
+  if (s > 0.f) {
+    qr = std::lrint(re / (double)s);
+    qi = std::lrint(im / (double)s);
+    qr = std::max(-32767L, std::min(32767L, qr));
+    qi = std::max(-32767L, std::min(32767L, qi));
+  }
+  return (unsigned)(unsigned short)(short)qr | ((unsigned)(unsigned short)(short)qi << 16);
+}
+
 static KernelSpec spec_of(const Plan& p) {
   KernelSpec ks;
   ks.kind = p.kind;
@@ -431,9 +479,30 @@ static KernelSpec spec_of(const Plan& p) {
 
 tb_status launch_core_eval(Plan& p, hipStream_t stream, const double2* host_cores) {
   unsigned mask = p.store_mask ? p.store_mask : TB_STORE_C64;
-  size_t esz[3] = {sizeof(double2), sizeof(float2), sizeof(unsigned)};
-  for (int t = 0; t < 3; ++t)
-    if (mask & (1u << t)) TB_TRY(dev_alloc(p, &p.cores[t], (size_t)p.core_total * esz[t]));
+  const size_t esz[5] = {sizeof(double2), sizeof(float2), sizeof(unsigned), 0, sizeof(unsigned)};
+  for (int t = 0; t < 5; ++t)
+    if (esz[t] && (mask & (1u << t))) TB_TRY(dev_alloc(p, &p.cores[t], (size_t)p.core_total * esz[t]));
+  if (mask & TB_STORE_CQ16)
+    TB_TRY(dev_alloc(p, reinterpret_cast<void**>(&p.core_scale), (size_t)std::max(1LL, p.col_total) * sizeof(float)));
+  if (host_cores && (mask & TB_STORE_CQ16)) {
+    const size_t N = (size_t)p.core_total;
+    std::vector<unsigned> h(N);
+    std::vector<float> sc((size_t)p.col_total);
+    for (long long pr = 0; pr < p.npairs; ++pr) {
+      const int RS = p.pair_meta[(size_t)pr * kPairMeta + 1], RTp = p.pair_meta[(size_t)pr * kPairMeta + 2];
+      for (int c = 0; c < RS; ++c) {
+        const size_t b = (size_t)(p.core_off[(size_t)pr] + (long long)c * RTp);
+        double mx = 0.0;
+        for (int r = 0; r < RTp; ++r)
+          mx = std::max(mx, std::max(std::fabs(host_cores[b + r].x), std::fabs(host_cores[b + r].y)));
+        const float s = (float)(mx / 32767.0);
+        for (int r = 0; r < RTp; ++r) h[b + r] = q16_pack_host(host_cores[b + r].x, host_cores[b + r].y, s);
+        sc[(size_t)(p.col_off[(size_t)pr] + c)] = s;
+      }
+    }
+    TB_HIP_TRY(hipMemcpy(p.cores[TB_CQ16], h.data(), N * sizeof(unsigned), hipMemcpyHostToDevice));
+    TB_HIP_TRY(hipMemcpy(p.core_scale, sc.data(), sc.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
   if (host_cores) {
     const size_t N = (size_t)p.core_total;
     if (mask & TB_STORE_C128)
@@ -452,7 +521,11 @@ tb_status launch_core_eval(Plan& p, hipStream_t stream, const double2* host_core
     }
     return TB_OK;
   }
-  if ((mask & 7u) == 0) return TB_OK;  // no stored cores (on-the-fly applies only)
+  if ((mask & 23u) == 0) return TB_OK;  // no stored cores (on-the-fly applies only)
+  // TB_CQ16 alone: FP32 entries in a temporary buffer, encoded below
+  float2* tmp64 = nullptr;
+  if ((mask & TB_STORE_CQ16) && !(mask & (TB_STORE_C128 | TB_STORE_C64)))
+    TB_HIP_TRY(hipMalloc(&tmp64, (size_t)p.core_total * sizeof(float2)));
   CoreEvalArgs a;
   a.ks = spec_of(p);
   a.nS = p.nS;
@@ -463,14 +536,31 @@ tb_status launch_core_eval(Plan& p, hipStream_t stream, const double2* host_core
     a.Rs = std::max(a.Rs, p.src[p.Lt].R[k]);
     a.Rt = std::max(a.Rt, p.tgt[p.Ls].R[k]);
   }
-  a.mask = mask;
+  a.mask = mask | (tmp64 ? TB_STORE_C64 : 0u);
   a.splits = 8;
   dim3 grid((unsigned)a.splits, (unsigned)p.npairs);
+  float2* c64 = tmp64 ? tmp64 : (float2*)p.cores[TB_C64];
   core_eval<<<grid, 256, 0, stream>>>(a, p.pair_meta_d, p.core_off_d, p.top_src_skel_d, p.top_tgt_skel_d,
-                                     (double2*)p.cores[TB_C128], (float2*)p.cores[TB_C64],
-                                     (unsigned*)p.cores[TB_CBF16]);
-  TB_HIP_TRY(hipGetLastError());
-  return TB_OK;
+                                     (double2*)p.cores[TB_C128], c64, (unsigned*)p.cores[TB_CBF16]);
+  tb_status st = hipGetLastError() == hipSuccess ? TB_OK : fail(TB_ERR_HIP, "core_eval launch failed");
+  if (st == TB_OK && (mask & TB_STORE_CQ16)) {
+    int maxRS = 1;
+    for (long long pr = 0; pr < p.npairs; ++pr) maxRS = std::max(maxRS, p.pair_meta[(size_t)pr * kPairMeta + 1]);
+    dim3 eg((unsigned)p.npairs, (unsigned)((maxRS + 3) / 4));
+    if (p.cores[TB_C128])
+      core_encode_q16<double2><<<eg, 256, 0, stream>>>(p.pair_meta_d, p.core_off_d, p.col_off_d,
+                                                      (const double2*)p.cores[TB_C128],
+                                                      (unsigned*)p.cores[TB_CQ16], p.core_scale);
+    else
+      core_encode_q16<float2><<<eg, 256, 0, stream>>>(p.pair_meta_d, p.core_off_d, p.col_off_d, c64,
+                                                     (unsigned*)p.cores[TB_CQ16], p.core_scale);
+    if (hipGetLastError() != hipSuccess) st = fail(TB_ERR_HIP, "core encoding launch failed");
+  }
+  if (tmp64) {
+    if (hipStreamSynchronize(stream) != hipSuccess && st == TB_OK) st = fail(TB_ERR_HIP, "core encoding failed");
+    (void)hipFree(tmp64);
+  }
+  return st;
 }
 
 // -------------------------------------------------------------- driver --
@@ -696,7 +786,7 @@ extern "C" tb_status tb_construct(tb_kernel kind, int d, long long n, double ome
     p.rden = d == 3 ? 100.0 : 3.0;
   }
   p.store_mask = o.store_mask ? o.store_mask : TB_STORE_C64;
-  if (p.store_mask & ~15u) return fail(TB_ERR_INVALID_ARG, "unknown store_mask bits");
+  if (p.store_mask & ~31u) return fail(TB_ERR_INVALID_ARG, "unknown store_mask bits");
   p.max_device_bytes = o.max_device_bytes;
   hipStream_t stream = static_cast<hipStream_t>(hip_stream);
   int ndev = 0;

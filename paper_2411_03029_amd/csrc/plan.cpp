@@ -143,7 +143,8 @@ tb_status build_core_tables(Plan& p) {
   const Level& ttop = p.tgt[p.Ls];
   p.pair_meta.assign((size_t)p.npairs * kPairMeta, 0);
   p.core_off.assign((size_t)p.npairs, 0);
-  long long off = 0;
+  p.col_off.assign((size_t)p.npairs, 0);
+  long long off = 0, cols = 0;
   for (auto& v : p.fwd_units) v.clear();
   p.mfma_fwd_units.clear();
   p.mfma_adj_units.clear();
@@ -167,6 +168,8 @@ tb_status build_core_tables(Plan& p) {
       m[2] = RTp;
       p.core_off[(size_t)pr] = off;
       off += (long long)RTp * RS;
+      p.col_off[(size_t)pr] = cols;
+      cols += RS;
       for (int lv = 0; lv < 3; ++lv)
         for (int r0 = 0; r0 < RT; r0 += 64 << lv) p.fwd_units[lv].push_back(make_int2((int)pr, r0));
       for (int r0 = 0; r0 < RT; r0 += 256) p.mfma_fwd_units.push_back(make_int2((int)pr, r0));
@@ -174,7 +177,9 @@ tb_status build_core_tables(Plan& p) {
       for (int c0 = 0; c0 < RS; c0 += 64) p.adj_units.push_back(make_int2((int)pr, c0));
     }
   p.core_total = off;
+  p.col_total = cols;
   TB_TRY(upload(p, &p.pair_meta_d, p.pair_meta));
+  TB_TRY(upload(p, &p.col_off_d, p.col_off));
   TB_TRY(upload(p, &p.core_off_d, p.core_off));
   for (int lv = 0; lv < 3; ++lv) TB_TRY(upload(p, &p.fwd_units_d[lv], p.fwd_units[lv]));
   TB_TRY(upload(p, &p.mfma_fwd_units_d, p.mfma_fwd_units));
@@ -445,7 +450,7 @@ extern "C" tb_status tb_plan_load(const char* path, const tb_options* opt,
   if (opt) {
     p.store_mask = opt->store_mask ? opt->store_mask : TB_STORE_C64;
     p.max_device_bytes = opt->max_device_bytes;
-    if (p.store_mask & ~15u) return fail(TB_ERR_INVALID_ARG, "unknown store_mask bits");
+    if (p.store_mask & ~31u) return fail(TB_ERR_INVALID_ARG, "unknown store_mask bits");
   }
   const int d = p.d;
   p.src.resize(p.Lt + 1);

@@ -118,7 +118,12 @@ struct Plan {
   std::vector<long long> core_off;   // npairs (elements)
   long long core_total = 0;          // elements incl. padding
   unsigned store_mask = TB_STORE_C64;
-  void* cores[3] = {nullptr, nullptr, nullptr};  // indexed by tb_dtype
+  void* cores[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // indexed by tb_dtype
+  // TB_CQ16 cores: one scale per core column at col_off[pair] + column
+  float* core_scale = nullptr;
+  std::vector<long long> col_off;    // npairs (columns before the pair)
+  long long* col_off_d = nullptr;
+  long long col_total = 0;
   int* pair_meta_d = nullptr;
   long long* core_off_d = nullptr;
   // core work lists: forward row panels of 64 VR rows (index log2 VR, for

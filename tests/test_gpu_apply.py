@@ -225,6 +225,68 @@ def test_fanin_forms_agree(name, nrhs, tmp_path):
     assert any(i < nfwd for i in fanin) and any(i >= nfwd for i in fanin)
 
 
+@pytest.mark.parametrize("name", ["helm3_n32", "radon2_n32", "fourier2_n64", "plates2_n64", "radon3_n16"])
+def test_q16_cores_match_oracle(name, tmp_path):
+    # block-scaled 16-bit cores (one scale per core column, int16 parts):
+    # per part the error is uniform within half a step, 2^-16 of the
+    # column's largest part, independent over entries, so the core stage
+    # adds a relative error of about 2^-16 * 0.6 * (column max / rms entry):
+    # 1.3e-5 for unit-modulus kernels, below 4e-5 for the Helmholtz cubes
+    # (distances 1..3).  With the FP32 bound 2e-5 the sum stays below 1e-4,
+    # per right-hand side, forward and adjoint; the plan's cores are encoded
+    # on the host from the oracle's FP64 cores
+    torch = torch_gpu()
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path, store=("cq16",))
+    n, d = op.n, op.d
+    for nrhs in (1, 6):
+        f = inputs.rhs_batch(n, d, nrhs, config=92)
+        say(f"[gpu] 16-bit cores {name} nrhs={nrhs}")
+        x = to_dev(f, torch.complex64)
+        u = to_host(plan.apply(x, dtype="cq16"))
+        v = to_host(plan.apply_adjoint(x, dtype="cq16"))
+        torch.cuda.synchronize()
+        ue, ve = bf.apply(op, f), bf.apply_adjoint(op, f)
+        for q in range(nrhs):
+            assert relerr(u[q], ue[q]) <= 1e-4, (q, relerr(u[q], ue[q]))
+            assert relerr(v[q], ve[q]) <= 1e-4, (q, relerr(v[q], ve[q]))
+
+
+def test_q16_cores_encoded_on_the_gpu(tmp_path):
+    # the device encoder (cores evaluated into a temporary FP32 buffer, then
+    # one scale per column) against the host encoder of the same plan's FP64
+    # cores: the same scales up to FP32 rounding of the entries, so the two
+    # applies agree to the quantization bound; and a plan built with the
+    # 16-bit cores alone applies within 1e-4 of the FP64 apply
+    torch = torch_gpu()
+    import paper_2411_03029_amd as tb
+    name = "helm3_n32"
+    op = oracle_plan(name)
+    host = gpu_plan(name, tmp_path, store=("cq16",))
+    dev = gpu_plan(name, tmp_path, store=("cq16",), recompute=True)
+    ref = gpu_plan(name, tmp_path, store=("c128",))
+    f = inputs.rhs_batch(op.n, op.d, 3, config=91)
+    x = to_dev(f, torch.complex64)
+    for adjoint in (False, True):
+        a = host.apply_adjoint(x, dtype="cq16") if adjoint else host.apply(x, dtype="cq16")
+        b = dev.apply_adjoint(x, dtype="cq16") if adjoint else dev.apply(x, dtype="cq16")
+        e = ref.apply_adjoint(to_dev(f, torch.complex128), dtype="c128") if adjoint else \
+            ref.apply(to_dev(f, torch.complex128), dtype="c128")
+        torch.cuda.synchronize()
+        assert relerr(to_host(b), to_host(a)) <= 1e-4
+        assert relerr(to_host(b), to_host(e)) <= 1e-4
+    lean = tb.construct("radon", 2, 32, 1e-3, store=("cq16",))
+    full = tb.construct("radon", 2, 32, 1e-3, store=("c128",))
+    assert lean.info()["device_bytes"] < full.info()["device_bytes"]
+    f = inputs.rhs_batch(32, 2, 2, config=90)
+    u = to_host(lean.apply(to_dev(f, torch.complex64), dtype="cq16"))
+    w = to_host(full.apply(to_dev(f, torch.complex128), dtype="c128"))
+    torch.cuda.synchronize()
+    assert relerr(u, w) <= 1e-4
+    with pytest.raises(tb.TBError):
+        lean.apply(to_dev(f, torch.complex64), dtype="c64")
+
+
 def test_stage_multiply_add_split(tmp_path):
     # the per-stage split of the multiply-add count adds up, and the core
     # share is the sum of R_T R_S over the pairs, i.e. the core entries

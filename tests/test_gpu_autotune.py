@@ -77,6 +77,8 @@ def _candidates(stage, nrhs, dtype):
             out.append(dict(core_kernel=3))
         if dtype == "cbf16" and nrhs >= 4:
             out += [dict(core_kernel=v) for v in (4, 5, 6, 7)]
+        if dtype == "cq16":
+            out = [c for c in out if c["core_kernel"] <= 2]
         return out
     fanout = stage in ("src_leaf", "src_transfer", "tgt_leaf_adj", "tgt_transfer_adj")
     out = []
@@ -106,6 +108,7 @@ def _candidates(stage, nrhs, dtype):
     (kernels.FOURIER, 2, 64, 1e-6, 8, 1, "c64"),
     (kernels.HELMHOLTZ, 3, 32, 1e-4, 8, 6, "c64otf"),
     (kernels.RADON, 2, 32, 1e-3, 8, 20, "cbf16"),
+    (kernels.HELMHOLTZ, 3, 32, 1e-4, 8, 5, "cq16"),
 ])
 def test_every_launch_candidate_matches_oracle(kind, d, n, tol, leaf, nrhs, dtype, tmp_path):
     # each slot in turn runs each of its candidates (the rest keep the
@@ -117,8 +120,9 @@ def test_every_launch_candidate_matches_oracle(kind, d, n, tol, leaf, nrhs, dtyp
     op = bf.construct(Operator(kind, d, n, omega=om), tol, leaf=leaf)
     path = str(tmp_path / "p.tbplan")
     planio.save_plan(op, path)
-    store = {"c128": ("c128",), "c64": ("c64",), "c64otf": ("otf",), "cbf16": ("cbf16",)}[dtype]
-    bound = {"c128": 1e-12, "cbf16": 5e-3}.get(dtype, 2e-5)
+    store = {"c128": ("c128",), "c64": ("c64",), "c64otf": ("otf",), "cbf16": ("cbf16",),
+             "cq16": ("cq16",)}[dtype]
+    bound = {"c128": 1e-12, "cbf16": 5e-3, "cq16": 1e-4}.get(dtype, 2e-5)
     cdt = torch.complex128 if dtype == "c128" else torch.complex64
     f = inputs.rhs_batch(n, d, nrhs, config=81)
     x = to_dev(f, cdt)
