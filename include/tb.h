@@ -74,7 +74,8 @@ typedef enum {
  * FP32; available for every plan, stored cores or not.
  * TB_CQ16: complex64 arrays, FP32 factors and accumulation, cores stored
  * compressed as block-scaled 16-bit fixed point (a fixed-rate core codec in
- * the spirit of the paper's ZFP-compressed cores, section 5): one FP32 scale
+ * the spirit of the paper's ZFP-compressed cores, section 3.2 and Algorithm 2
+ * step 2): one FP32 scale
  * per core column (its largest real or imaginary magnitude / 32767) and two
  * int16 per entry, 4 bytes per complex entry; decoded inside the core
  * contraction.  Per entry the error is at most half a step, 2^-16 of the
