@@ -61,7 +61,9 @@ typedef enum {
 typedef enum {
   TB_KERNEL_FOURIER = 0,
   TB_KERNEL_HELMHOLTZ = 1,
-  TB_KERNEL_RADON = 2
+  TB_KERNEL_RADON = 2,
+  TB_KERNEL_NUDFT = 3   /* type-2 non-uniform DFT, section 4.3: K = exp(2 pi i x.y),
+                           y = j/n, x_k = X[k][i_k] from tb_options.nudft_x */
 } tb_kernel;
 
 /* Element type of the apply.  TB_C128: complex128 arrays, FP64 factors,
@@ -112,6 +114,11 @@ typedef struct {
                            (d = 2) or the section 4.2 a=3, b=1, den=100
                            (d = 3)                                         */
   double radon_a, radon_b, radon_den;
+  const double* nudft_x; /* TB_KERNEL_NUDFT (required): host array of d * n
+                            target coordinates, mode k at [k n, (k + 1) n),
+                            each in [0, n - 1] and non-decreasing within a
+                            mode (index blocks are then coordinate
+                            intervals); copied into the plan              */
 } tb_options;
 
 /* Summary of a plan (tb_plan_info). */
@@ -286,6 +293,7 @@ const char* tb_status_string(tb_status s);
  *   char[8]    "TBPLAN01"
  *   int32[8]   kind, d, n, leaf, L, Lt, Ls, has_cores
  *   float64[5] omega, tol, radon_a, radon_b, radon_den
+ *   float64[d][n] target coordinates, TB_KERNEL_NUDFT plans only
  *   source IDs, for l = 0..Lt, s (level Ls, flat), tau (level l, flat),
  *     k = 0..d-1, nu = 0..2^(Lt-l)-1:   int32 r, int32 c, int32 skel[r],
  *     complex128 X[r][c]

@@ -30,6 +30,11 @@ radon      K = exp(2 pi i phi(x, k)), x = i/n, k = j - n/2 (section 4.2).
            d = 3: phi = x.k + c(x)|k|,
            c = (a + b sin(2 pi x1) sin(2 pi x2) sin(2 pi x3))/den with the
            paper's a=3, b=1, den=100 as the default.
+nudft      K = exp(2 pi i x.y), the type-2 non-uniform DFT of section 4.3:
+           y = j/n and x_k = X[k][i_k], with X[k] n given coordinates in
+           [0, n - 1] per mode (random in the paper; passed in here, sorted
+           so that index blocks are coordinate intervals).  The phase x.y is
+           formed in FP64 and reduced modulo 1 before the exponential.
 """
 from __future__ import annotations
 
@@ -40,8 +45,9 @@ import numpy as np
 FOURIER = 0
 HELMHOLTZ = 1
 RADON = 2
+NUDFT = 3
 
-KIND_NAMES = {FOURIER: "fourier", HELMHOLTZ: "helmholtz", RADON: "radon"}
+KIND_NAMES = {FOURIER: "fourier", HELMHOLTZ: "helmholtz", RADON: "radon", NUDFT: "nudft"}
 
 
 @dataclass(frozen=True)
@@ -55,8 +61,12 @@ class Operator:
     radon_a: float | None = None  # Radon constants (ignored otherwise);
     radon_b: float | None = None  # None: (2, 1, 3) for d = 2, (3, 1, 100)
     radon_den: float | None = None  # for d = 3
+    nudft_x: tuple | None = None  # NUDFT target coordinates, d tuples of n
 
     def __post_init__(self):
+        if self.nudft_x is not None:
+            object.__setattr__(self, "nudft_x",
+                               tuple(tuple(float(v) for v in row) for row in self.nudft_x))
         a, b, den = radon_defaults(self.d)
         for name, v in (("radon_a", a), ("radon_b", b), ("radon_den", den)):
             if getattr(self, name) is None:
@@ -73,6 +83,8 @@ class Operator:
         if self.kind == RADON:
             return radon_entries(self.n, ti, sj, self.radon_a, self.radon_b,
                                  self.radon_den)
+        if self.kind == NUDFT:
+            return nudft_entries(self.n, np.asarray(self.nudft_x), ti, sj)
         raise ValueError(f"unknown kernel kind {self.kind}")
 
 
@@ -135,3 +147,14 @@ def radon_entries(n: int, ti: np.ndarray, sj: np.ndarray, a: float, b: float,
     phase = np.sum(x * k, axis=-1) + np.sqrt(cc1 ** 2 * k[..., 0] ** 2 +
                                              cc2 ** 2 * k[..., 1] ** 2)
     return np.exp(2j * np.pi * phase)
+
+
+def nudft_entries(n: int, xs: np.ndarray, ti: np.ndarray, sj: np.ndarray) -> np.ndarray:
+    # x.y = sum_k X[k][i_k] j_k / n, reduced modulo 1 in FP64
+    d = ti.shape[-1]
+    if xs.shape != (d, n):
+        raise ValueError(f"NUDFT coordinates must have shape ({d}, {n})")
+    phase = np.zeros(np.broadcast_shapes(ti.shape[:-1], sj.shape[:-1]))
+    for k in range(d):
+        phase = phase + xs[k][ti[..., k]] * sj[..., k].astype(np.float64) / n
+    return np.exp(2j * np.pi * np.mod(phase, 1.0))

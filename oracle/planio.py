@@ -9,6 +9,7 @@ Format, version 1 (little endian, no padding between fields)
   char[8]   magic "TBPLAN01"
   int32[8]  kind, d, n, leaf, L, Lt, Ls, has_cores
   float64[5] omega, tol, radon_a, radon_b, radon_den
+  float64[d][n] target coordinates X[k][i] (kind 3, the NUDFT, only)
   source IDs: for l = 0..Lt, s_flat, tau_flat (at level l), k = 0..d-1,
               nu = 0..2^(Lt-l)-1:
       int32 r, int32 c, int32 skel[r], complex128 X[r][c]
@@ -49,6 +50,8 @@ def plan_bytes(plan: Plan, with_cores: bool = True) -> bytes:
                          plan.Ls, 1 if with_cores else 0),
              struct.pack("<5d", op.omega, plan.tol, op.radon_a, op.radon_b,
                          op.radon_den)]
+    if op.nudft_x is not None:
+        parts.append(np.asarray(op.nudft_x, dtype="<f8").tobytes())
     for l in range(plan.Lt + 1):
         for s_flat in range(1 << (d * plan.Ls)):
             for tau_flat in range(1 << (d * l)):

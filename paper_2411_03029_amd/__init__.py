@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import TBError
 
 KINDS = {"fourier": _lib.TB_KERNEL_FOURIER, "helmholtz": _lib.TB_KERNEL_HELMHOLTZ,
-         "radon": _lib.TB_KERNEL_RADON}
+         "radon": _lib.TB_KERNEL_RADON, "nudft": _lib.TB_KERNEL_NUDFT}
 DTYPES = {"c128": _lib.TB_C128, "c64": _lib.TB_C64, "cbf16": _lib.TB_CBF16,
           "c64otf": _lib.TB_C64_OTF, "cq16": _lib.TB_CQ16}
 STORE = {"c128": _lib.TB_STORE_C128, "c64": _lib.TB_STORE_C64,
@@ -221,15 +221,23 @@ def construct(kind, d: int, n: int, tol: float, omega: float | None = None,
               stream=None, **opts) -> Plan:
     """Build the butterfly of operator ``kind`` on the GPU (Algorithm 1).
 
-    ``kind``: "fourier", "helmholtz" or "radon".  ``omega`` defaults to
-    4 points per wavelength for Helmholtz.  Options: leaf, lt, proxy_pair,
-    proxy_other, id_tol_scale, store (tuple of "c128"/"c64"/"cbf16"),
-    max_rank, max_device_bytes, radon=(a, b, den).
+    ``kind``: "fourier", "helmholtz", "radon" or "nudft".  ``omega`` defaults
+    to 4 points per wavelength for Helmholtz.  Options: leaf, lt, proxy_pair,
+    proxy_other, id_tol_scale, store (tuple of "c128"/"c64"/"cbf16"/"cq16"/
+    "otf"), max_rank, max_device_bytes, radon=(a, b, den), nudft_x (the
+    NUDFT's (d, n) target coordinates).
     """
     k = KINDS[kind] if isinstance(kind, str) else int(kind)
     if omega is None:
         omega = helmholtz_omega(n) if k == _lib.TB_KERNEL_HELMHOLTZ else 0.0
+    xs = opts.pop("nudft_x", None)
     o = _options(**opts)
+    if xs is not None:
+        import numpy as np
+        xs = np.ascontiguousarray(xs, dtype=np.float64)
+        if xs.shape != (d, n):
+            raise ValueError(f"nudft_x must have shape ({d}, {n})")
+        o.nudft_x = xs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     h = ctypes.c_void_p()
     _lib.check(_lib.load().tb_construct(k, d, n, float(omega), float(tol), ctypes.byref(o),
                                         _stream_handle(stream), ctypes.byref(h)))

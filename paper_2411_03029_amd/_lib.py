@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libtb.so")
 
 TB_OK, TB_ERR_INVALID_ARG, TB_ERR_UNSUPPORTED, TB_ERR_OOM, TB_ERR_HIP, \
     TB_ERR_NUMERIC, TB_ERR_IO = range(7)
-TB_KERNEL_FOURIER, TB_KERNEL_HELMHOLTZ, TB_KERNEL_RADON = range(3)
+TB_KERNEL_FOURIER, TB_KERNEL_HELMHOLTZ, TB_KERNEL_RADON, TB_KERNEL_NUDFT = range(4)
 TB_C128, TB_C64, TB_CBF16, TB_C64_OTF, TB_CQ16 = range(5)
 TB_STORE_C128, TB_STORE_C64, TB_STORE_CBF16, TB_STORE_OTF, TB_STORE_CQ16 = 1, 2, 4, 8, 16
 
@@ -35,7 +35,8 @@ class TbOptions(ctypes.Structure):
                 ("id_tol_scale", ctypes.c_double), ("store_mask", ctypes.c_uint),
                 ("max_rank", ctypes.c_int), ("max_device_bytes", ctypes.c_size_t),
                 ("radon_custom", ctypes.c_int), ("radon_a", ctypes.c_double),
-                ("radon_b", ctypes.c_double), ("radon_den", ctypes.c_double)]
+                ("radon_b", ctypes.c_double), ("radon_den", ctypes.c_double),
+                ("nudft_x", ctypes.POINTER(ctypes.c_double))]
 
 
 class TbLaunchCfg(ctypes.Structure):

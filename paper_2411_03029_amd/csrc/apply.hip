@@ -3451,6 +3451,7 @@ static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const vo
     maxRS = std::max(maxRS, p.pair_meta[(size_t)pr * kPairMeta + 1]);
   }
   if (cfg.core == 3) return fail(TB_ERR_UNSUPPORTED, "no matrix-core path for on-the-fly cores");
+  if (p.kind == TB_KERNEL_NUDFT) return fail(TB_ERR_UNSUPPORTED, "no on-the-fly cores for the non-uniform DFT");
   const int QT = (cfg.core == 2 || (cfg.core == 0 && nrhs >= 4)) ? 4 : 1;
   int limit = 0;
   TB_TRY(lds_limit(&limit));

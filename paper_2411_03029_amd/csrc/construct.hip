@@ -34,11 +34,20 @@ struct KernelSpec {
   int kind, d;
   long long n;
   double omega, ra, rb, rden;
+  const double* nux;  // non-uniform DFT: d * n target coordinates
 };
 
 // K(x^i, y^j) for multi-indices ti, sj, in FP64.
 __device__ double2 entry(const KernelSpec& ks, const int* ti, const int* sj) {
   double s, c;
+  if (ks.kind == TB_KERNEL_NUDFT) {
+    // exp(2 pi i x.y), x_k = X[k][i_k], y = j/n: phase in FP64, and sincospi
+    // reduces 2 phase modulo 2 exactly
+    double ph = 0.0;
+    for (int k = 0; k < ks.d; ++k) ph += ks.nux[(long long)k * ks.n + ti[k]] * (double)sj[k];
+    sincospi(2.0 * (ph / (double)ks.n), &s, &c);
+    return make_double2(c, s);
+  }
   if (ks.kind == TB_KERNEL_FOURIER) {
     // exp(-2 pi i (i.k)/n), k = j - n/2, phase reduced exactly mod n
     long long p = 0;
@@ -474,6 +483,7 @@ static KernelSpec spec_of(const Plan& p) {
   ks.ra = p.ra;
   ks.rb = p.rb;
   ks.rden = p.rden;
+  ks.nux = p.nux_d;
   return ks;
 }
 
@@ -747,8 +757,10 @@ extern "C" tb_status tb_construct(tb_kernel kind, int d, long long n, double ome
   tb_options o;
   std::memset(&o, 0, sizeof(o));
   if (opt) o = *opt;
-  if (kind < TB_KERNEL_FOURIER || kind > TB_KERNEL_RADON)
+  if (kind < TB_KERNEL_FOURIER || kind > TB_KERNEL_NUDFT)
     return fail(TB_ERR_INVALID_ARG, "unknown kernel kind");
+  if (kind == TB_KERNEL_NUDFT && !o.nudft_x)
+    return fail(TB_ERR_INVALID_ARG, "the non-uniform DFT needs tb_options.nudft_x");
   if (d < 1 || d > 8) return fail(TB_ERR_INVALID_ARG, "d must be in [1, 8]");
   if (d < 2 || d > 3)
     return fail(TB_ERR_UNSUPPORTED, "kernel/dimension pair not built (every kernel has d = 2 and 3)");
@@ -794,6 +806,7 @@ extern "C" tb_status tb_construct(tb_kernel kind, int d, long long n, double ome
     (void)hipGetLastError();
     return fail(TB_ERR_HIP, "no HIP device visible");
   }
+  if (kind == TB_KERNEL_NUDFT) TB_TRY(set_nudft_points(p, o.nudft_x));
   p.src.resize(p.Lt + 1);
   for (int l = 0; l <= p.Lt; ++l) {
     Level& lv = p.src[l];

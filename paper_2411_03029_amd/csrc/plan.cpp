@@ -134,6 +134,23 @@ static tb_status pad_level(Plan& p, Level& lv, const Level* prev) {
   return TB_OK;
 }
 
+tb_status set_nudft_points(Plan& p, const double* x) {
+  if (!x) return fail(TB_ERR_INVALID_ARG, "the non-uniform DFT needs tb_options.nudft_x");
+  const size_t N = (size_t)p.d * (size_t)p.n;
+  for (int k = 0; k < p.d; ++k)
+    for (long long i = 0; i < p.n; ++i) {
+      const double v = x[(size_t)k * p.n + i];
+      if (!(v >= 0.0 && v <= (double)(p.n - 1)))
+        return fail(TB_ERR_INVALID_ARG, "NUDFT coordinates must lie in [0, n - 1]");
+      if (i > 0 && v < x[(size_t)k * p.n + i - 1])
+        return fail(TB_ERR_INVALID_ARG, "NUDFT coordinates must be non-decreasing within a mode");
+    }
+  p.nux.assign(x, x + N);
+  TB_TRY(dev_alloc(p, reinterpret_cast<void**>(&p.nux_d), N * sizeof(double)));
+  TB_HIP_TRY(hipMemcpy(p.nux_d, p.nux.data(), N * sizeof(double), hipMemcpyHostToDevice));
+  return TB_OK;
+}
+
 tb_status build_core_tables(Plan& p) {
   const int d = p.d;
   p.nT = 1LL << (d * p.Lt);
@@ -445,8 +462,14 @@ extern "C" tb_status tb_plan_load(const char* path, const tb_options* opt,
   p.rden = dh[4];
   if (p.d < 2 || p.d > kMaxD || p.L < 0 || p.L > 12 || p.leaf < 1 || p.Lt < 0 ||
       p.Ls < 0 || p.Lt + p.Ls != p.L || ((long long)p.leaf << p.L) != p.n ||
-      p.kind < 0 || p.kind > 2)
+      p.kind < 0 || p.kind > TB_KERNEL_NUDFT)
     return fail(TB_ERR_IO, "plan header is inconsistent");
+  if (p.kind == TB_KERNEL_NUDFT) {
+    std::vector<double> x((size_t)p.d * p.n);
+    for (double& v : x) v = rd.get<double>();
+    if (!rd.ok) return fail(TB_ERR_IO, "truncated NUDFT coordinates");
+    TB_TRY(set_nudft_points(p, x.data()));
+  }
   if (opt) {
     p.store_mask = opt->store_mask ? opt->store_mask : TB_STORE_C64;
     p.max_device_bytes = opt->max_device_bytes;
@@ -513,6 +536,7 @@ extern "C" tb_status tb_plan_save(tb_plan ph, const char* path) {
   put_bytes(out, hdr, sizeof(hdr));
   double dh[5] = {p.omega, p.tol, p.ra, p.rb, p.rden};
   put_bytes(out, dh, sizeof(dh));
+  if (p.kind == TB_KERNEL_NUDFT) put_bytes(out, p.nux.data(), sizeof(double) * p.nux.size());
   for (const auto* side : {&p.src, &p.tgt})
     for (const Level& lv : *side)
       for (const IdRec& id : lv.ids) {

@@ -108,6 +108,8 @@ struct Plan {
   long long n = 0;
   double omega = 0, tol = 0, eps_id = 0;
   double ra = 2, rb = 1, rden = 3;
+  std::vector<double> nux;           // TB_KERNEL_NUDFT: d * n target coordinates
+  double* nux_d = nullptr;
   int proxy_pair = 2, proxy_other = 4;
   std::vector<Level> src, tgt;
 
@@ -159,6 +161,7 @@ struct Plan {
 tb_status dev_alloc(Plan& p, void** ptr, size_t bytes);
 tb_status finalize_plan(Plan& p, hipStream_t stream);  // pads + uploads factors
 tb_status build_core_tables(Plan& p);
+tb_status set_nudft_points(Plan& p, const double* x);  // checks, copies, uploads
 long long apply_cmacs(const Plan& p, long long* per_stage = nullptr);
 
 // kernels launched by host code

@@ -40,3 +40,11 @@ def gaussian_bumps(n: int, nbumps: int, seed: int) -> np.ndarray:
 def uneven_rhs_counts(count: int = 12, lo: int = 16, hi: int = 128, seed: int = 4) -> np.ndarray:
     """Right-hand-side counts of the uneven batched mix, uniform in [lo, hi]."""
     return np.random.default_rng(seed).integers(lo, hi + 1, count)
+
+
+def nudft_points(n: int, d: int, seed: int = 11) -> np.ndarray:
+    """Target coordinates of a type-2 non-uniform DFT: per mode, n numbers
+    drawn uniformly in [0, n - 1] and sorted, shape (d, n).  Sorting makes a
+    dyadic block of indices an interval of coordinates."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.uniform(0.0, n - 1.0, size=(d, n)), axis=1)

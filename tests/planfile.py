@@ -30,6 +30,10 @@ class PlanFile:
         self._buf = buf
         self._pos = 80
         d = self.d
+        self.nudft_x = None
+        if self.kind == 3:   # NUDFT: the target coordinates follow the header
+            self.nudft_x = np.frombuffer(buf, "<f8", d * self.n, self._pos).reshape(d, self.n)
+            self._pos += 8 * d * self.n
         self.src = []
         for l in range(self.Lt + 1):
             lev = {}

@@ -56,6 +56,7 @@ def test_status_strings():
     ((_lib.TB_KERNEL_HELMHOLTZ, 4, 64, 1.0, 1e-3), _lib.TB_ERR_UNSUPPORTED), # d
     ((_lib.TB_KERNEL_RADON, 1, 64, 0.0, 1e-3), _lib.TB_ERR_UNSUPPORTED),     # d
     ((7, 2, 64, 0.0, 1e-3), _lib.TB_ERR_INVALID_ARG),                        # kind
+    ((_lib.TB_KERNEL_NUDFT, 2, 64, 0.0, 1e-3), _lib.TB_ERR_INVALID_ARG),     # no coordinates
 ])
 def test_construct_rejects_bad_arguments(args, status):
     lib = _lib.load()

@@ -32,6 +32,8 @@ CASES = {
     "helm3_n8_single": (kernels.HELMHOLTZ, 3, 8, 1e-4, 8),   # L = 0
     "plates2_n64": (kernels.HELMHOLTZ, 2, 64, 1e-6, 8),      # parallel plates
     "radon3_n16": (kernels.RADON, 3, 16, 1e-3, 4),           # 3-D Radon
+    "nudft2_n32": (kernels.NUDFT, 2, 32, 1e-6, 8),           # type-2 non-uniform DFT
+    "nudft3_n16": (kernels.NUDFT, 3, 16, 1e-3, 4),
 }
 
 _PLANS = {}
@@ -41,7 +43,8 @@ def oracle_plan(name):
     if name not in _PLANS:
         kind, d, n, tol, leaf = CASES[name]
         om = kernels.helmholtz_omega(n) if kind == kernels.HELMHOLTZ else 0.0
-        _PLANS[name] = bf.construct(Operator(kind, d, n, omega=om), tol, leaf=leaf)
+        xs = inputs.nudft_points(n, d) if kind == kernels.NUDFT else None
+        _PLANS[name] = bf.construct(Operator(kind, d, n, omega=om, nudft_x=xs), tol, leaf=leaf)
     return _PLANS[name]
 
 
@@ -309,6 +312,12 @@ def test_on_the_fly_cores_match_oracle(name, tmp_path):
     op = oracle_plan(name)
     plan = gpu_plan(name, tmp_path, store=("otf",))
     n, d = op.n, op.d
+    if op.op.kind == kernels.NUDFT:  # no on-the-fly entries for the non-uniform DFT
+        x = to_dev(inputs.rhs_batch(n, d, 1, config=95), torch.complex64)
+        with pytest.raises(tb.TBError) as ei:
+            plan.apply(x, dtype="c64otf")
+        assert ei.value.status == 2   # TB_ERR_UNSUPPORTED
+        return
     for nrhs in (1, 5):
         f = inputs.rhs_batch(n, d, nrhs, config=95)
         say(f"[gpu] on-the-fly cores {name} nrhs={nrhs}")

@@ -20,12 +20,19 @@ from .planfile import PlanFile
 
 pytestmark = pytest.mark.gpu
 
-KIND = {kernels.FOURIER: "fourier", kernels.HELMHOLTZ: "helmholtz", kernels.RADON: "radon"}
+KIND = {kernels.FOURIER: "fourier", kernels.HELMHOLTZ: "helmholtz", kernels.RADON: "radon",
+        kernels.NUDFT: "nudft"}
 
 
 def _op(kind, d, n):
     om = kernels.helmholtz_omega(n) if kind == kernels.HELMHOLTZ else 0.0
-    return Operator(kind, d, n, omega=om)
+    xs = inputs.nudft_points(n, d) if kind == kernels.NUDFT else None
+    return Operator(kind, d, n, omega=om, nudft_x=xs)
+
+
+def _extra(kind, d, n):
+    """Construction options an operator needs beyond (kind, d, n, tol)."""
+    return {"nudft_x": inputs.nudft_points(n, d)} if kind == kernels.NUDFT else {}
 
 
 @pytest.mark.parametrize("kind,d,n,tol,leaf", [
@@ -35,6 +42,8 @@ def _op(kind, d, n):
     (kernels.HELMHOLTZ, 3, 16, 1e-4, 8),
     (kernels.HELMHOLTZ, 2, 64, 1e-6, 8),   # parallel plates
     (kernels.RADON, 3, 16, 1e-3, 4),       # 3-D Radon
+    (kernels.NUDFT, 2, 32, 1e-6, 8),       # type-2 non-uniform DFT
+    (kernels.NUDFT, 3, 16, 1e-3, 4),
 ])
 def test_gpu_factors_match_oracle(kind, d, n, tol, leaf, tmp_path):
     torch = torch_gpu()
@@ -42,7 +51,7 @@ def test_gpu_factors_match_oracle(kind, d, n, tol, leaf, tmp_path):
     op = _op(kind, d, n)
     ora = bf.construct(op, tol, leaf=leaf)
     say(f"[gpu] construct {KIND[kind]} d={d} n={n} tol={tol}")
-    plan = tb.construct(KIND[kind], d, n, tol, leaf=leaf, store=("c128", "c64"))
+    plan = tb.construct(KIND[kind], d, n, tol, leaf=leaf, store=("c128", "c64"), **_extra(kind, d, n))
     info = plan.info()
     assert (info["L"], info["Lt"], info["Ls"]) == (ora.L, ora.Lt, ora.Ls)
     path = str(tmp_path / "gpu.tbplan")
@@ -130,3 +139,21 @@ def test_construct_without_stored_cores():
     torch.cuda.synchronize()
     assert relerr(u, dense.apply_exact(op, f)) <= tol
     assert relerr(v, dense.adjoint_exact(op, f)) <= tol
+
+
+def test_nudft_rejects_bad_points():
+    # coordinates outside [0, n - 1] or decreasing within a mode are refused
+    torch_gpu()
+    import paper_2411_03029_amd as tb
+    n = 32
+    xs = inputs.nudft_points(n, 2)
+    bad = xs.copy()
+    bad[0, 3] = n
+    with pytest.raises(tb.TBError) as ei:
+        tb.construct("nudft", 2, n, 1e-6, nudft_x=bad)
+    assert ei.value.status == 1   # TB_ERR_INVALID_ARG
+    bad = xs.copy()
+    bad[1, 5], bad[1, 6] = bad[1, 6], bad[1, 5] - 0.5
+    with pytest.raises(tb.TBError) as ei:
+        tb.construct("nudft", 2, n, 1e-6, nudft_x=bad)
+    assert ei.value.status == 1

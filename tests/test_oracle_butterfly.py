@@ -96,6 +96,29 @@ def test_helmholtz32_meets_tolerance(helm32):
     assert st["core_entries"] < 0.05 * 32 ** 6
 
 
+@pytest.fixture(scope="module")
+def nudft32():
+    """Type-2 non-uniform DFT (section 4.3), d = 2, n = 32, tol 1e-6."""
+    from paper_2411_03029_amd import inputs
+    return bf.construct(Operator(kernels.NUDFT, 2, 32, nudft_x=inputs.nudft_points(32, 2)), 1e-6)
+
+
+def test_nudft32_meets_tolerance(nudft32):
+    op = nudft32.op
+    f = _rand((2, 32, 32), 6)
+    assert _relerr(bf.apply(nudft32, f), dense.apply_brute(op, f)) <= 1e-6
+    assert _relerr(bf.apply_adjoint(nudft32, f), dense.adjoint_brute(op, f)) <= 1e-6
+
+
+def test_nudft3_meets_tolerance():
+    from paper_2411_03029_amd import inputs
+    op = Operator(kernels.NUDFT, 3, 16, nudft_x=inputs.nudft_points(16, 3))
+    plan = bf.construct(op, 1e-3, leaf=4)
+    f = _rand((1, 16, 16, 16), 7)
+    assert _relerr(bf.apply(plan, f), dense.apply_brute(op, f)) <= 1e-3
+    assert _relerr(bf.apply_adjoint(plan, f), dense.adjoint_brute(op, f)) <= 1e-3
+
+
 def test_radon32_meets_tolerance(radon32):
     op = radon32.op
     f = _rand((1, 32, 32), 3)
@@ -117,7 +140,8 @@ def test_radon3_meets_tolerance(radon3_16):
     assert _relerr(bf.apply_adjoint(radon3_16, f), dense.adjoint_brute(op, f)) <= 1e-3
 
 
-@pytest.mark.parametrize("which", ["fourier64", "helm32", "radon32", "plates64", "radon3_16"])
+@pytest.mark.parametrize("which", ["fourier64", "helm32", "radon32", "plates64", "radon3_16",
+                                   "nudft32"])
 def test_adjoint_identity_and_linearity(which, request):
     plan = request.getfixturevalue(which)
     shape = (1,) + (plan.n,) * plan.d
@@ -240,3 +264,15 @@ def test_plan_file_round_trip(helm32, tmp_path):
     raw[100] ^= 0x40
     with pytest.raises(ValueError):
         PlanFile(bytes(raw))
+
+
+def test_nudft_plan_file_carries_the_points(nudft32, tmp_path):
+    # the target coordinates follow the header; every ID and core after them
+    # reads back unchanged
+    path = tmp_path / "n.tbplan"
+    planio.save_plan(nudft32, str(path))
+    pf = PlanFile(str(path))
+    assert (pf.kind, pf.d, pf.n) == (kernels.NUDFT, 2, 32)
+    np.testing.assert_array_equal(pf.nudft_x, np.asarray(nudft32.op.nudft_x))
+    for key, C in nudft32.cores.items():
+        np.testing.assert_array_equal(C, pf.cores[key])

@@ -203,3 +203,62 @@ def test_dense_adjoint_identity_new_operators(kind, d, n):
     lhs = np.vdot(g, dense.apply_brute(op, f))
     rhs = np.vdot(dense.adjoint_brute(op, g), f)
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# ---------------------------------------------------- non-uniform DFT --
+# section 4.3, type 2: K = exp(2 pi i x.y), y = j/n, x_k = X[k][i_k] given
+
+def _nudft(d, n, xs=None, seed=11):
+    from paper_2411_03029_amd import inputs
+    if xs is None:
+        xs = inputs.nudft_points(n, d, seed)
+    return Operator(kernels.NUDFT, d, n, nudft_x=xs)
+
+
+@pytest.mark.parametrize("d,n", [(2, 8), (3, 4)])
+def test_nudft_on_integer_points_is_an_inverse_dft(d, n):
+    # x_k = i_k exactly: K = exp(2 pi i i.j / n), whose sum is n^d ifftn
+    op = _nudft(d, n, xs=np.tile(np.arange(n, dtype=float), (d, 1)))
+    f = _rand((1,) + (n,) * d, 16)
+    axes = tuple(range(1, d + 1))
+    np.testing.assert_allclose(dense.apply_brute(op, f),
+                               np.fft.ifftn(f, axes=axes) * n ** d, atol=1e-10)
+
+
+def test_nudft_shift_of_points_is_a_source_modulation():
+    # x -> x + m multiplies K(x, y) by exp(2 pi i m.y): a diagonal on the
+    # source side, so K' f = K (e f) with e_j = exp(2 pi i m.j / n)
+    d, n = 2, 8
+    xs = _nudft(d, n).nudft_x
+    m = np.array([3.0, 5.0])
+    shifted = _nudft(d, n, xs=np.asarray(xs) + m[:, None])
+    f = _rand((1, n, n), 17)
+    j = np.stack(np.meshgrid(np.arange(n), np.arange(n), indexing="ij"), axis=-1)
+    e = np.exp(2j * np.pi * (j @ m) / n)
+    np.testing.assert_allclose(dense.apply_brute(shifted, f),
+                               dense.apply_brute(_nudft(d, n), f * e[None]), atol=1e-10)
+
+
+def test_nudft_special_values():
+    # j = 0 gives 1 for every target; a target at the origin gives 1 for every source
+    d, n = 3, 4
+    xs = np.asarray(_nudft(d, n).nudft_x).copy()
+    xs[:, 0] = 0.0
+    op = _nudft(d, n, xs=xs)
+    ti = np.array([[1, 2, 3], [3, 0, 1]])
+    np.testing.assert_allclose(op.entries(ti, np.zeros((2, 3), np.int64)), 1.0, atol=1e-15)
+    sj = np.array([[1, 2, 3], [3, 3, 2]])
+    np.testing.assert_allclose(op.entries(np.zeros((2, 3), np.int64), sj), 1.0, atol=1e-15)
+    # unit modulus everywhere
+    kk = op.entries(np.array([[1, 1, 1]]), np.array([[2, 3, 1]]))
+    assert abs(abs(kk[0]) - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("d,n", [(2, 8), (3, 4)])
+def test_nudft_dense_adjoint_identity(d, n):
+    op = _nudft(d, n)
+    f = _rand((1,) + (n,) * d, 18)
+    g = _rand((1,) + (n,) * d, 19)
+    lhs = np.vdot(g, dense.apply_brute(op, f))
+    rhs = np.vdot(dense.adjoint_brute(op, g), f)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
