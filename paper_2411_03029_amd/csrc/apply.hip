@@ -1534,13 +1534,16 @@ __global__ void __launch_bounds__(kThreads)
 //   Radon      d = 2: rev = x . k + sqrt(c1(x)^2 k1^2 + c2(x)^2 k2^2), with
 //              c1(x)^2, c2(x)^2 precomputed per target point; d = 3: rev =
 //              x . k + c(x) |k| with c per target and |k| per source point;
+//              amp = 1, in FP64;
+//   NUDFT      rev = x . y with the target's coordinates x and y = j/n,
 //              amp = 1, in FP64.
 // The fraction of a turn goes to FP32 sine and cosine; the product with F
 // runs in FP32.  A point is four ints (Fourier, Helmholtz: the per-mode
 // grid indices, the source's first index shifted by 2n for the cube
 // offset) or four doubles (Radon: x1, x2, c1^2, c2^2 on the target side,
-// k1, k2 on the source side).
+// k1, k2 on the source side; NUDFT: the coordinates).
 struct OtfSpec {
+  const double* nux;  // non-uniform DFT: d * n target coordinates
   long long n;
   double omega_rev;  // omega / (2 pi)
   double ra, rb, rden;
@@ -1555,10 +1558,16 @@ template <>
 struct OtfPoint<TB_KERNEL_RADON> {
   using V = double4;
 };
+template <>
+struct OtfPoint<TB_KERNEL_NUDFT> {
+  using V = double4;
+};
 
 template <int KIND, int D>
 __device__ __forceinline__ typename OtfPoint<KIND>::V otf_target(const OtfSpec& o, const int* ti) {
-  if constexpr (KIND == TB_KERNEL_RADON && D == 3) {
+  if constexpr (KIND == TB_KERNEL_NUDFT) {  // the target's coordinates
+    return make_double4(o.nux[ti[0]], o.nux[o.n + ti[1]], D == 3 ? o.nux[2 * o.n + ti[D - 1]] : 0.0, 0.0);
+  } else if constexpr (KIND == TB_KERNEL_RADON && D == 3) {
     const double inv = 1.0 / (double)o.n;
     double x[3], sp = 1.0;
 #pragma unroll
@@ -1585,7 +1594,10 @@ __device__ __forceinline__ typename OtfPoint<KIND>::V otf_target(const OtfSpec& 
 template <int KIND, int D>
 __device__ __forceinline__ typename OtfPoint<KIND>::V otf_source(const OtfSpec& o, const int* sj) {
   const int h = (int)(o.n / 2);
-  if constexpr (KIND == TB_KERNEL_RADON && D == 3) {
+  if constexpr (KIND == TB_KERNEL_NUDFT) {  // y = j/n, exact (n is a power of two)
+    const double inv = 1.0 / (double)o.n;
+    return make_double4(sj[0] * inv, sj[1] * inv, D == 3 ? sj[D - 1] * inv : 0.0, 0.0);
+  } else if constexpr (KIND == TB_KERNEL_RADON && D == 3) {
     const double k0 = sj[0] - h, k1 = sj[1] - h, k2 = sj[2] - h;
     return make_double4(k0, k1, k2, sqrt(k0 * k0 + k1 * k1 + k2 * k2));
   } else if constexpr (KIND == TB_KERNEL_RADON) {
@@ -1625,6 +1637,9 @@ __device__ __forceinline__ float2 otf_entry(const OtfSpec& o, const typename Otf
     const double rev = o.omega_rev * (r2 * ir);
     f = (float)(rev - floor(rev));
     amp = (float)ir;
+  } else if constexpr (KIND == TB_KERNEL_NUDFT) {  // x.y
+    const double rev = fma(x.x, y.x, fma(x.y, y.y, x.z * y.z));
+    f = (float)(rev - floor(rev));
   } else if constexpr (D == 3) {  // Radon 3-D: x.k + c |k|
     const double rev = fma(x.x, y.x, fma(x.y, y.y, fma(x.z, y.z, x.w * y.w)));
     f = (float)(rev - floor(rev));
@@ -3433,6 +3448,7 @@ static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const vo
   a.Es = st.E;
   a.Et = tt.E;
   OtfSpec o{};
+  o.nux = p.nux_d;
   o.n = p.n;
   o.omega_rev = p.omega / (2.0 * 3.14159265358979323846);
   o.ra = p.ra;
@@ -3451,14 +3467,14 @@ static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const vo
     maxRS = std::max(maxRS, p.pair_meta[(size_t)pr * kPairMeta + 1]);
   }
   if (cfg.core == 3) return fail(TB_ERR_UNSUPPORTED, "no matrix-core path for on-the-fly cores");
-  if (p.kind == TB_KERNEL_NUDFT) return fail(TB_ERR_UNSUPPORTED, "no on-the-fly cores for the non-uniform DFT");
   const int QT = (cfg.core == 2 || (cfg.core == 0 && nrhs >= 4)) ? 4 : 1;
   int limit = 0;
   TB_TRY(lds_limit(&limit));
   if (p.kind == TB_KERNEL_FOURIER && p.n > (1 << 15))
     return fail(TB_ERR_UNSUPPORTED, "on-the-fly Fourier cores need n <= 32768");
   const int along = adjoint ? maxRT : maxRS;
-  const size_t point = p.kind == TB_KERNEL_RADON ? sizeof(double4) : sizeof(int4);
+  const size_t point =
+      (p.kind == TB_KERNEL_RADON || p.kind == TB_KERNEL_NUDFT) ? sizeof(double4) : sizeof(int4);
   const size_t lds = (size_t)along * point + ((size_t)along + kThreads) * QT * sizeof(float2);
   if (lds > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "on-the-fly core block exceeds the LDS limit");
   const std::vector<int2>& units = adjoint ? p.adj_units : p.fwd_units[0];
@@ -3483,6 +3499,7 @@ static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const vo
   switch (p.kind) {
     case TB_KERNEL_FOURIER: return by_kind(std::integral_constant<int, TB_KERNEL_FOURIER>{});
     case TB_KERNEL_HELMHOLTZ: return by_kind(std::integral_constant<int, TB_KERNEL_HELMHOLTZ>{});
+    case TB_KERNEL_NUDFT: return by_kind(std::integral_constant<int, TB_KERNEL_NUDFT>{});
     default:
       return by_kind(std::integral_constant<int, TB_KERNEL_RADON>{});
   }

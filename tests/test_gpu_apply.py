@@ -312,12 +312,6 @@ def test_on_the_fly_cores_match_oracle(name, tmp_path):
     op = oracle_plan(name)
     plan = gpu_plan(name, tmp_path, store=("otf",))
     n, d = op.n, op.d
-    if op.op.kind == kernels.NUDFT:  # no on-the-fly entries for the non-uniform DFT
-        x = to_dev(inputs.rhs_batch(n, d, 1, config=95), torch.complex64)
-        with pytest.raises(tb.TBError) as ei:
-            plan.apply(x, dtype="c64otf")
-        assert ei.value.status == 2   # TB_ERR_UNSUPPORTED
-        return
     for nrhs in (1, 5):
         f = inputs.rhs_batch(n, d, nrhs, config=95)
         say(f"[gpu] on-the-fly cores {name} nrhs={nrhs}")
