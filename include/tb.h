@@ -225,7 +225,9 @@ typedef struct {
                              cores; 4 = BF16 matrix cores (BF16 applies; right-hand sides split
                              into bf16 hi + lo); 5, 6, 7 = BF16 matrix cores, second form, with
                              256 x 32, 128 x 64, 128 x 32 (rows x right-hand sides) per
-                             workgroup */
+                             workgroup; 8, 9 = adjoint vector
+                             kernel with 16-lane column groups, 1 or 4 RHS per pass
+                             (adjoint launches only) */
   int fanin_in_turn;      /* fan-in stages: 1 = children in turn, first mode in registers;
                              2 = children in turn, first mode first, the coarse slice summed
                              in LDS (8 outputs per thread) */

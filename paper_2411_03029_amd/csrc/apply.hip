@@ -1522,6 +1522,122 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// The adjoint with 16-lane column groups: each wave is four groups of 16
+// lanes, a group owns kAdjCols columns and its lanes sweep the rows (VR per
+// lane per load), so a column's partial sums are reduced over 16 lanes (four
+// steps) instead of 64.  A workgroup owns a 256-column panel (two passes of
+// 4 waves x 4 groups x kAdjCols columns) and stages G once for it.
+template <class T, class CS, int D, int QT>
+__global__ void __launch_bounds__(kThreads)
+    core_adj16(CoreArgs a, const CS* __restrict__ cores, const long long* __restrict__ core_off,
+               const int* __restrict__ meta, const int2* __restrict__ units,
+               const typename CplxOf<T>::type* __restrict__ G, typename CplxOf<T>::type* __restrict__ F) {
+  using C = typename CplxOf<T>::type;
+  using CV = CoreVec<CS>;
+  constexpr int VR = CV::VR;
+  constexpr int kPass = 4 * 4 * kAdjCols;  // columns per pass of the workgroup
+  extern __shared__ unsigned char smem_raw[];
+  C* y = reinterpret_cast<C*>(smem_raw);
+  const int2 u = units[blockIdx.x];
+  const int pair = u.x, c0 = u.y;
+  const int* m = meta + pair * kPairMeta;
+  const int RT = m[0], RS = m[1], RTp = m[2];
+  int rt[D], rs[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    rt[k] = m[3 + k];
+    rs[k] = m[6 + k];
+  }
+  const long long t = pair / a.nS, s = pair % a.nS;
+  const long long sitem = s * a.nT + t, titem = t * a.nS + s;
+  const int q0 = blockIdx.y * QT;
+  const int Qa = min(QT, a.nrhs - q0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int grp = lane >> 4, gl = lane & 15;
+  const typename CV::V* base = reinterpret_cast<const typename CV::V*>(cores + core_off[pair]);
+  const long long cstride = RTp / VR;
+  for (int idx = threadIdx.x; idx < RTp * QT; idx += kThreads) {
+    const int q = idx % QT, r = idx / QT;
+    y[idx] = (r < RT && q < Qa) ? G[(titem * a.Et + padded_pos<D>(r, rt, a.Rt)) * a.nrhs + q0 + q]
+                                : czero<C>();
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int pass = 0; pass < 256 / kPass; ++pass) {
+    const int cb = c0 + pass * kPass + (w * 4 + grp) * kAdjCols;
+    const int ncol = max(0, min(kAdjCols, RS - cb));
+    C acc[kAdjCols][QT];
+#pragma unroll
+    for (int i = 0; i < kAdjCols; ++i)
+#pragma unroll
+      for (int q = 0; q < QT; ++q) acc[i][q] = czero<C>();
+    // columns past the last one re-read the last valid column (results unused)
+    const typename CV::V* cp[kAdjCols];
+#pragma unroll
+    for (int i = 0; i < kAdjCols; ++i)
+      cp[i] = base + (long long)min(cb + min(i, max(ncol - 1, 0)), RS - 1) * cstride;
+    if (ncol > 0) {
+      for (int rb = gl * VR; rb < RTp; rb += 16 * VR) {
+        typename CV::V vv[kAdjCols];
+#pragma unroll
+        for (int i = 0; i < kAdjCols; ++i) vv[i] = cp[i][rb / VR];
+        C yv[VR][QT];
+#pragma unroll
+        for (int v = 0; v < VR; ++v)
+#pragma unroll
+          for (int q = 0; q < QT; ++q) yv[v][q] = y[(rb + v) * QT + q];
+#pragma unroll
+        for (int i = 0; i < kAdjCols; ++i) {
+          C c[VR];
+          CV::get(vv[i], c);
+#pragma unroll
+          for (int v = 0; v < VR; ++v)
+#pragma unroll
+            for (int q = 0; q < QT; ++q) acc[i][q] = cfma_conj(acc[i][q], c[v], yv[v][q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kAdjCols; ++i)
+#pragma unroll
+      for (int q = 0; q < QT; ++q) {
+        T re = acc[i][q].x, im = acc[i][q].y;
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {  // within the 16-lane group
+          re += __shfl_xor(re, o, 64);
+          im += __shfl_xor(im, o, 64);
+        }
+        acc[i][q].x = re;
+        acc[i][q].y = im;
+      }
+    if (gl < ncol) {
+      // lane gl of the group writes column cb + gl (values equal across the group)
+#pragma unroll
+      for (int i = 0; i < kAdjCols; ++i)
+        if (i == gl) {
+          const long long pos = padded_pos<D>(cb + i, rs, a.Rs);
+          T sc = T(1);
+          if constexpr (std::is_same<CS, Q16>::value) sc = a.colscale[a.col_off[pair] + cb + i];
+#pragma unroll
+          for (int q = 0; q < QT; ++q)
+            if (q < Qa) {
+              C v = acc[i][q];
+              if constexpr (std::is_same<CS, Q16>::value) {
+                v.x *= sc;
+                v.y *= sc;
+              }
+              F[(sitem * a.Es + pos) * a.nrhs + q0 + q] = v;
+            }
+        }
+    }
+  }
+  if (c0 == 0) {
+    for (long long p = threadIdx.x; p < a.Es; p += kThreads)
+      if (is_padding<D>(p, rs, a.Rs))
+        for (int q = 0; q < Qa; ++q) F[(sitem * a.Es + p) * a.nrhs + q0 + q] = czero<C>();
+  }
+}
+
 // -------------------------------------------------- on-the-fly cores --
 // K(tbar, sbar) evaluated inside the core contraction instead of streamed
 // from memory (no stored cores).  Every kernel is exp(2 pi i rev) * amp:
@@ -3283,7 +3399,7 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
 template <class T, class CS, int D, int QT>
 static tb_status launch_core_q(const Plan& p, CoreArgs a, bool adjoint, const void* cores,
                                const void* in, void* out, int maxRS, int maxRTp, int limit,
-                               hipStream_t stream) {
+                               hipStream_t stream, bool grouped = false) {
   using C = typename CplxOf<T>::type;
   constexpr int VR = CoreVec<CS>::VR;
   const unsigned gy = (unsigned)((a.nrhs + QT - 1) / QT);
@@ -3297,10 +3413,15 @@ static tb_status launch_core_q(const Plan& p, CoreArgs a, bool adjoint, const vo
   } else {
     const size_t lds = (size_t)maxRTp * QT * sizeof(C);
     if (lds > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "core block exceeds the LDS budget");
-    // 64-column panels (two column groups per workgroup)
-    TB_TRY(set_lds(core_adj<T, CS, D, QT, 2>, lds));
-    core_adj<T, CS, D, QT, 2><<<dim3((unsigned)p.adj_units.size(), gy), kThreads, lds, stream>>>(
-        a, (const CS*)cores, p.core_off_d, p.pair_meta_d, p.adj_units_d, (const C*)in, (C*)out);
+    if (grouped) {  // 16-lane column groups, 256-column panels
+      TB_TRY(set_lds(core_adj16<T, CS, D, QT>, lds));
+      core_adj16<T, CS, D, QT><<<dim3((unsigned)p.mfma_adj_units.size(), gy), kThreads, lds, stream>>>(
+          a, (const CS*)cores, p.core_off_d, p.pair_meta_d, p.mfma_adj_units_d, (const C*)in, (C*)out);
+    } else {  // 64-column panels (two column groups per workgroup)
+      TB_TRY(set_lds(core_adj<T, CS, D, QT, 2>, lds));
+      core_adj<T, CS, D, QT, 2><<<dim3((unsigned)p.adj_units.size(), gy), kThreads, lds, stream>>>(
+          a, (const CS*)cores, p.core_off_d, p.pair_meta_d, p.adj_units_d, (const C*)in, (C*)out);
+    }
   }
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;
@@ -3397,7 +3518,10 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
     maxRTp = std::max(maxRTp, p.pair_meta[(size_t)pr * kPairMeta + 2]);
   }
   constexpr bool kQ16 = std::is_same<CS, Q16>::value;  // vector kernels only
-  if (kQ16 && cfg.core >= 3) return fail(TB_ERR_UNSUPPORTED, "16-bit cores run on the vector core kernels");
+  if (kQ16 && cfg.core >= 3 && cfg.core <= 7)
+    return fail(TB_ERR_UNSUPPORTED, "16-bit cores run on the vector core kernels");
+  const bool grouped = cfg.core == 8 || cfg.core == 9;  // adjoint with 16-lane column groups
+  if (grouped && !adjoint) return fail(TB_ERR_UNSUPPORTED, "16-lane column groups are an adjoint kernel");
   if constexpr (std::is_same<CS, unsigned>::value) {  // BF16 cores
     if (cfg.core >= 5 && cfg.core <= 7) {
       int maxRT = 0;
@@ -3413,7 +3537,7 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
       return d == 2 ? launch_core_mfma<CS, 2>(p, a, adjoint, cores, in, out, stream, true)
                     : launch_core_mfma<CS, 3>(p, a, adjoint, cores, in, out, stream, true);
   } else {
-    if (cfg.core >= 4) return fail(TB_ERR_UNSUPPORTED, "BF16 matrix cores need BF16 cores");
+    if (cfg.core >= 4 && cfg.core <= 7) return fail(TB_ERR_UNSUPPORTED, "BF16 matrix cores need BF16 cores");
   }
   if constexpr (sizeof(T) == 4 && !kQ16) {
     if (cfg.core == 3 || (cfg.core == 0 && nrhs >= kMfmaMinRhs))
@@ -3427,12 +3551,13 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
   using C = typename CplxOf<T>::type;
   const size_t need4 = adjoint ? (size_t)maxRTp * 4 * sizeof(C)
                                : ((size_t)maxRS * 4 + (size_t)kThreads * CoreVec<CS>::VR * 4) * sizeof(C);
-  if (cfg.core == 2 && need4 > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "core tile exceeds LDS");
-  if (cfg.core == 1 || nrhs == 1 || need4 > (size_t)limit)
-    return d == 2 ? launch_core_q<T, CS, 2, 1>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream)
-                  : launch_core_q<T, CS, 3, 1>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream);
-  return d == 2 ? launch_core_q<T, CS, 2, 4>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream)
-                : launch_core_q<T, CS, 3, 4>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream);
+  const int cq = grouped ? cfg.core - 7 : cfg.core;  // 1 or 4 right-hand sides per pass
+  if (cq == 2 && need4 > (size_t)limit) return fail(TB_ERR_UNSUPPORTED, "core tile exceeds LDS");
+  if (cq == 1 || nrhs == 1 || need4 > (size_t)limit)
+    return d == 2 ? launch_core_q<T, CS, 2, 1>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream, grouped)
+                  : launch_core_q<T, CS, 3, 1>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream, grouped);
+  return d == 2 ? launch_core_q<T, CS, 2, 4>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream, grouped)
+                : launch_core_q<T, CS, 3, 4>(p, a, adjoint, cores, in, out, maxRS, maxRTp, limit, stream, grouped);
 }
 
 // Core contraction with the cores evaluated on the fly (TB_C64_OTF); cfg.core
@@ -3466,7 +3591,7 @@ static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const vo
     maxRT = std::max(maxRT, p.pair_meta[(size_t)pr * kPairMeta]);
     maxRS = std::max(maxRS, p.pair_meta[(size_t)pr * kPairMeta + 1]);
   }
-  if (cfg.core == 3) return fail(TB_ERR_UNSUPPORTED, "no matrix-core path for on-the-fly cores");
+  if (cfg.core >= 3) return fail(TB_ERR_UNSUPPORTED, "on-the-fly cores take core kernel 1 or 2");
   const int QT = (cfg.core == 2 || (cfg.core == 0 && nrhs >= 4)) ? 4 : 1;
   int limit = 0;
   TB_TRY(lds_limit(&limit));
@@ -3712,6 +3837,14 @@ static std::vector<LaunchCfg> core_candidates(long long nrhs, tb_dtype io) {
   if (nrhs >= 2) {
     c.core = 2;
     out.push_back(c);
+  }
+  if (io != TB_C64_OTF) {  // adjoint with 16-lane column groups (forward slots reject it)
+    c.core = 8;
+    out.push_back(c);
+    if (nrhs >= 2) {
+      c.core = 9;
+      out.push_back(c);
+    }
   }
   if (io != TB_C128 && io != TB_C64_OTF && io != TB_CQ16 && nrhs >= 4) {
     c.core = 3;
@@ -4064,7 +4197,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   if (slot < 0 || slot >= nslots) return tb::fail(TB_ERR_INVALID_ARG, "launch slot out of range");
   const int g = cfg->outputs_per_thread, q = cfg->rhs_tile;
   if (!(g == 0 || g == 1 || g == 8) || !(q == 0 || q == 1 || q == 2 || q == 4 || q == 8) ||
-      cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 7 ||
+      cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 9 ||
       cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 2 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1 ||
       !(cfg->rhs_per_thread == 0 || cfg->rhs_per_thread == 1 || cfg->rhs_per_thread == 4))
     return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");

@@ -97,7 +97,8 @@ struct LaunchCfg {
   int QT = 0;     // transfer: right-hand sides per workgroup (1, 2, 4, 8)
   int split = 0;  // transfer: 1 = one workgroup per block (no slicing)
   int core = 0;   // core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = FP32 MFMA;
-                  // 4 = BF16 MFMA (BF16 cores)
+                  // 4 = BF16 MFMA (BF16 cores); 5-7 = BF16 MFMA, second form (three
+                  // tiles); 8, 9 = adjoint vector kernel, 16-lane column groups, 1 / 4 RHS
   int alt = 0;    // fan-in: 1 = children in turn, mode 0 in registers
   int mfma = 0;   // transfer levels: 1 = mode products on the matrix cores
   int V = 0;      // transfer: right-hand sides per thread (1 or 4; 4 needs QT >= 4)

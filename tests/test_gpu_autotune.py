@@ -77,8 +77,10 @@ def _candidates(stage, nrhs, dtype):
             out.append(dict(core_kernel=3))
         if dtype == "cbf16" and nrhs >= 4:
             out += [dict(core_kernel=v) for v in (4, 5, 6, 7)]
+        if dtype != "c64otf":   # adjoint with 16-lane column groups (forward slots reject)
+            out += [dict(core_kernel=8)] + ([dict(core_kernel=9)] if nrhs >= 2 else [])
         if dtype == "cq16":
-            out = [c for c in out if c["core_kernel"] <= 2]
+            out = [c for c in out if not 3 <= c["core_kernel"] <= 7]
         return out
     fanout = stage in ("src_leaf", "src_transfer", "tgt_leaf_adj", "tgt_transfer_adj")
     out = []
