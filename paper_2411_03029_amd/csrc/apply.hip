@@ -1658,6 +1658,8 @@ __global__ void __launch_bounds__(kThreads)
 // grid indices, the source's first index shifted by 2n for the cube
 // offset) or four doubles (Radon: x1, x2, c1^2, c2^2 on the target side,
 // k1, k2 on the source side; NUDFT: the coordinates).
+constexpr int kOtfChunk = 1024;  // points of the contracted index staged at a time
+
 struct OtfSpec {
   const double* nux;  // non-uniform DFT: d * n target coordinates
   long long n;
@@ -1802,20 +1804,11 @@ __global__ void __launch_bounds__(kThreads)
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
   const int q0 = blockIdx.y * QT;
   const int Qa = min(QT, a.nrhs - q0);
-  P* yv = reinterpret_cast<P*>(smem_raw);                 // [RS]
-  float2* x = reinterpret_cast<float2*>(yv + RS);          // [RS][QT]
-  float2* red = x + RS * QT;                               // [256][QT]
-  for (int b = threadIdx.x; b < RS; b += kThreads) {
-    int sj[D];
-    otf_index<D>(sskel, sitem, o.Rs_sk, rs, b, sj);
-    yv[b] = otf_source<KIND, D>(o, sj);
-  }
-  for (int idx = threadIdx.x; idx < RS * QT; idx += kThreads) {
-    const int q = idx % QT, b = idx / QT;
-    x[idx] = q < Qa ? F[(sitem * a.Es + padded_pos<D>(b, rs, a.Rs)) * a.nrhs + q0 + q]
-                    : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
+  // the source points and F of at most kOtfChunk columns at a time
+  const int CH = min(RS, kOtfChunk);
+  P* yv = reinterpret_cast<P*>(smem_raw);                 // [CH]
+  float2* x = reinterpret_cast<float2*>(yv + CH);          // [CH][QT]
+  float2* red = x + CH * QT;                               // [256][QT]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int row = r0 + lane;
   P xv;
@@ -1824,15 +1817,30 @@ __global__ void __launch_bounds__(kThreads)
     otf_index<D>(tskel, titem, o.Rt_sk, rt, min(row, RT - 1), ti);
     xv = otf_target<KIND, D>(o, ti);
   }
-  const int per = (RS + 3) / 4;
-  const int j0 = w * per, j1 = min(RS, j0 + per);
   float2 acc[QT];
 #pragma unroll
   for (int q = 0; q < QT; ++q) acc[q] = make_float2(0.f, 0.f);
-  for (int j = j0; j < j1; ++j) {
-    const float2 c = otf_entry<KIND, D>(o, xv, yv[j]);
+  for (int c0 = 0; c0 < RS; c0 += CH) {
+    const int nc = min(CH, RS - c0);
+    if (c0 > 0) __syncthreads();  // the previous chunk is read
+    for (int b = threadIdx.x; b < nc; b += kThreads) {
+      int sj[D];
+      otf_index<D>(sskel, sitem, o.Rs_sk, rs, c0 + b, sj);
+      yv[b] = otf_source<KIND, D>(o, sj);
+    }
+    for (int idx = threadIdx.x; idx < nc * QT; idx += kThreads) {
+      const int q = idx % QT, b = idx / QT;
+      x[idx] = q < Qa ? F[(sitem * a.Es + padded_pos<D>(c0 + b, rs, a.Rs)) * a.nrhs + q0 + q]
+                      : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const int per = (nc + 3) / 4;
+    const int j0 = w * per, j1 = min(nc, j0 + per);
+    for (int j = j0; j < j1; ++j) {
+      const float2 c = otf_entry<KIND, D>(o, xv, yv[j]);
 #pragma unroll
-    for (int q = 0; q < QT; ++q) acc[q] = cfma(acc[q], c, x[j * QT + q]);
+      for (int q = 0; q < QT; ++q) acc[q] = cfma(acc[q], c, x[j * QT + q]);
+    }
   }
 #pragma unroll
   for (int q = 0; q < QT; ++q) red[(w * 64 + lane) * QT + q] = acc[q];
@@ -1879,20 +1887,11 @@ __global__ void __launch_bounds__(kThreads)
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
   const int q0 = blockIdx.y * QT;
   const int Qa = min(QT, a.nrhs - q0);
-  P* xr = reinterpret_cast<P*>(smem_raw);                 // [RT]
-  float2* g = reinterpret_cast<float2*>(xr + RT);          // [RT][QT]
-  float2* red = g + RT * QT;                               // [256][QT]
-  for (int b = threadIdx.x; b < RT; b += kThreads) {
-    int ti[D];
-    otf_index<D>(tskel, titem, o.Rt_sk, rt, b, ti);
-    xr[b] = otf_target<KIND, D>(o, ti);
-  }
-  for (int idx = threadIdx.x; idx < RT * QT; idx += kThreads) {
-    const int q = idx % QT, b = idx / QT;
-    g[idx] = q < Qa ? G[(titem * a.Et + padded_pos<D>(b, rt, a.Rt)) * a.nrhs + q0 + q]
-                    : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
+  // the target points and G of at most kOtfChunk rows at a time
+  const int CH = min(RT, kOtfChunk);
+  P* xr = reinterpret_cast<P*>(smem_raw);                 // [CH]
+  float2* g = reinterpret_cast<float2*>(xr + CH);          // [CH][QT]
+  float2* red = g + CH * QT;                               // [256][QT]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int col = c0 + lane;
   P yv;
@@ -1901,15 +1900,30 @@ __global__ void __launch_bounds__(kThreads)
     otf_index<D>(sskel, sitem, o.Rs_sk, rs, min(col, RS - 1), sj);
     yv = otf_source<KIND, D>(o, sj);
   }
-  const int per = (RT + 3) / 4;
-  const int i0 = w * per, i1 = min(RT, i0 + per);
   float2 acc[QT];
 #pragma unroll
   for (int q = 0; q < QT; ++q) acc[q] = make_float2(0.f, 0.f);
-  for (int i = i0; i < i1; ++i) {
-    const float2 c = otf_entry<KIND, D>(o, xr[i], yv);
+  for (int r0 = 0; r0 < RT; r0 += CH) {
+    const int nr = min(CH, RT - r0);
+    if (r0 > 0) __syncthreads();  // the previous chunk is read
+    for (int b = threadIdx.x; b < nr; b += kThreads) {
+      int ti[D];
+      otf_index<D>(tskel, titem, o.Rt_sk, rt, r0 + b, ti);
+      xr[b] = otf_target<KIND, D>(o, ti);
+    }
+    for (int idx = threadIdx.x; idx < nr * QT; idx += kThreads) {
+      const int q = idx % QT, b = idx / QT;
+      g[idx] = q < Qa ? G[(titem * a.Et + padded_pos<D>(r0 + b, rt, a.Rt)) * a.nrhs + q0 + q]
+                      : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const int per = (nr + 3) / 4;
+    const int i0 = w * per, i1 = min(nr, i0 + per);
+    for (int i = i0; i < i1; ++i) {
+      const float2 c = otf_entry<KIND, D>(o, xr[i], yv);
 #pragma unroll
-    for (int q = 0; q < QT; ++q) acc[q] = cfma_conj(acc[q], c, g[i * QT + q]);
+      for (int q = 0; q < QT; ++q) acc[q] = cfma_conj(acc[q], c, g[i * QT + q]);
+    }
   }
 #pragma unroll
   for (int q = 0; q < QT; ++q) red[(w * 64 + lane) * QT + q] = acc[q];
@@ -3597,7 +3611,7 @@ static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const vo
   TB_TRY(lds_limit(&limit));
   if (p.kind == TB_KERNEL_FOURIER && p.n > (1 << 15))
     return fail(TB_ERR_UNSUPPORTED, "on-the-fly Fourier cores need n <= 32768");
-  const int along = adjoint ? maxRT : maxRS;
+  const int along = std::min(adjoint ? maxRT : maxRS, kOtfChunk);
   const size_t point =
       (p.kind == TB_KERNEL_RADON || p.kind == TB_KERNEL_NUDFT) ? sizeof(double4) : sizeof(int4);
   const size_t lds = (size_t)along * point + ((size_t)along + kThreads) * QT * sizeof(float2);
