@@ -461,6 +461,72 @@ __global__ void __launch_bounds__(kThreads)
 // a_0 in this workgroup's slice [lo, lo + na) (compact numbering).  All
 // children are processed together: two barriers per workgroup.
 constexpr int kMaxChildren = 1 << kMaxD;
+constexpr int kStageU = 8;  // staging loads in flight per thread (fan-in)
+
+// Stages the fan-in children's matrices of modes [K0, D) in LDS, compact:
+// child c's block starts at mall[c * msz]; mode 0's slice rows [lo, lo + na)
+// are transposed to [ai][j] (na x r_0(c)); mode k >= 1 is r_k(c) x c_k (row
+// stride c_k) at offset chunk * R_0 + sum of R_k' * A_k' over 1 <= k' < k.
+// Per mode, the slices of all the children go in one flat pass with
+// kStageU loads in flight per thread before any LDS store: one memory round
+// trip per kStageU * kThreads entries instead of one per child.
+template <int D, int K0, class C>
+__device__ __forceinline__ void stage_child_mats(C* mall, int msz, const StageArgs& a,
+                                                 const C* __restrict__ mats, const int* cfi,
+                                                 const int (*crk)[kMaxD], int nchild, const Seg* sg,
+                                                 const int* beta, int lo, int na) {
+  int moff = a.chunk * a.R[0];
+#pragma unroll
+  for (int k = K0; k < D; ++k) {
+    const int ck = sg[k].c;
+    const int mo = k == 0 ? 0 : moff;
+    if (k > 0) moff += a.R[k] * a.A[k];
+    int cend[kMaxChildren];
+    int tot = 0;
+#pragma unroll
+    for (int c = 0; c < kMaxChildren; ++c) {
+      tot += c < nchild ? (k == 0 ? na * crk[c][0] : crk[c][k] * ck) : 0;
+      cend[c] = tot;
+    }
+    const long long kbase = a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
+    for (int e0 = threadIdx.x; e0 < tot; e0 += kStageU * kThreads) {
+      C v[kStageU];
+      int dst[kStageU];
+#pragma unroll
+      for (int u = 0; u < kStageU; ++u) {
+        const int e = e0 + u * kThreads;
+        dst[u] = -1;
+        if (e < tot) {
+          int c = 0, start = 0;  // the child whose slice holds entry e
+#pragma unroll
+          for (int cc = 0; cc + 1 < kMaxChildren; ++cc)
+            if (e >= cend[cc]) {
+              c = cc + 1;
+              start = cend[cc];
+            }
+          const int i = e - start;
+          long long off;
+          if (k == 0) {
+            const int r0 = crk[c][0], ai = i / r0, j = i % r0;
+            off = (long long)j * a.A[0] + sg[0].pos(lo + ai);
+          } else {
+            const int row = i / ck, j = i % ck;
+            off = (long long)row * a.A[k] + sg[k].pos(j);
+          }
+          v[u] = mats[(long long)cfi[c] * a.mat_item_stride + kbase + off];
+          dst[u] = c * msz + mo + i;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kStageU; ++u)
+        if (dst[u] >= 0) {
+          C x = v[u];
+          if (a.conj) x.y = -x.y;
+          mall[dst[u]] = x;
+        }
+    }
+  }
+}
 
 template <class T, int D, int QT, bool SM, int kG, int kV>
 __global__ void __launch_bounds__(kThreads)
@@ -508,31 +574,39 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 1; k < D; ++k) msz += a.R[k] * a.A[k];
   C* mall = sm;
-  for (int c = 0; SM && c < nchild; ++c) {
-    const C* mbase = mats + (long long)cfi[c] * a.mat_item_stride;
-    int off = c * msz;
-    if (kG > 1) {
-      const C* src = mbase + a.mat_k_off[0] + (long long)beta[0] * a.R[0] * A0;
-      const int r0 = crk[c][0];
-      for (int i = threadIdx.x; i < na * r0; i += kThreads) {
-        const int ai = i / r0, j = i % r0;
-        C v = src[j * A0 + sg[0].pos(lo + ai)];
-        if (a.conj) v.y = -v.y;
-        mall[off + i] = v;
+  if constexpr (SM && kG == 1 && kV == 1) {
+    // one output per thread: the block is small and latency-bound, so the
+    // flat staging pays; mode 0 stays in global memory (read from LDS it
+    // was slower)
+    stage_child_mats<D, 1>(mall, msz, a, mats, cfi, crk, nchild, sg, beta, lo, na);
+  } else {
+    // register-blocked forms: the flat pass's registers would cost occupancy
+    for (int c = 0; SM && c < nchild; ++c) {
+      const C* mbase = mats + (long long)cfi[c] * a.mat_item_stride;
+      int off = c * msz;
+      if (kG > 1) {
+        const C* src = mbase + a.mat_k_off[0] + (long long)beta[0] * a.R[0] * A0;
+        const int r0 = crk[c][0];
+        for (int i = threadIdx.x; i < na * r0; i += kThreads) {
+          const int ai = i / r0, j = i % r0;
+          C v = src[j * A0 + sg[0].pos(lo + ai)];
+          if (a.conj) v.y = -v.y;
+          mall[off + i] = v;
+        }
       }
-    }
-    off += a.chunk * a.R[0];
+      off += a.chunk * a.R[0];
 #pragma unroll
-    for (int k = 1; k < D; ++k) {
-      const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
-      const int ck = sg[k].c, rk = crk[c][k];
-      for (int i = threadIdx.x; i < rk * ck; i += kThreads) {
-        const int row = i / ck, j = i % ck;
-        C v = src[row * a.A[k] + sg[k].pos(j)];
-        if (a.conj) v.y = -v.y;
-        mall[off + i] = v;
+      for (int k = 1; k < D; ++k) {
+        const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
+        const int ck = sg[k].c, rk = crk[c][k];
+        for (int i = threadIdx.x; i < rk * ck; i += kThreads) {
+          const int row = i / ck, j = i % ck;
+          C v = src[row * a.A[k] + sg[k].pos(j)];
+          if (a.conj) v.y = -v.y;
+          mall[off + i] = v;
+        }
+        off += a.R[k] * a.A[k];
       }
-      off += a.R[k] * a.A[k];
     }
   }
   C* buf1 = sm + (SM ? nchild * msz : 0);
@@ -758,7 +832,6 @@ __global__ void __launch_bounds__(kThreads)
   long long fs[D];
   (void)fine_base<D>(a, 0, beta, 0, fs);   // strides only
   __syncthreads();
-  const int A0 = a.A[0];
   const int R1 = a.R[1];
   const int c1 = sg[1].c;
   // every child's matrices, compact in LDS: M_0[j][lo + ai] transposed to
@@ -767,31 +840,37 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 1; k < D; ++k) msz += a.R[k] * a.A[k];
   C* mall = sm;
-  for (int c = 0; c < nchild; ++c) {
-    const C* mbase = mats + (long long)cfi[c] * a.mat_item_stride;
-    int off = c * msz;
-    {
-      const C* src = mbase + a.mat_k_off[0] + (long long)beta[0] * a.R[0] * A0;
-      const int r0 = crk[c][0];
-      for (int i = threadIdx.x; i < na * r0; i += kThreads) {
-        const int ai = i / r0, j = i % r0;
-        C v = src[j * A0 + sg[0].pos(lo + ai)];
-        if (a.conj) v.y = -v.y;
-        mall[off + i] = v;
+  if constexpr (D == 3) {
+    stage_child_mats<D, 0>(mall, msz, a, mats, cfi, crk, nchild, sg, beta, lo, na);
+  } else {
+    // d = 2: the flat pass's registers would cost occupancy
+    const int A0 = a.A[0];
+    for (int c = 0; c < nchild; ++c) {
+      const C* mbase = mats + (long long)cfi[c] * a.mat_item_stride;
+      int off = c * msz;
+      {
+        const C* src = mbase + a.mat_k_off[0] + (long long)beta[0] * a.R[0] * A0;
+        const int r0 = crk[c][0];
+        for (int i = threadIdx.x; i < na * r0; i += kThreads) {
+          const int ai = i / r0, j = i % r0;
+          C v = src[j * A0 + sg[0].pos(lo + ai)];
+          if (a.conj) v.y = -v.y;
+          mall[off + i] = v;
+        }
       }
-    }
-    off += a.chunk * a.R[0];
+      off += a.chunk * a.R[0];
 #pragma unroll
-    for (int k = 1; k < D; ++k) {
-      const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
-      const int ck = sg[k].c, rk = crk[c][k];
-      for (int i = threadIdx.x; i < rk * ck; i += kThreads) {
-        const int row = i / ck, j = i % ck;
-        C v = src[row * a.A[k] + sg[k].pos(j)];
-        if (a.conj) v.y = -v.y;
-        mall[off + i] = v;
+      for (int k = 1; k < D; ++k) {
+        const C* src = mbase + a.mat_k_off[k] + (long long)beta[k] * a.R[k] * a.A[k];
+        const int ck = sg[k].c, rk = crk[c][k];
+        for (int i = threadIdx.x; i < rk * ck; i += kThreads) {
+          const int row = i / ck, j = i % ck;
+          C v = src[row * a.A[k] + sg[k].pos(j)];
+          if (a.conj) v.y = -v.y;
+          mall[off + i] = v;
+        }
+        off += a.R[k] * a.A[k];
       }
-      off += a.R[k] * a.A[k];
     }
   }
   C* buf1 = sm + nchild * msz;
