@@ -31,12 +31,22 @@
  * Ownership: a plan owns all device memory for factors, cores and
  *            workspace; tb_destroy frees it.
  * Indexing:  target multi-index i and source multi-index j in [0, n)^d.
- *            Fourier: K = exp(-2 pi i x.k), x = i/n, k = j - n/2.
- *            Helmholtz (d = 3): K = exp(+i omega rho)/rho, rho = |x - y|,
- *              x = i/n, y = j/n + (2, 0, 0)  (two unit cubes, centres 2 apart).
- *            Radon (d = 2): K = exp(2 pi i (x.k + sqrt(c1^2 k1^2 + c2^2 k2^2)))
- *              with x = i/n, k = j - n/2, c1 = (a + b sin 2pi x1 sin 2pi x2)/den,
- *              c2 = (a + b cos 2pi x1 cos 2pi x2)/den  (section 4.2).
+ *            Fourier (d = 2, 3): K = exp(-2 pi i x.k), x = i/n, k = j - n/2
+ *              (section 4.3, phase reduced exactly in integers).
+ *            Helmholtz (section 4.1): K = exp(+i omega rho)/rho, rho = |x - y|;
+ *              d = 3: x = i/n, y = j/n + (2, 0, 0) (two unit cubes, centres
+ *              2 apart along x1); d = 2: x = (i/n, 0), y = (j/n, 1) (two
+ *              parallel facing unit plates, 1 apart).
+ *            Radon (section 4.2), x = i/n, k = j - n/2, K = exp(2 pi i phi):
+ *              d = 2: phi = x.k + sqrt(c1^2 k1^2 + c2^2 k2^2),
+ *                c1 = (a + b sin 2pi x1 sin 2pi x2)/den,
+ *                c2 = (a + b cos 2pi x1 cos 2pi x2)/den, (a, b, den) = (2, 1, 3)
+ *                unless tb_options sets them (the paper's are (2, 1, 16));
+ *              d = 3: phi = x.k + c |k|,
+ *                c = (a + b sin 2pi x1 sin 2pi x2 sin 2pi x3)/den,
+ *                (a, b, den) = (3, 1, 100) unless set.
+ *            Non-uniform DFT, type 2 (section 4.3, d = 2, 3): K = exp(2 pi i x.y),
+ *              y = j/n, x_k = X[k][i_k] from tb_options.nudft_x.
  */
 #ifndef TB_H
 #define TB_H

@@ -178,6 +178,51 @@ def _sample(op: Operator, tgt_rows, src_rows, k_src=None, k_tgt=None,
     return op.entries(ti, sj)
 
 
+def source_unfolding(plan: Plan, s, l: int, tau, k: int, cols) -> np.ndarray:
+    """Proxy-sampled mode-k unfolding of a source-side ID (section 3.2,
+    Algorithm 1 step 1): rows are the proxy targets of tau (level l) in every
+    mode, times the proxy sources of the middle multi-set s in every mode
+    but k; columns are the candidate mode-k source indices ``cols``.  The
+    paired mode k of tau gets p_pair samples per column."""
+    op, n, d = plan.op, plan.n, plan.d
+    tlists = []
+    for i in range(d):
+        lo, ln = node_range(l, tau[i], n)
+        p = _pair_count(plan.p_pair, len(cols)) if i == k else plan.p_other
+        tlists.append(proxies(lo, ln, p))
+    slists = []
+    for i in range(d):
+        if i == k:
+            slists.append(np.zeros(1, dtype=np.int64))
+        else:
+            lo, ln = node_range(plan.Ls, s[i], n)
+            slists.append(proxies(lo, ln, plan.p_other))
+    rows = _product_rows(tlists + slists)
+    return _sample(op, rows[:, :d], rows[:, d:], k_src=k, cols=np.asarray(cols))
+
+
+def target_unfolding(plan: Plan, t, l: int, nu, k: int, cols) -> np.ndarray:
+    """The target-side mirror of ``source_unfolding``: rows are the proxy
+    targets of the middle multi-set t in every mode but k, times the proxy
+    sources of nu (level l) in every mode; columns are mode-k target
+    indices."""
+    op, n, d = plan.op, plan.n, plan.d
+    tlists = []
+    for i in range(d):
+        if i == k:
+            tlists.append(np.zeros(1, dtype=np.int64))
+        else:
+            lo, ln = node_range(plan.Lt, t[i], n)
+            tlists.append(proxies(lo, ln, plan.p_other))
+    slists = []
+    for i in range(d):
+        lo, ln = node_range(l, nu[i], n)
+        p = _pair_count(plan.p_pair, len(cols)) if i == k else plan.p_other
+        slists.append(proxies(lo, ln, p))
+    rows = _product_rows(tlists + slists)
+    return _sample(op, rows[:, :d], rows[:, d:], k_tgt=k, cols=np.asarray(cols))
+
+
 def construct(op: Operator, tol: float, leaf: int = 8, p_pair: int | None = None,
               p_other: int | None = None, id_tol_scale: float | None = None,
               lt: int | None = None) -> Plan:
@@ -222,21 +267,7 @@ def construct(op: Operator, tol: float, leaf: int = 8, p_pair: int | None = None
                             ptau = flatten([b >> 1 for b in tau], l - 1)
                             par = plan.src[l - 1][(s_flat, ptau)][k]
                             cols = np.concatenate([par[2 * nu].skel, par[2 * nu + 1].skel])
-                        tlists = []
-                        for i in range(d):
-                            lo, ln = node_range(l, tau[i], n)
-                            p = _pair_count(p_pair, len(cols)) if i == k else p_other
-                            tlists.append(proxies(lo, ln, p))
-                        slists = []
-                        for i in range(d):
-                            if i == k:
-                                slists.append(np.zeros(1, dtype=np.int64))
-                            else:
-                                lo, ln = node_range(Ls, s[i], n)
-                                slists.append(proxies(lo, ln, p_other))
-                        rows = _product_rows(tlists + slists)
-                        trow, srow = rows[:, :d], rows[:, d:]
-                        A = _sample(op, trow, srow, k_src=k, cols=cols)
+                        A = source_unfolding(plan, s, l, tau, k, cols)
                         cid = column_id(A, eps)
                         ids.append(Skeleton(cols[cid.skel], cid.X))
                     per_k.append(ids)
@@ -262,21 +293,7 @@ def construct(op: Operator, tol: float, leaf: int = 8, p_pair: int | None = None
                             pnu = flatten([b >> 1 for b in nu], l - 1)
                             par = plan.tgt[l - 1][(t_flat, pnu)][k]
                             cols = np.concatenate([par[2 * tau].skel, par[2 * tau + 1].skel])
-                        tlists = []
-                        for i in range(d):
-                            if i == k:
-                                tlists.append(np.zeros(1, dtype=np.int64))
-                            else:
-                                lo, ln = node_range(Lt, t[i], n)
-                                tlists.append(proxies(lo, ln, p_other))
-                        slists = []
-                        for i in range(d):
-                            lo, ln = node_range(l, nu[i], n)
-                            p = _pair_count(p_pair, len(cols)) if i == k else p_other
-                            slists.append(proxies(lo, ln, p))
-                        rows = _product_rows(tlists + slists)
-                        trow, srow = rows[:, :d], rows[:, d:]
-                        A = _sample(op, trow, srow, k_tgt=k, cols=cols)
+                        A = target_unfolding(plan, t, l, nu, k, cols)
                         cid = column_id(A, eps)
                         ids.append(Skeleton(cols[cid.skel], cid.X))
                     per_k.append(ids)

@@ -4188,6 +4188,7 @@ static tb_status capture_batched(const GraphKey& key, std::vector<Plan*>& plans,
     e = hipEventRecord(ev[np], cap);
     for (int i = 0; i < np && e == hipSuccess; ++i) e = hipStreamWaitEvent(g_branch_streams[i], ev[np], 0);
     if (e != hipSuccess) st = fail(TB_ERR_HIP, std::string("graph fork: ") + hipGetErrorString(e));
+    std::vector<bool> joined(np, false);
     for (int i = 0; i < np && st == TB_OK; ++i) {
       st = run_apply(*plans[i], key.in[i], key.out[i], key.nrhs[i], (tb_dtype)key.io, key.adjoint != 0,
                      g_branch_streams[i]);
@@ -4195,8 +4196,15 @@ static tb_status capture_batched(const GraphKey& key, std::vector<Plan*>& plans,
         e = hipEventRecord(ev[i], g_branch_streams[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(cap, ev[i], 0);
         if (e != hipSuccess) st = fail(TB_ERR_HIP, std::string("graph join: ") + hipGetErrorString(e));
+        joined[i] = e == hipSuccess;
       }
     }
+    // after a failure, join every forked branch back so that the capture
+    // ends cleanly and the branch streams leave capture mode; the graph is
+    // then discarded
+    for (int i = 0; i < np; ++i)
+      if (!joined[i] && hipEventRecord(ev[i], g_branch_streams[i]) == hipSuccess)
+        (void)hipStreamWaitEvent(cap, ev[i], 0);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cap, &graph);
     if (st == TB_OK && e != hipSuccess)

@@ -3,7 +3,8 @@
 The oracle builds a plan and writes it to a plan file; the library loads
 the file and applies it with its HIP kernels.  Both sides then contract the
 same factorisation, so the GPU result must match the oracle's apply element
-by element: FP64 to 1e-12 relative, FP32 to 2e-5 relative.  (FP32 bound:
+by element: FP64 to 1e-12 relative, FP32 to 2e-5 relative, per right-hand
+side both in the 2-norm and for the worst single output (``assert_parity``).  (FP32 bound:
 each output is a chain of about 2(L+1)d small contractions and one core dot
 product of at most a few thousand terms, each rounding at 2^-24 ~ 6e-8;
 sqrt(terms) growth gives ~1e-5 at worst.)
@@ -16,12 +17,14 @@ from oracle import kernels, planio
 from oracle.kernels import Operator
 from paper_2411_03029_amd import inputs
 
-from .gpu_util import relerr, say, to_dev, to_host, torch_gpu
+from .gpu_util import (assert_parity, relerr, say, to_dev, to_host, torch_gpu, with_bf16_cores,
+                        with_q16_cores)
 
 pytestmark = pytest.mark.gpu
 
 CASES = {
-    # name: (kind, d, n, tol, leaf)  -- tiles span several blocks and levels
+    # name: (kind, d, n, tol, leaf[, target middle level])  -- tiles span
+    # several blocks and levels
     "fourier2_n32": (kernels.FOURIER, 2, 32, 1e-6, 8),
     "fourier2_n64": (kernels.FOURIER, 2, 64, 1e-6, 8),
     "fourier3_n16": (kernels.FOURIER, 3, 16, 1e-4, 4),
@@ -34,6 +37,15 @@ CASES = {
     "radon3_n16": (kernels.RADON, 3, 16, 1e-3, 4),           # 3-D Radon
     "nudft2_n32": (kernels.NUDFT, 2, 32, 1e-6, 8),           # type-2 non-uniform DFT
     "nudft3_n16": (kernels.NUDFT, 3, 16, 1e-3, 4),
+    # d = 3 with L = 3 (two source transfer levels, the second reading a
+    # workspace parent, 512 middle pairs): the structure of the n = 64 cube
+    # workload at a quarter of its points
+    "helm3_n32_leaf4": (kernels.HELMHOLTZ, 3, 32, 1e-4, 4),
+    # contracted dimensions above the on-the-fly cores' 1024-point staging
+    # chunk: R_S up to 3375 (forward chunks), and with the target middle
+    # level at 0, R_T up to 3375 (adjoint chunks), with ragged last chunks
+    "radon3_n16_leaf8": (kernels.RADON, 3, 16, 1e-4, 8),
+    "radon3_n16_leaf8_lt0": (kernels.RADON, 3, 16, 1e-4, 8, 0),
 }
 
 _PLANS = {}
@@ -41,10 +53,12 @@ _PLANS = {}
 
 def oracle_plan(name):
     if name not in _PLANS:
-        kind, d, n, tol, leaf = CASES[name]
+        kind, d, n, tol, leaf = CASES[name][:5]
+        lt = CASES[name][5] if len(CASES[name]) > 5 else None
         om = kernels.helmholtz_omega(n) if kind == kernels.HELMHOLTZ else 0.0
         xs = inputs.nudft_points(n, d) if kind == kernels.NUDFT else None
-        _PLANS[name] = bf.construct(Operator(kind, d, n, omega=om, nudft_x=xs), tol, leaf=leaf)
+        _PLANS[name] = bf.construct(Operator(kind, d, n, omega=om, nudft_x=xs), tol, leaf=leaf,
+                                    lt=lt)
     return _PLANS[name]
 
 
@@ -66,11 +80,11 @@ def test_apply_matches_oracle_fp64(name, tmp_path):
         say(f"[gpu] apply fp64 {name} nrhs={nrhs}")
         u = to_host(plan.apply(to_dev(f, torch.complex128), dtype="c128"))
         torch.cuda.synchronize()
-        assert relerr(u, bf.apply(op, f)) <= 1e-12
+        assert_parity(u, bf.apply(op, f), 1e-12, "forward")
         say(f"[gpu] adjoint fp64 {name} nrhs={nrhs}")
         v = to_host(plan.apply_adjoint(to_dev(f, torch.complex128), dtype="c128"))
         torch.cuda.synchronize()
-        assert relerr(v, bf.apply_adjoint(op, f)) <= 1e-12
+        assert_parity(v, bf.apply_adjoint(op, f), 1e-12, "adjoint")
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -85,12 +99,8 @@ def test_apply_matches_oracle_fp32(name, tmp_path):
         u = to_host(plan.apply(to_dev(f, torch.complex64), dtype="c64"))
         v = to_host(plan.apply_adjoint(to_dev(f, torch.complex64), dtype="c64"))
         torch.cuda.synchronize()
-        assert relerr(u, bf.apply(op, f)) <= 2e-5
-        assert relerr(v, bf.apply_adjoint(op, f)) <= 2e-5
-        # every right-hand side individually
-        ue = bf.apply(op, f)
-        for q in range(nrhs):
-            assert relerr(u[q], ue[q]) <= 2e-5
+        assert_parity(u, bf.apply(op, f), 2e-5, "forward")
+        assert_parity(v, bf.apply_adjoint(op, f), 2e-5, "adjoint")
 
 
 def test_single_input_shape_and_batched_rhs_consistency(tmp_path):
@@ -152,22 +162,28 @@ def test_dtype_without_cores_is_rejected(tmp_path):
 def test_batched_rhs_matrix_cores(name, nrhs, tmp_path):
     # from 8 right-hand sides the core contraction runs on the matrix cores
     # (complex via four real 16x16x4 FP32 MFMAs); BF16 cores accumulate in
-    # FP32 (bound: BF16 rounding 2^-9 per core entry, random signs)
+    # FP32 with the right-hand sides split into BF16 hi + lo parts (each part
+    # within 2^-18 of the FP32 value), so against the oracle's apply of the
+    # BF16-rounded cores the FP32 bound holds with 1e-5 for the split;
+    # against the unrounded cores the BF16 rounding (2^-9 per core part,
+    # random signs) stays within 5e-3 in the 2-norm
     torch = torch_gpu()
     op = oracle_plan(name)
     plan = gpu_plan(name, tmp_path, store=("c64", "cbf16"))
     n, d = op.n, op.d
     f = inputs.rhs_batch(n, d, nrhs, config=98)
-    ue, ve = bf.apply(op, f), bf.apply_adjoint(op, f)
-    for dt, tol in (("c64", 2e-5), ("cbf16", 5e-3)):
+    obf = with_bf16_cores(op)
+    for dt, ref, tol in (("c64", op, 2e-5), ("cbf16", obf, 3e-5)):
         say(f"[gpu] batched {name} nrhs={nrhs} {dt}")
         x = to_dev(f, torch.complex64)
         u = to_host(plan.apply(x, dtype=dt))
         v = to_host(plan.apply_adjoint(x, dtype=dt))
         torch.cuda.synchronize()
-        for q in range(nrhs):
-            assert relerr(u[q], ue[q]) <= tol, (dt, q, relerr(u[q], ue[q]))
-            assert relerr(v[q], ve[q]) <= tol, (dt, q, relerr(v[q], ve[q]))
+        assert_parity(u, bf.apply(ref, f), tol, f"forward {dt}")
+        assert_parity(v, bf.apply_adjoint(ref, f), tol, f"adjoint {dt}")
+        if dt == "cbf16":
+            assert relerr(u, bf.apply(op, f)) <= 5e-3
+            assert relerr(v, bf.apply_adjoint(op, f)) <= 5e-3
 
 
 @pytest.mark.parametrize("name,nrhs", [("helm3_n32", 70), ("radon2_n32", 130), ("fourier2_n64", 9),
@@ -195,8 +211,9 @@ def test_bf16_core_forms_agree(name, nrhs, tmp_path):
     for form in (5, 6, 7):
         assert torch.equal(outs[form][0], outs[4][0]), ("forward", form)
         assert torch.equal(outs[form][1], outs[4][1]), ("adjoint", form)
-    assert relerr(to_host(outs[6][0]), bf.apply(op, f)) <= 5e-3
-    assert relerr(to_host(outs[6][1]), bf.apply_adjoint(op, f)) <= 5e-3
+    obf = with_bf16_cores(op)
+    assert_parity(to_host(outs[6][0]), bf.apply(obf, f), 3e-5, "forward")
+    assert_parity(to_host(outs[6][1]), bf.apply_adjoint(obf, f), 3e-5, "adjoint")
 
 
 @pytest.mark.parametrize("name,nrhs", [("helm3_n32", 13), ("radon2_n32", 11), ("fourier3_n16", 9)])
@@ -230,16 +247,19 @@ def test_fanin_forms_agree(name, nrhs, tmp_path):
 
 @pytest.mark.parametrize("name", ["helm3_n32", "radon2_n32", "fourier2_n64", "plates2_n64", "radon3_n16"])
 def test_q16_cores_match_oracle(name, tmp_path):
-    # block-scaled 16-bit cores (one scale per core column, int16 parts):
-    # per part the error is uniform within half a step, 2^-16 of the
-    # column's largest part, independent over entries, so the core stage
-    # adds a relative error of about 2^-16 * 0.6 * (column max / rms entry):
-    # 1.3e-5 for unit-modulus kernels, below 4e-5 for the Helmholtz cubes
-    # (distances 1..3).  With the FP32 bound 2e-5 the sum stays below 1e-4,
-    # per right-hand side, forward and adjoint; the plan's cores are encoded
-    # on the host from the oracle's FP64 cores
+    # block-scaled 16-bit cores (one scale per core column, int16 parts),
+    # encoded on the host from the oracle's FP64 cores.  Against the oracle's
+    # apply of the same cores passed through the codec the kernels meet the
+    # FP32 bound, per output.  Against the unrounded cores: per part the
+    # error is uniform within half a step, 2^-16 of the column's largest
+    # part, independent over entries, so the core stage adds a relative
+    # error of about 2^-16 * 0.6 * (column max / rms entry): 1.3e-5 for
+    # unit-modulus kernels, below 4e-5 for the Helmholtz cubes (distances
+    # 1..3); with the FP32 bound 2e-5 the 2-norm stays below 1e-4, per
+    # right-hand side, forward and adjoint
     torch = torch_gpu()
     op = oracle_plan(name)
+    oq = with_q16_cores(op)
     plan = gpu_plan(name, tmp_path, store=("cq16",))
     n, d = op.n, op.d
     for nrhs in (1, 6):
@@ -249,10 +269,11 @@ def test_q16_cores_match_oracle(name, tmp_path):
         u = to_host(plan.apply(x, dtype="cq16"))
         v = to_host(plan.apply_adjoint(x, dtype="cq16"))
         torch.cuda.synchronize()
+        assert_parity(u, bf.apply(oq, f), 2e-5, "forward")
+        assert_parity(v, bf.apply_adjoint(oq, f), 2e-5, "adjoint")
         ue, ve = bf.apply(op, f), bf.apply_adjoint(op, f)
         for q in range(nrhs):
-            assert relerr(u[q], ue[q]) <= 1e-4, (q, relerr(u[q], ue[q]))
-            assert relerr(v[q], ve[q]) <= 1e-4, (q, relerr(v[q], ve[q]))
+            assert relerr(u[q], ue[q]) <= 1e-4 and relerr(v[q], ve[q]) <= 1e-4, q
 
 
 def test_q16_cores_encoded_on_the_gpu(tmp_path):
@@ -319,9 +340,7 @@ def test_on_the_fly_cores_match_oracle(name, tmp_path):
         u = to_host(plan.apply(x, dtype="c64otf"))
         v = to_host(plan.apply_adjoint(x, dtype="c64otf"))
         torch.cuda.synchronize()
-        ue, ve = bf.apply(op, f), bf.apply_adjoint(op, f)
-        for q in range(nrhs):
-            assert relerr(u[q], ue[q]) <= 2e-5, (q, relerr(u[q], ue[q]))
-            assert relerr(v[q], ve[q]) <= 2e-5, (q, relerr(v[q], ve[q]))
+        assert_parity(u, bf.apply(op, f), 2e-5, "forward")
+        assert_parity(v, bf.apply_adjoint(op, f), 2e-5, "adjoint")
     with pytest.raises(tb.TBError):  # no stored FP32 cores
         plan.apply(x, dtype="c64")

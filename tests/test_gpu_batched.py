@@ -20,7 +20,7 @@ from oracle import dense, kernels, planio
 from oracle.kernels import Operator
 from paper_2411_03029_amd import inputs
 
-from .gpu_util import relerr, say, to_dev, to_host, torch_gpu
+from .gpu_util import assert_parity, relerr, say, to_dev, to_host, torch_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -66,12 +66,50 @@ def test_batched_matches_single_and_oracle_over_replays(tmp_path):
                 torch.cuda.synchronize()
                 assert torch.equal(single, outs[i]), (adjoint, rep, i)
                 ref = bf.apply_adjoint(ops[i], fs[i]) if adjoint else bf.apply(ops[i], fs[i])
-                assert relerr(to_host(outs[i]), ref) <= 2e-5, (adjoint, rep, i)
+                assert_parity(to_host(outs[i]), ref, 2e-5, f"adjoint={adjoint} replay {rep} plan {i}")
             # eager work between replays on the same plans and buffers
             for i, p in enumerate(plans):
                 outs[i].zero_()
                 p.apply(xs[i])
             torch.cuda.synchronize()
+
+
+def test_batched_capture_failure_then_success(tmp_path):
+    # a launch that does not fit (4 right-hand sides per thread with a tile of
+    # 1) fails the capture of the second plan's branch after the first plan's
+    # branch and part of the second's were captured; every forked branch is
+    # joined back and the capture discarded, so the next call, with that
+    # launch restored to the heuristic, captures and replays normally
+    torch = torch_gpu()
+    import paper_2411_03029_amd as tb
+    from paper_2411_03029_amd import _lib
+    ops, plans, xs, outs = [], [], [], []
+    for i, (kind, d, n, tol, leaf, nrhs) in enumerate(SMALL[:3]):
+        op = bf.construct(_oracle_op(kind, d, n), tol, leaf=leaf)
+        path = str(tmp_path / f"p{i}.tbplan")
+        planio.save_plan(op, path)
+        ops.append(op)
+        plans.append(tb.load_plan(path, store=("c64",)))
+        f = inputs.rhs_batch(n, d, nrhs, config=70 + i)
+        xs.append(to_dev(f, torch.complex64))
+        outs.append(torch.empty_like(xs[-1]))
+    tb.batched_reset()
+    bad = plans[1].launch_slots().index("core") + 1   # first target transfer
+    nrhs1 = xs[1].shape[0]
+    plans[1].set_launch(nrhs1, bad, rhs_tile=1, rhs_per_thread=4)
+    say("[gpu] batched capture that fails in the second branch")
+    with pytest.raises(tb.TBError) as ei:
+        tb.apply_batched(plans, xs, outs)
+    assert ei.value.status == _lib.TB_ERR_UNSUPPORTED
+    torch.cuda.synchronize()
+    plans[1].set_launch(nrhs1, bad)   # back to the heuristic
+    say("[gpu] batched capture after the failure")
+    for rep in range(2):
+        tb.apply_batched(plans, xs, outs)
+        torch.cuda.synchronize()
+        for i, p in enumerate(plans):
+            assert torch.equal(p.apply(xs[i]), outs[i]), (rep, i)
+            assert_parity(to_host(outs[i]), bf.apply(ops[i], to_host(xs[i])), 2e-5, f"plan {i}")
 
 
 def test_batched_rejects_bad_arguments(tmp_path):

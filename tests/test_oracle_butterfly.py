@@ -276,3 +276,39 @@ def test_nudft_plan_file_carries_the_points(nudft32, tmp_path):
     np.testing.assert_array_equal(pf.nudft_x, np.asarray(nudft32.op.nudft_x))
     for key, C in nudft32.cores.items():
         np.testing.assert_array_equal(C, pf.cores[key])
+
+
+def _offsets(paper_rmax, ours):
+    return [p - o for p, o in zip(paper_rmax, ours)]
+
+
+def test_plate_ranks_follow_table2_trend():
+    # Table 2 (plates, n = 16384): max rank 8, 10, 11, 12, 13 at eps =
+    # 1e-2..1e-6.  The paper's leaf size and proxy rule are not stated, so
+    # the absolute ranks are parity unpinned; at n = 32, leaf 8 and IDs at
+    # eps, the oracle's max ranks grow with the tolerance as the paper's do:
+    # the offset to the paper's column stays constant within 1.
+    with open(os.path.join(GOLDEN, "table2_plates.json")) as fh:
+        rows = json.load(fh)["rows"]
+    n = 32
+    op = Operator(kernels.HELMHOLTZ, 2, n, omega=kernels.helmholtz_omega(n))
+    ours = [int(bf.construct(op, row[0], id_tol_scale=1.0).ranks().max()) for row in rows]
+    off = _offsets([row[2] for row in rows], ours)
+    assert max(off) - min(off) <= 1, (ours, off)
+    assert all(b >= a for a, b in zip(ours, ours[1:])) and ours[-1] > ours[0]
+
+
+def test_radon3_ranks_follow_table3_trend():
+    # Table 3 (3-D Radon, eq. randon3d with the paper's (3 + ...)/100, n =
+    # 128): max rank 6, 8, 9, 11 at eps = 1e-2..1e-5.  At n = 16 with leaf 8
+    # and IDs at eps the oracle's max ranks keep a constant offset (within
+    # 1) to that column; absolute values are parity unpinned (leaf size and
+    # proxies unknown).
+    with open(os.path.join(GOLDEN, "table3_radon.json")) as fh:
+        rows = json.load(fh)["radon3d_n128"]
+    op = Operator(kernels.RADON, 3, 16)
+    assert (op.radon_a, op.radon_b, op.radon_den) == (3.0, 1.0, 100.0)
+    ours = [int(bf.construct(op, row[0], leaf=8, id_tol_scale=1.0).ranks().max()) for row in rows]
+    off = _offsets([row[2] for row in rows], ours)
+    assert max(off) - min(off) <= 1, (ours, off)
+    assert all(b >= a for a, b in zip(ours, ours[1:])) and ours[-1] > ours[0]

@@ -262,3 +262,74 @@ def test_nudft_dense_adjoint_identity(d, n):
     lhs = np.vdot(g, dense.apply_brute(op, f))
     rhs = np.vdot(dense.adjoint_brute(op, g), f)
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# ------------------------------------------- Radon speed away from x = 0 --
+# Section 4.2's speed functions at points where the sin/cos products are
+# +-1, 0 or 1/2, so that c1, c2 (d = 2) and c (d = 3) are short fractions
+# worked out by hand: every b-term is live, unlike at x = 0.
+
+def _radon2(n, ti, k, a, b, den):
+    sj = np.array([[n // 2 + k[0], n // 2 + k[1]]])
+    return kernels.radon_entries(n, np.array([ti]), sj, a, b, den)[0]
+
+
+def test_radon2_speed_at_quarter_points_workload_constants():
+    # (a, b, den) = (2, 1, 3).  x = (1/4, 1/4): sin(pi/2)^2 = 1, cos(pi/2) = 0,
+    # so c1 = 1 and c2 = 2/3.  k = (3, 6): x.k = 9/4 and
+    # sqrt(9 + (2/3)^2 36) = 5, phase 7.25 -> K = exp(i pi/2) = i.
+    n = 16
+    assert _radon2(n, (4, 4), (3, 6), 2, 1, 3) == pytest.approx(1j, abs=1e-12)
+    # k = (4, -3): x.k = 1/4, sqrt(16 + 4) = 2 sqrt 5
+    assert _radon2(n, (4, 4), (4, -3), 2, 1, 3) == pytest.approx(
+        np.exp(2j * np.pi * (0.25 + 2 * np.sqrt(5.0))), abs=1e-12)
+    # x = (3/4, 1/4): sin(3pi/2) sin(pi/2) = -1, so c1 = 1/3, c2 = 2/3.
+    # k = (6, 3): x.k = 4.5 + 0.75, sqrt(4 + 4) = 2 sqrt 2
+    assert _radon2(n, (12, 4), (6, 3), 2, 1, 3) == pytest.approx(
+        np.exp(2j * np.pi * (5.25 + 2 * np.sqrt(2.0))), abs=1e-12)
+    # x = (1/8, 1/8): sin^2(pi/4) = cos^2(pi/4) = 1/2, c1 = c2 = 5/6.
+    # k = (3, 4): x.k = 7/8, (5/6) |k| = 25/6
+    assert _radon2(n, (2, 2), (3, 4), 2, 1, 3) == pytest.approx(
+        np.exp(2j * np.pi * (7 / 8 + 25 / 6)), abs=1e-12)
+    # x = (0, 1/4): sin 0 = 0, cos 0 cos(pi/2) = 0: c1 = c2 = 2/3 (the b-terms
+    # vanish on this line only); k = (3, 0) -> 2, x.k = 0 -> K = 1
+    assert _radon2(n, (0, 4), (3, 0), 2, 1, 3) == pytest.approx(1.0, abs=1e-12)
+
+
+def test_radon2_speed_at_quarter_points_paper_constants():
+    # Section 4.2's constants (a, b, den) = (2, 1, 16).  x = (1/4, 1/4):
+    # c1 = 3/16, c2 = 1/8.  k = (-16, 24) at n = 64: x.k = 2 and
+    # sqrt(9 + 9) = 3 sqrt 2.  x = (1/2, 1/2): sin pi = 0, cos pi cos pi = 1,
+    # so c1 = 1/8, c2 = 3/16; k = (16, 16): x.k = 16, sqrt(4 + 9) = sqrt 13.
+    n = 64
+    assert _radon2(n, (16, 16), (-16, 24), 2, 1, 16) == pytest.approx(
+        np.exp(2j * np.pi * (2 + 3 * np.sqrt(2.0))), abs=1e-12)
+    assert _radon2(n, (32, 32), (16, 16), 2, 1, 16) == pytest.approx(
+        np.exp(2j * np.pi * np.sqrt(13.0)), abs=1e-12)
+    # x = (1/4, 3/4): sin(pi/2) sin(3pi/2) = -1, cos(pi/2) cos(3pi/2) = 0,
+    # c1 = 1/16, c2 = 1/8; k = (16, 8): x.k = 10, sqrt(1 + 1) = sqrt 2
+    assert _radon2(n, (16, 48), (16, 8), 2, 1, 16) == pytest.approx(
+        np.exp(2j * np.pi * (10 + np.sqrt(2.0))), abs=1e-12)
+
+
+def test_radon3_speed_at_quarter_points():
+    # (a, b, den) = (3, 1, 100).  x = (1/4, 1/4, 1/4): the sine product is 1,
+    # c = 4/100.  k = (3, 4, 12), |k| = 13: phase 19/4 + 0.52.
+    n = 16
+    op = Operator(kernels.RADON, 3, n)
+    h = n // 2
+    k = np.array([3, 4, 12])
+    assert op.entries(np.array([[4, 4, 4]]), np.array([h + k]))[0] == pytest.approx(
+        np.exp(2j * np.pi * (4.75 + 0.52)), abs=1e-12)
+    # x = (1/4, 3/4, 1/4): the product is -1, c = 2/100; x.k = 0.75 + 3 + 3
+    assert op.entries(np.array([[4, 12, 4]]), np.array([h + k]))[0] == pytest.approx(
+        np.exp(2j * np.pi * (6.75 + 0.26)), abs=1e-12)
+    # x = (1/8, 1/8, 1/4): product 1/2, c = 3.5/100; k = (0, 6, 8), |k| = 10
+    k2 = np.array([0, 6, 8])
+    assert op.entries(np.array([[2, 2, 4]]), np.array([h + k2]))[0] == pytest.approx(
+        np.exp(2j * np.pi * (0.75 + 2 + 0.35)), abs=1e-12)
+    # the workload's own constants (2, 1, 3) at (1/4, 1/4, 1/4): c = 1,
+    # phase 4.75 + 13 -> exp(2 pi i 0.75) = -i
+    op3 = Operator(kernels.RADON, 3, n, radon_a=2.0, radon_b=1.0, radon_den=3.0)
+    assert op3.entries(np.array([[4, 4, 4]]), np.array([h + k]))[0] == pytest.approx(
+        -1j, abs=1e-12)
