@@ -188,6 +188,24 @@ tb_status tb_apply(tb_plan p, const void* f, void* u, long long nrhs,
 tb_status tb_apply_adjoint(tb_plan p, const void* g, void* v, long long nrhs,
                            tb_dtype io, void* hip_stream);
 
+/* Allocation-free apply, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): u = K_BF f (adjoint == 0) or v = K_BF^H g (adjoint != 0),
+ * with the same kernels, launch shapes and results as tb_apply /
+ * tb_apply_adjoint.  The intermediates live in a static device array of
+ * TB_NOALLOC_SCRATCH_BYTES owned by the library (one per GPU, held until the
+ * process ends) instead of the plan's workspace; the call makes no
+ * hipMalloc, hipFree or event creation (per-stage timing is not recorded).
+ * Arrays and streams as for tb_apply.  Every call on one GPU shares that
+ * array and leaves its contents behind: calls that overlap on one GPU (other
+ * streams, other threads, other plans) race, and must be serialised by the
+ * caller.  A request whose intermediates need more than the array holds
+ * fails with TB_ERR_OOM before any launch (the message gives the size);
+ * other errors as tb_apply. */
+#define TB_NOALLOC_SCRATCH_BYTES (256ull << 20)
+tb_status tb_apply_noalloc(tb_plan p, const void* in, void* out, long long nrhs,
+                           tb_dtype io, int adjoint, void* hip_stream);
+
 /* Several operators in one submission: plan i maps in[i] -> out[i] with
  * nrhs[i] right-hand sides (forward, or adjoint if adjoint != 0), all of
  * element type io.  The plans' kernel sequences are the parallel branches of

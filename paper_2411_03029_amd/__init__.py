@@ -128,6 +128,14 @@ class Plan:
         """v = K_BF^H g."""
         return self._run(_lib.load().tb_apply_adjoint, g, out, dtype)
 
+    def apply_noalloc(self, x, out=None, adjoint: bool = False, dtype="c64"):
+        """K_BF x (or K_BF^H x) through tb_apply_noalloc: the intermediates
+        live in the library's fixed device scratch array, no allocation; calls
+        overlapping on one GPU race (see tb_apply_noalloc)."""
+        lib = _lib.load()
+        fn = lambda h, i, o, q, io, st: lib.tb_apply_noalloc(h, i, o, q, io, 1 if adjoint else 0, st)
+        return self._run(fn, x, out, dtype)
+
     def autotune(self, nrhs: int, dtype: str = "c64", cache: str | None = None,
                  stream=None) -> int:
         """Time the launch candidates of every apply kernel for ``nrhs``

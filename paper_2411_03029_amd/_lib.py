@@ -19,7 +19,7 @@ TB_C128, TB_C64, TB_CBF16, TB_C64_OTF, TB_CQ16 = range(5)
 TB_STORE_C128, TB_STORE_C64, TB_STORE_CBF16, TB_STORE_OTF, TB_STORE_CQ16 = 1, 2, 4, 8, 16
 
 # every symbol include/tb.h declares
-EXPORTS = ("tb_construct", "tb_apply", "tb_apply_adjoint", "tb_apply_batched",
+EXPORTS = ("tb_construct", "tb_apply", "tb_apply_adjoint", "tb_apply_noalloc", "tb_apply_batched",
            "tb_batched_reset", "tb_plan_autotune", "tb_plan_set_launch", "tb_plan_info",
            "tb_plan_save", "tb_plan_load", "tb_destroy", "tb_plan_set_timing",
            "tb_plan_stage_times", "tb_last_error", "tb_status_string")
@@ -83,6 +83,7 @@ def load() -> ctypes.CDLL:
                                  ctypes.POINTER(TbOptions), P, ctypes.POINTER(P)]
     lib.tb_apply.argtypes = [P, P, P, ctypes.c_longlong, ctypes.c_int, P]
     lib.tb_apply_adjoint.argtypes = [P, P, P, ctypes.c_longlong, ctypes.c_int, P]
+    lib.tb_apply_noalloc.argtypes = [P, P, P, ctypes.c_longlong, ctypes.c_int, ctypes.c_int, P]
     lib.tb_apply_batched.argtypes = [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P),
                                      ctypes.POINTER(P), ctypes.POINTER(ctypes.c_longlong),
                                      ctypes.c_int, ctypes.c_int, P]
@@ -103,8 +104,8 @@ def load() -> ctypes.CDLL:
     lib.tb_last_error.restype = ctypes.c_char_p
     lib.tb_status_string.restype = ctypes.c_char_p
     lib.tb_status_string.argtypes = [ctypes.c_int]
-    for name in ("tb_construct", "tb_apply", "tb_apply_adjoint", "tb_apply_batched",
-                 "tb_batched_reset", "tb_plan_autotune", "tb_plan_set_launch", "tb_plan_info",
+    for name in ("tb_construct", "tb_apply", "tb_apply_adjoint", "tb_apply_noalloc",
+                 "tb_apply_batched", "tb_batched_reset", "tb_plan_autotune", "tb_plan_set_launch", "tb_plan_info",
                  "tb_plan_save", "tb_plan_load", "tb_plan_set_timing",
                  "tb_plan_stage_times"):
         getattr(lib, name).restype = ctypes.c_int

@@ -3744,15 +3744,24 @@ struct Step {
   std::function<tb_status(const LaunchCfg&)> run;
 };
 
+// ws_ext (nullable): a workspace of ws_cap bytes owned by the caller of the
+// apply; otherwise the plan's own workspace, grown on demand.
 template <class T, class CS>
 static tb_status build_steps(Plan& p, const void* in, void* out, long long nrhs, bool adjoint,
                              const void* cores, hipStream_t stream, std::vector<Step>* steps,
-                             bool otf = false) {
+                             bool otf = false, void* ws_ext = nullptr, size_t ws_cap = 0) {
   using C = typename CplxOf<T>::type;
   const size_t esz = sizeof(C);
   Buffers b = layout(p, nrhs, esz);
-  TB_TRY(ensure_workspace(p, b.total));
-  char* ws = static_cast<char*>(p.ws.base);
+  if (ws_ext) {
+    if (b.total > ws_cap)
+      return fail(TB_ERR_OOM, "apply needs " + std::to_string(b.total) +
+                                  " bytes of workspace; the allocation-free scratch holds " +
+                                  std::to_string(ws_cap));
+  } else {
+    TB_TRY(ensure_workspace(p, b.total));
+  }
+  char* ws = static_cast<char*>(ws_ext ? ws_ext : p.ws.base);
   auto S = [ws, b](int l) { return (void*)(ws + b.src_off[l]); };
   auto Tb = [ws, b](int l) { return (void*)(ws + b.tgt_off[l]); };
   auto mats = [](const Level& lv) -> const void* {
@@ -3802,19 +3811,24 @@ static tb_status build_steps(Plan& p, const void* in, void* out, long long nrhs,
 
 static int steps_per_direction(const Plan& p) { return p.Lt + p.Ls + 3; }
 
+// With a caller workspace (ws_ext) no event is recorded: per-stage timing
+// creates events, and that path promises to allocate nothing.
 template <class T, class CS>
 static tb_status apply_typed(Plan& p, tb_dtype io, const void* in, void* out, long long nrhs, bool adjoint,
-                             const void* cores, hipStream_t stream) {
+                             const void* cores, hipStream_t stream, void* ws_ext, size_t ws_cap) {
   std::vector<Step> steps;
-  const tb_status built =
-      build_steps<T, CS>(p, in, out, nrhs, adjoint, cores, stream, &steps, io == TB_C64_OTF);
+  const tb_status built = build_steps<T, CS>(p, in, out, nrhs, adjoint, cores, stream, &steps,
+                                             io == TB_C64_OTF, ws_ext, ws_cap);
   TB_TRY(built);
   const auto it = p.tuned.find({(int)io, nrhs});
   const LaunchCfg none{};
   const int base = adjoint ? steps_per_direction(p) : 0;
   for (size_t i = 0; i < steps.size(); ++i) {
     const LaunchCfg& cfg = it == p.tuned.end() ? none : it->second[base + i];
-    TB_TRY(timed(p, steps[i].stage, stream, [&] { return steps[i].run(cfg); }));
+    if (ws_ext)
+      TB_TRY(steps[i].run(cfg));
+    else
+      TB_TRY(timed(p, steps[i].stage, stream, [&] { return steps[i].run(cfg); }));
   }
   return TB_OK;
 }
@@ -3827,7 +3841,7 @@ static bool has_cores(const Plan& p, int io) {
 }
 
 tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs, tb_dtype io, bool adjoint,
-                    hipStream_t stream) {
+                    hipStream_t stream, void* ws_ext, size_t ws_cap) {
   if (!in || !out) return fail(TB_ERR_INVALID_ARG, "null input or output pointer");
   if (nrhs < 1 || nrhs > (1 << 20)) return fail(TB_ERR_INVALID_ARG, "nrhs must be in [1, 2^20]");
   if (!valid_io(io)) return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
@@ -3835,14 +3849,52 @@ tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs, tb_dtype
     return fail(TB_ERR_INVALID_ARG,
                 "the plan holds no cores of the requested precision (see store_mask)");
   if (in == out) return fail(TB_ERR_INVALID_ARG, "input and output must not alias");
+  void* cs = io == TB_C64_OTF ? nullptr : p.cores[io];
   switch (io) {
-    case TB_C128: return apply_typed<double, double2>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
-    case TB_C64: return apply_typed<float, float2>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
-    case TB_CBF16: return apply_typed<float, unsigned>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
-    case TB_C64_OTF: return apply_typed<float, float2>(p, io, in, out, nrhs, adjoint, nullptr, stream);
-    case TB_CQ16: return apply_typed<float, Q16>(p, io, in, out, nrhs, adjoint, p.cores[io], stream);
+    case TB_C128: return apply_typed<double, double2>(p, io, in, out, nrhs, adjoint, cs, stream, ws_ext, ws_cap);
+    case TB_C64: return apply_typed<float, float2>(p, io, in, out, nrhs, adjoint, cs, stream, ws_ext, ws_cap);
+    case TB_CBF16: return apply_typed<float, unsigned>(p, io, in, out, nrhs, adjoint, cs, stream, ws_ext, ws_cap);
+    case TB_C64_OTF: return apply_typed<float, float2>(p, io, in, out, nrhs, adjoint, cs, stream, ws_ext, ws_cap);
+    case TB_CQ16: return apply_typed<float, Q16>(p, io, in, out, nrhs, adjoint, cs, stream, ws_ext, ws_cap);
   }
   return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
+}
+
+// --------------------------------------------------- allocation-free apply --
+// The apply's intermediates (one buffer per level, the whole workspace of
+// tb_apply) in a file-scope device array instead of plan-owned memory, for
+// callers that cannot allocate.  Each device holds its own copy of the array
+// for the life of the process.  In host code its name is a host-side stand-in,
+// so its device address is looked up once per device (with that device
+// current) and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[TB_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+static tb_status scratch_address(void** out) {
+  int dev = 0;
+  TB_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(TB_ERR_UNSUPPORTED, "device index beyond the allocation-free apply's table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(TB_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TB_OK;
+}
+
+tb_status run_apply_noalloc(Plan& p, const void* in, void* out, long long nrhs, tb_dtype io,
+                            bool adjoint, hipStream_t stream) {
+  void* ws = nullptr;
+  TB_TRY(scratch_address(&ws));
+  return run_apply(p, in, out, nrhs, io, adjoint, stream, ws, (size_t)TB_NOALLOC_SCRATCH_BYTES);
 }
 
 // ------------------------------------------------------------ autotuner --
@@ -4336,4 +4388,11 @@ extern "C" tb_status tb_apply_adjoint(tb_plan ph, const void* g, void* v, long l
   if (!ph) return tb::fail(TB_ERR_INVALID_ARG, "tb_apply_adjoint: null plan");
   return tb::run_apply(*reinterpret_cast<tb::Plan*>(ph), g, v, nrhs, io, true,
                        static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" tb_status tb_apply_noalloc(tb_plan ph, const void* in, void* out, long long nrhs, tb_dtype io,
+                                      int adjoint, void* hip_stream) {
+  if (!ph) return tb::fail(TB_ERR_INVALID_ARG, "tb_apply_noalloc: null plan");
+  return tb::run_apply_noalloc(*reinterpret_cast<tb::Plan*>(ph), in, out, nrhs, io, adjoint != 0,
+                               static_cast<hipStream_t>(hip_stream));
 }

@@ -168,7 +168,8 @@ long long apply_cmacs(const Plan& p, long long* per_stage = nullptr);
 // kernels launched by host code
 tb_status launch_core_eval(Plan& p, hipStream_t stream, const double2* host_cores);
 tb_status run_apply(Plan& p, const void* in, void* out, long long nrhs,
-                    tb_dtype io, bool adjoint, hipStream_t stream);
+                    tb_dtype io, bool adjoint, hipStream_t stream,
+                    void* ws_ext = nullptr, size_t ws_cap = 0);
 tb_status run_construct_ids(Plan& p, hipStream_t stream);
 tb_status prepare_workspace(Plan& p, long long nrhs, tb_dtype io);
 tb_status run_autotune(Plan& p, long long nrhs, tb_dtype io, const char* cache, hipStream_t stream,

@@ -71,6 +71,7 @@ def test_null_plan_and_pointers():
     lib = _lib.load()
     assert lib.tb_apply(None, None, None, 1, 1, None) == _lib.TB_ERR_INVALID_ARG
     assert lib.tb_apply_adjoint(None, None, None, 1, 1, None) == _lib.TB_ERR_INVALID_ARG
+    assert lib.tb_apply_noalloc(None, None, None, 1, 1, 0, None) == _lib.TB_ERR_INVALID_ARG
     assert lib.tb_plan_info(None, None) == _lib.TB_ERR_INVALID_ARG
     assert lib.tb_plan_save(None, b"/tmp/x") == _lib.TB_ERR_INVALID_ARG
     assert lib.tb_plan_autotune(None, 1, 1, None, None, None) == _lib.TB_ERR_INVALID_ARG
