@@ -10,7 +10,13 @@ helmholtz_cubes_n64 (default)
     complex FP32 with FP32 accumulation, on a plan built and autotuned on the
     GPU.  Also printed: the plain FP64 apply of the same plan, the errors of
     both against the exact operator, the roofline of the dominant kernel (the
-    core contraction, HBM-bound) and the CPU oracle on the host cores.
+    core contraction, HBM-bound), the whole apply against the HBM roof per
+    direction, the median step time from HIP events, the on-the-fly and
+    16-bit core forms, a batched leg (the cubes at n = 128 with 64
+    right-hand sides: per-stage TFLOP/s against the FP32 matrix-core peak),
+    and on the host cores: the CPU oracle's own butterfly, the exact operator
+    by FFT convolution, and the library applying the oracle's plan against
+    the oracle (e_kernel).
 uneven_mix_bf16
     Eight 2-D Fourier operators (n in {64, 128, 256}, accuracy 1e-6) and four
     Helmholtz cube operators (n in {32, 64}, 1e-4), each with a seeded number
@@ -21,6 +27,12 @@ helmholtz_cubes_n128_lsq
     Helmholtz cubes at n = 128 (2097152 points per cube), 64 right-hand
     sides; one step of gradient descent on ||K f - b||^2 with b = K f_true +
     noise, f_true sums of Gaussian bumps (r = K f - b, g = K^H r, f -= eta g).
+helmholtz_cubes_n512_paper
+    The cubes at the paper's n = 512 with cores on the fly (context).
+operator_table
+    The parallel plates, the 3-D Radon transform and the type-2 non-uniform
+    DFT at several sizes: construction, ranks, forward + adjoint time per
+    core storage and the error on sampled rows against direct summation.
 
 Each run prints one JSON line.
 
@@ -65,10 +77,49 @@ def time_steps(plan, x, dtype, steps, warmup, torch):
     return time.perf_counter() - t0
 
 
-def cpu_baseline_leg(kind, d, n, tol, f_host, gpu_out):
+def cpu_model() -> str:
+    """The host CPU's model name (what lscpu prints as 'Model name')."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def kernel_parity(tb, torch, oplan, f_host, uo, vo):
+    """e_kernel: the library applying the oracle's own plan (written to a plan
+    file, loaded with FP32 and FP64 cores) against the oracle's apply of that
+    plan, forward and adjoint: relative 2-norm and worst single output."""
+    import tempfile
+
+    import numpy as np
+
+    from oracle import planio
+    out = {}
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "oracle.tbplan")
+        planio.save_plan(oplan, path)
+        plan = tb.load_plan(path, store=("c64", "c128"))
+    for dt, cdt in (("c64", torch.complex64), ("c128", torch.complex128)):
+        x = torch.from_numpy(f_host).to("cuda", cdt)
+        u = plan.apply(x, dtype=dt).cpu().numpy().astype(np.complex128)
+        v = plan.apply_adjoint(x, dtype=dt).cpu().numpy().astype(np.complex128)
+        out[dt] = {"fwd": _relerr(u, uo), "adj": _relerr(v, vo),
+                   "fwd_elem": float(np.abs(u - uo).max() / np.abs(uo).max()),
+                   "adj_elem": float(np.abs(v - vo).max() / np.abs(vo).max())}
+    plan.close()
+    return out
+
+
+def cpu_baseline_leg(kind, d, n, tol, f_host, gpu_out, tb=None, torch=None):
     """The FP64 oracle on the host cores: its plain tensor butterfly apply
     (forward + adjoint, own plan, construction untimed) and the exact
-    operator, which also gives the errors of the GPU results."""
+    operator (FFT convolution / FFT), which also gives the errors of the GPU
+    results; with the library at hand, also the library's apply of the
+    oracle's own plan against the oracle's (e_kernel)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -81,8 +132,13 @@ def cpu_baseline_leg(kind, d, n, tol, f_host, gpu_out):
     om = kernels.helmholtz_omega(n) if kid == kernels.HELMHOLTZ else 0.0
     op = kernels.Operator(kid, d, n, omega=om)
     with threadpool_limits(cores):
-        u_exact = dense.apply_exact(op, f_host)
-        v_exact = dense.adjoint_exact(op, f_host)
+        dense.apply_exact(op, f_host)                  # warm-up (FFT plans)
+        ereps, t0 = 0, time.perf_counter()
+        while ereps < 2 or time.perf_counter() - t0 < 2.0:
+            u_exact = dense.apply_exact(op, f_host)
+            v_exact = dense.adjoint_exact(op, f_host)
+            ereps += 1
+        t_exact = (time.perf_counter() - t0) / ereps
         errors = {}
         for name, (u, v) in gpu_out.items():
             errors[name] = {
@@ -100,6 +156,7 @@ def cpu_baseline_leg(kind, d, n, tol, f_host, gpu_out):
             reps += 1
         t_step = (time.perf_counter() - t0) / reps
     err_oracle = float(np.linalg.norm(uo - u_exact) / np.linalg.norm(u_exact))
+    err_oracle_adj = float(np.linalg.norm(vo - v_exact) / np.linalg.norm(v_exact))
     base = {
         "value": f_host.shape[0] * n ** d / t_step,
         "unit": "points/s",
@@ -108,7 +165,16 @@ def cpu_baseline_leg(kind, d, n, tol, f_host, gpu_out):
         "sample": (f"{reps} forward+adjoint applies of the FP64 plain tensor butterfly "
                    f"(numpy, own plan, construction {t_construct:.1f} s untimed) on "
                    f"the full workload; rel err {err_oracle:.2e}"),
+        "cpu_model": cpu_model(),
+        "e_comp_oracle": {"fwd": err_oracle, "adj": err_oracle_adj},
+        "exact_reference": {
+            "value": f_host.shape[0] * n ** d / t_exact, "unit": "points/s",
+            "ms_per_step": 1e3 * t_exact,
+            "kind": ("the exact operator by zero-padded FFT convolution (FFT for the DFT), numpy "
+                     f"FP64, forward + adjoint, {ereps} repetitions")},
     }
+    if tb is not None:
+        base["e_kernel"] = kernel_parity(tb, torch, oplan, f_host, uo, vo)
     return base, errors
 
 
@@ -338,9 +404,39 @@ def run_single(args, tb, inputs, torch, np) -> dict:
                  "frac_fwd": round(apply_bytes / t_fwd / 1e9 / HBM_PEAK_GBS, 4),
                  "frac_adj": round(apply_bytes / t_adj / 1e9 / HBM_PEAK_GBS, 4)}
 
+    # per-step times from HIP events on the stream the library launches on
+    # (torch's current stream): median over the steps, beside the wall clock
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    u32 = plan.apply(x32)
+    v32 = plan.apply_adjoint(u32)
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record()
+        plan.apply(x32, out=u32)
+        plan.apply_adjoint(u32, out=v32)
+        e1.record()
+    torch.cuda.synchronize()
+    ms_events = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    step_events = {"median_ms": ms_events[len(ms_events) // 2], "min_ms": ms_events[0],
+                   "max_ms": ms_events[-1], "steps": len(ms_events)}
+
+    # the on-the-fly core kernel against the ALU: 8 flops per complex
+    # multiply-add of the contraction (the entry evaluation comes on top:
+    # an FP64 squared distance, a refined reciprocal square root and FP32
+    # sine and cosine per entry)
+    otf_flops = 8.0 * info["core_entries"] * nrhs
+    otf["alu"] = {"bound": "alu", "achieved": round(otf_flops / otf_fwd_s / 1e12, 2),
+                  "peak": 157.3, "unit": "TFLOP/s",
+                  "frac": round(otf_flops / otf_fwd_s / 1e12 / 157.3, 4),
+                  "issue_limit_no_packed_fp32": 78.6,
+                  "frac_of_issue_limit": round(otf_flops / otf_fwd_s / 1e12 / 78.6, 4)}
+
+    batched = None if args.no_batched else batched_leg(args, tb, inputs, torch, np)
+
     cpu_base, errors = None, None
     if not args.no_cpu_baseline:
-        cpu_base, errors = cpu_baseline_leg(kind, d, n, tol, f_host, gpu_out)
+        cpu_base, errors = cpu_baseline_leg(kind, d, n, tol, f_host, gpu_out, tb, torch)
 
     return _line(
         args, METRIC, value, "points/s", 1000 * t32 / args.steps, "f32",
@@ -353,11 +449,49 @@ def run_single(args, tb, inputs, torch, np) -> dict:
                                   all(errors[k]["fwd"] <= 1e-4 and errors[k]["adj"] <= 1e-4
                                       for k in ("c64", "c128", "c64otf")))},
         roofline=roofline, apply_hbm=apply_hbm, stage_avg_us=stage_us, on_the_fly_cores=otf,
-        q16_cores=q16,
+        q16_cores=q16, step_hip_events=step_events, batched_n128_64rhs=batched,
         cpu_baseline=cpu_base,
         construct_s=round(construct_s, 3), autotune_s=round(autotune_s, 3),
         plan={k: info[k] for k in ("L", "Lt", "Ls", "r_min", "r_max", "n_ids", "n_pairs",
                                    "core_entries", "factor_entries", "apply_cmacs", "eps_id")})
+
+
+def batched_leg(args, tb, inputs, torch, np) -> dict:
+    """The batched form at the n = 128 cube workload: Helmholtz cubes, n =
+    128, tol 1e-4, 64 right-hand sides, one step = tb_apply + tb_apply_adjoint
+    in complex FP32 (cores on the FP32 matrix cores); per-stage TFLOP/s from
+    HIP events against the FP32 matrix-core peak."""
+    kind, d, n, tol, nrhs = "helmholtz", 3, 128, 1e-4, 64
+    t0 = time.perf_counter()
+    plan = tb.construct(kind, d, n, tol, store=("c64",))
+    torch.cuda.synchronize()
+    construct_s = time.perf_counter() - t0
+    info = plan.info()
+    t0 = time.perf_counter()
+    plan.autotune(nrhs, dtype="c64", cache=args.tune_cache)
+    autotune_s = time.perf_counter() - t0
+    x = torch.from_numpy(inputs.rhs_batch(n, d, nrhs, config=5)).to("cuda", torch.complex64)
+    steps = max(3, min(args.steps, 20))
+    t = time_steps(plan, x, "c64", steps, 2, torch)
+    plan.set_timing(True)
+    time_steps(plan, x, "c64", 1, 0, torch)
+    st = _stage_ms(plan)
+    plan.set_timing(False)
+    per = {k: {"ms": round(ms, 3), "launches": c,
+               "TFLOP/s": round(_stage_flops(info, k, nrhs) / (ms * 1e-3) / 1e12, 2),
+               "frac_fp32_mfma": round(_stage_flops(info, k, nrhs) / (ms * 1e-3) / 1e12 / 157.3, 4)}
+           for k, (ms, c) in st.items()}
+    dom = max(st, key=lambda k: st[k][0])
+    flops = 8.0 * info["apply_cmacs"] * nrhs * 2
+    out = {"value": nrhs * n ** d * steps / t, "unit": "points/s",
+           "ms_per_step": 1e3 * t / steps, "steps": steps, "nrhs": nrhs,
+           "step": "tb_apply + tb_apply_adjoint, complex FP32",
+           "whole_step_TFLOPs": round(flops / (t / steps) / 1e12, 2),
+           "dominant_stage": dom, "dominant_frac_fp32_mfma": per[dom]["frac_fp32_mfma"],
+           "stages": per, "construct_s": round(construct_s, 3), "autotune_s": round(autotune_s, 3)}
+    plan.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 MIX = ([("fourier", 2, n, 1e-6) for n in (64, 128, 256, 64, 128, 256, 64, 128)] +
@@ -595,6 +729,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="helmholtz_cubes_n64", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="", help="operator_table: comma-separated row labels")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the n = 128, 64 right-hand-side leg of the default workload")
     ap.add_argument("--tune-cache", default=None, metavar="PATH",
                     help="autotuner cache file (reused choices skip the timed trials)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -672,11 +809,77 @@ def run_paper_scale(args, tb, inputs, torch, np) -> dict:
                        "note": "one forward apply there; context, not this metric's baseline"})
 
 
+OPERATOR_TABLE = [
+    # (label, kind, d, n, tol, stores): the more-operators and non-uniform
+    # DFT rows; the sampled error is against direct summation
+    ("plates_n256", "helmholtz", 2, 256, 1e-6, ("c64", "otf")),
+    ("plates_n1024", "helmholtz", 2, 1024, 1e-6, ("c64", "otf")),
+    ("radon3_n32", "radon", 3, 32, 1e-3, ("c64", "otf")),
+    ("radon3_n64", "radon", 3, 64, 1e-3, ("c64", "otf")),
+    ("radon3_n128", "radon", 3, 128, 1e-3, ("otf",)),
+    ("nudft2_n256", "nudft", 2, 256, 1e-6, ("c64", "cq16")),
+    ("nudft2_n1024", "nudft", 2, 1024, 1e-6, ("c64", "cq16")),
+    ("nudft3_n32", "nudft", 3, 32, 1e-3, ("c64", "cq16")),
+    ("nudft3_n64", "nudft", 3, 64, 1e-3, ("c64", "cq16")),
+]
+
+
+def run_operator_table(args, tb, inputs, torch, np) -> dict:
+    """The plates (Helmholtz d = 2), 3-D Radon and type-2 non-uniform DFT
+    rows: construction time, ranks, core entries, forward + adjoint time per
+    core storage (autotuned, one right-hand side, complex FP32) and the error
+    on 64 sampled target rows against direct summation.  Rows whose label
+    is not in --only (comma separated, default all) are skipped."""
+    from oracle import dense, kernels
+    only = set(args.only.split(",")) if args.only else None
+    kid = {"helmholtz": kernels.HELMHOLTZ, "radon": kernels.RADON, "nudft": kernels.NUDFT}
+    rows = {}
+    for label, kind, d, n, tol, stores in OPERATOR_TABLE:
+        if only is not None and label not in only:
+            continue
+        extra = {}
+        xs = None
+        if kind == "nudft":
+            xs = inputs.nudft_points(n, d)
+            extra["nudft_x"] = xs
+        print(f"[bench] {label}: construct", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        plan = tb.construct(kind, d, n, tol, store=stores, **extra)
+        torch.cuda.synchronize()
+        construct_s = time.perf_counter() - t0
+        info = plan.info()
+        f_host = inputs.rhs_batch(n, d, 1, config=7)
+        x = torch.from_numpy(f_host).to("cuda", torch.complex64)
+        om = kernels.helmholtz_omega(n) if kind == "helmholtz" else 0.0
+        op = kernels.Operator(kid[kind], d, n, omega=om, nudft_x=xs)
+        sel = np.sort(np.random.default_rng(8).choice(n ** d, 64, replace=False))
+        exact = dense.apply_brute(op, f_host, rows=sel).reshape(-1)
+        row = {"kind": kind, "d": d, "n": n, "tol": tol, "construct_s": round(construct_s, 3),
+               "r_min": info["r_min"], "r_max": info["r_max"], "core_entries": info["core_entries"],
+               "device_bytes": info["device_bytes"]}
+        for st in stores:
+            dt = {"c64": "c64", "otf": "c64otf", "cq16": "cq16"}[st]
+            plan.autotune(1, dtype=dt, cache=args.tune_cache)
+            steps = max(3, min(args.steps, 50))
+            t = time_steps(plan, x, dt, steps, 2, torch)
+            u = plan.apply(x, dtype=dt).cpu().numpy().astype(np.complex128).reshape(-1)
+            row[dt] = {"ms_fwd_adj": round(1e3 * t / steps, 3),
+                       "sampled_err": _relerr(u[sel], exact)}
+        plan.close()
+        torch.cuda.empty_cache()
+        rows[label] = row
+        print(f"[bench] {label}: {row}", file=sys.stderr, flush=True)
+    return _line(
+        args, "tb_apply n^d points/s (fwd+adjoint) per operator", None, "points/s", None, "f32",
+        {"workload": args.workload, "rows": list(rows)}, operators=rows, cpu_baseline=None)
+
+
 WORKLOADS = {
     "helmholtz_cubes_n64": run_single,
     "uneven_mix_bf16": run_mix,
     "helmholtz_cubes_n128_lsq": run_lsq,
     "helmholtz_cubes_n512_paper": run_paper_scale,
+    "operator_table": run_operator_table,
 }
 
 

@@ -149,10 +149,10 @@ class Plan:
 
     def set_launch(self, nrhs: int, slot: int, dtype: str = "c64", outputs_per_thread=0,
                    rhs_tile=0, whole_blocks=0, core_kernel=0, fanin_in_turn=0,
-                   transfer_mfma=0, rhs_per_thread=0) -> None:
+                   transfer_mfma=0, rhs_per_thread=0, flat_stage=0) -> None:
         """Force the configuration of one launch slot (see tb_plan_set_launch)."""
         c = _lib.TbLaunchCfg(outputs_per_thread, rhs_tile, whole_blocks, core_kernel,
-                             fanin_in_turn, transfer_mfma, rhs_per_thread)
+                             fanin_in_turn, transfer_mfma, rhs_per_thread, flat_stage)
         _lib.check(_lib.load().tb_plan_set_launch(self._h, int(nrhs), DTYPES[dtype], int(slot),
                                                   ctypes.byref(c)))
 

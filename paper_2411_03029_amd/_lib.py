@@ -43,7 +43,7 @@ class TbLaunchCfg(ctypes.Structure):
     _fields_ = [("outputs_per_thread", ctypes.c_int), ("rhs_tile", ctypes.c_int),
                 ("whole_blocks", ctypes.c_int), ("core_kernel", ctypes.c_int),
                 ("fanin_in_turn", ctypes.c_int), ("transfer_mfma", ctypes.c_int),
-                ("rhs_per_thread", ctypes.c_int)]
+                ("rhs_per_thread", ctypes.c_int), ("flat_stage", ctypes.c_int)]
 
 
 class TbPlanInfo(ctypes.Structure):

@@ -30,230 +30,10 @@
 #include <type_traits>
 
 #include "cplx.h"
+#include "stage_common.h"
 #include "tb_internal.h"
 
 namespace tb {
-
-constexpr int kThreads = 256;
-
-struct StageArgs {
-  int nb, nblk, lvl;              // blocks per mode, nb^d, fine level
-  int nsplit, chunk;              // slices of the first output mode
-  int R[kMaxD], A[kMaxD];         // fine padded ranks, coarse block sizes
-  long long mat_item_stride;
-  long long mat_k_off[kMaxD];
-  long long fineE;                // entries per fine item
-  long long fst[kMaxD];           // fine item strides (entries)
-  int coarse_global;              // coarse is the caller's (nrhs, n^d) array
-  long long coarseE;
-  long long cst[kMaxD];           // coarse item strides (entries)
-  long long n, ndim;              // n and n^d (global arrays)
-  int outer_level, outer_block;   // outer multi-set level and block size
-  int nrhs;
-  int conj;
-  const int* rank_f;              // true ranks of the fine level [item][k][blk]
-  const int* rank_c;              // true ranks of the coarse level (null: leaves)
-  int nb_c;                       // blocks per mode of a coarse item
-  int Rc[kMaxD];                  // padded ranks of the coarse level
-};
-
-// True extent of mode k of the coarse block beta_k: the two children's
-// skeletons of sizes h1, h2 sit at offsets 0 and Rc in the padded block.
-// Leaves (caller's array) are dense: h1 = A, no second part.
-struct Seg {
-  int c, h1, off2;
-  __device__ int pos(int j) const { return j < h1 ? j : off2 + (j - h1); }
-};
-
-template <int D>
-__device__ __forceinline__ void unflatten_blk(int f, int nb, int* beta) {
-#pragma unroll
-  for (int k = D - 1; k >= 0; --k) {
-    beta[k] = f % nb;
-    f /= nb;
-  }
-}
-
-template <int D>
-__device__ __forceinline__ int parent_of(int item, int l) {
-  int outer = item >> (D * l);
-  int inner = item & ((1 << (D * l)) - 1);
-  int pin = 0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    int b = (inner >> (l * (D - 1 - k))) & ((1 << l) - 1);
-    pin = (pin << (l - 1)) | (b >> 1);
-  }
-  return (outer << (D * (l - 1))) | pin;
-}
-
-template <int D>
-__device__ __forceinline__ int child_of(int citem, int l, int c) {
-  // citem at level l - 1; child c in [0, 2^D) at level l
-  int outer = citem >> (D * (l - 1));
-  int pin = citem & ((1 << (D * (l - 1))) - 1);
-  int inner = 0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    int pk = (l > 1) ? (pin >> ((l - 1) * (D - 1 - k))) & ((1 << (l - 1)) - 1) : 0;
-    int ck = (c >> (D - 1 - k)) & 1;
-    inner = (inner << l) | (2 * pk + ck);
-  }
-  return (outer << (D * l)) | inner;
-}
-
-// Address of element (j_0..j_{D-1}, q) of coarse block beta of coarse item
-// `citem` (intermediate) or of outer block `citem` (global array).
-template <int D>
-struct CoarseAddr {
-  long long base;
-  long long stride[D];
-  long long qstride;
-  __device__ void init(const StageArgs& a, int citem, const int* beta, int q0) {
-    if (a.coarse_global) {
-      int o[D];
-      unflatten_blk<D>(citem, 1 << a.outer_level, o);
-      long long st = 1;
-      base = 0;
-#pragma unroll
-      for (int k = D - 1; k >= 0; --k) {
-        stride[k] = st;
-        base += (long long)(o[k] * a.outer_block + beta[k] * a.A[k]) * st;
-        st *= a.n;
-      }
-      qstride = a.ndim;
-      base += (long long)q0 * a.ndim;
-    } else {
-      base = (long long)citem * a.coarseE;
-#pragma unroll
-      for (int k = 0; k < D; ++k) base += (long long)beta[k] * a.A[k] * a.cst[k];
-      base = base * a.nrhs + q0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) stride[k] = a.cst[k] * a.nrhs;
-      qstride = 1;
-    }
-  }
-};
-
-template <int D>
-__device__ __forceinline__ long long fine_base(const StageArgs& a, int fi, const int* beta, int q0,
-                                               long long* stride) {
-  long long base = (long long)fi * a.fineE;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    base += (long long)beta[k] * a.R[k] * a.fst[k];
-    stride[k] = a.fst[k] * a.nrhs;
-  }
-  return base * a.nrhs + q0;
-}
-
-template <int D>
-__device__ __forceinline__ void coarse_segs(const StageArgs& a, int citem, const int* beta, Seg* sg) {
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    if (a.rank_c == nullptr) {
-      sg[k].c = a.A[k];
-      sg[k].h1 = a.A[k];
-      sg[k].off2 = 0;
-    } else {
-      const int* rc = a.rank_c + ((long long)citem * D + k) * a.nb_c + 2 * beta[k];
-      sg[k].h1 = rc[0];
-      sg[k].c = rc[0] + rc[1];
-      sg[k].off2 = a.Rc[k];
-    }
-  }
-}
-
-// Register-blocked mode product shared by the stage kernels:
-//   acc[g] += sum_{j < nj} m(g, j) x(j),  g < ng (wave-uniform, ng <= G).
-// One thread owns a fiber x of the contracted mode and G outputs along the
-// new mode, so each input element is loaded once per group of G outputs.
-// G = 1 keeps every thread busy on small blocks (one right-hand side);
-// G = 8 cuts loads when right-hand sides fill the workgroup.  The stage
-// kernels take G (kG) as a template parameter; the autotuner picks it.
-// Outputs g >= ng repeat row ng - 1 (an in-bounds read) and are never
-// stored: the inner loop carries no per-output branch.
-template <int G, class C, class MF, class XF>
-__device__ __forceinline__ void gdot(C (&acc)[G], int ng, int nj, MF m, XF x) {
-  int row[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) row[g] = min(g, ng - 1);
-#pragma unroll 2
-  for (int j = 0; j < nj; ++j) {
-    const C xv = x(j);
-#pragma unroll
-    for (int g = 0; g < G; ++g) acc[g] = cfma(acc[g], m(row[g], j), xv);
-  }
-}
-
-template <int G, class C>
-__device__ __forceinline__ void gzero(C (&acc)[G]) {
-#pragma unroll
-  for (int g = 0; g < G; ++g) acc[g] = czero<C>();
-}
-
-// gdot with V right-hand sides per thread as well (x(j, v) is element j of
-// right-hand side v): each matrix element loaded serves V products.  The
-// order of the sum per output is the one of gdot.
-template <int G, int V, class C, class MF, class XF>
-__device__ __forceinline__ void gdotv(C (&acc)[G][V], int ng, int nj, MF m, XF x) {
-  int row[G];
-#pragma unroll
-  for (int g = 0; g < G; ++g) row[g] = min(g, ng - 1);
-#pragma unroll 2
-  for (int j = 0; j < nj; ++j) {
-    C xv[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) xv[v] = x(j, v);
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const C mv = m(row[g], j);
-#pragma unroll
-      for (int v = 0; v < V; ++v) acc[g][v] = cfma(acc[g][v], mv, xv[v]);
-    }
-  }
-}
-
-template <int G, int V, class C>
-__device__ __forceinline__ void gzero2(C (&acc)[G][V]) {
-#pragma unroll
-  for (int g = 0; g < G; ++g)
-#pragma unroll
-    for (int v = 0; v < V; ++v) acc[g][v] = czero<C>();
-}
-
-
-// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
-// xcd_item maps workgroup b of n to work item u so that groups of g
-// consecutive items (items that share data: the right-hand-side tiles of
-// one block or core panel) run back to back on one XCD, while successive
-// groups still go round-robin over the XCDs (irregular work stays balanced).
-// The tail that does not fill 8 whole groups keeps the identity map; a
-// bijection on [0, n) for any n and g.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_item(int b, int n, int g) {
-  const int span = kXcds * g;
-  if (g <= 1 || b >= n / span * span) return b;
-  const int x = b % kXcds, i = b / kXcds;  // i-th workgroup on XCD x
-  return ((i / g) * kXcds + x) * g + i % g;
-}
-
-// Workgroup -> (block, slice, right-hand-side tile); the tile index runs
-// fastest and the enumeration is XCD-contiguous, so that workgroups sharing
-// cache lines of the q-innermost intermediates run in the same L2.
-struct StageBid {
-  int item_blk, split, q0;
-};
-__device__ __forceinline__ StageBid stage_bid(const StageArgs& a, int QT) {
-  const int nqt = (a.nrhs + QT - 1) / QT;
-  int bid = xcd_item(blockIdx.x, gridDim.x, nqt * a.nsplit);
-  StageBid s;
-  s.q0 = (bid % nqt) * QT;
-  bid /= nqt;
-  s.split = bid % a.nsplit;
-  s.item_blk = bid / a.nsplit;
-  return s;
-}
 
 // --------------------------------------------------------------- fan-out --
 // fine(a_0..a_{D-1}, q) = sum_j prod_k M_k[a_k][j_k] coarse(j_0..j_{D-1}, q)
@@ -460,7 +240,6 @@ __global__ void __launch_bounds__(kThreads)
 // over the children's true ranks, for the coarse block's true entries with
 // a_0 in this workgroup's slice [lo, lo + na) (compact numbering).  All
 // children are processed together: two barriers per workgroup.
-constexpr int kMaxChildren = 1 << kMaxD;
 constexpr int kStageU = 8;  // staging loads in flight per thread (fan-in)
 
 // Stages the fan-in children's matrices of modes [K0, D) in LDS, compact:
@@ -1367,6 +1146,7 @@ __global__ void __launch_bounds__(kThreads)
   extern __shared__ unsigned char smem_raw[];
   C* x = reinterpret_cast<C*>(smem_raw);
   const int2 u = units[blockIdx.x];
+  if (u.x < 0) return;  // padding of the XCD-grouped unit list (whole workgroup)
   const int pair = u.x, r0 = u.y;
   const int* m = meta + pair * kPairMeta;
   const int RT = m[0], RS = m[1], RTp = m[2];
@@ -1870,6 +1650,7 @@ __global__ void __launch_bounds__(kThreads)
   using P = typename OtfPoint<KIND>::V;
   extern __shared__ unsigned char smem_raw[];
   const int2 u = units[blockIdx.x];
+  if (u.x < 0) return;  // padding of the XCD-grouped unit list (whole workgroup)
   const int pair = u.x, r0 = u.y;
   const int* m = meta + pair * kPairMeta;
   const int RT = m[0], RS = m[1];
@@ -3441,6 +3222,16 @@ template <class T>
 static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_items, const void* in,
                               void* out, const void* mats, hipStream_t stream, const LaunchCfg& cfg) {
   using C = typename CplxOf<T>::type;
+  if (cfg.alt == 3) {  // flat staging, one right-hand side per workgroup
+    if constexpr (sizeof(T) != 4) {
+      return fail(TB_ERR_UNSUPPORTED, "flat-staged transfer stages are FP32 only");
+    } else {
+      int limit = 0;
+      TB_TRY(lds_limit(&limit));
+      return launch_stage_flat_f32(a, p.d, fanout, n_items, in, out, mats, stream, cfg.split == 1 ? 2 : 1,
+                                   limit);
+    }
+  }
   if (cfg.mfma == 1) return launch_stage_xmfma<T>(p, a, fanout, n_items, in, out, mats, stream, cfg);
   if (cfg.alt == 1 || cfg.alt == 2) {
     if (fanout) return fail(TB_ERR_UNSUPPORTED, "no in-turn variant of the fan-out");
@@ -3971,6 +3762,13 @@ static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout, bool
       out.push_back(c);
     }
   }
+  if (fp32)
+    for (int split : {0, 1}) {  // flat staging, one right-hand side per workgroup
+      LaunchCfg c;
+      c.alt = 3;
+      c.split = split;
+      out.push_back(c);
+    }
   return out;
 }
 
@@ -4352,7 +4150,8 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   if (!(g == 0 || g == 1 || g == 8) || !(q == 0 || q == 1 || q == 2 || q == 4 || q == 8) ||
       cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 9 ||
       cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 2 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1 ||
-      !(cfg->rhs_per_thread == 0 || cfg->rhs_per_thread == 1 || cfg->rhs_per_thread == 4))
+      !(cfg->rhs_per_thread == 0 || cfg->rhs_per_thread == 1 || cfg->rhs_per_thread == 4) ||
+      cfg->flat_stage < 0 || cfg->flat_stage > 1 || (cfg->flat_stage && cfg->fanin_in_turn))
     return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");
   auto& v = p->tuned[{(int)io, nrhs}];
   if ((int)v.size() != nslots) v.assign(nslots, tb::LaunchCfg{});
@@ -4361,7 +4160,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   c.QT = q;
   c.split = cfg->whole_blocks;
   c.core = cfg->core_kernel;
-  c.alt = cfg->fanin_in_turn;
+  c.alt = cfg->flat_stage ? 3 : cfg->fanin_in_turn;
   c.mfma = cfg->transfer_mfma;
   c.V = cfg->rhs_per_thread;
   v[slot] = c;

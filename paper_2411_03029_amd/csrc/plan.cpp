@@ -151,6 +151,33 @@ tb_status set_nudft_points(Plan& p, const double* x) {
   return TB_OK;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  The
+// row panels of one pair share the cache lines where its columns meet and the
+// pair's slice of F, so all panels of a pair go to one XCD: pairs are dealt to
+// the XCD with the fewest panels so far, and the list is interleaved so that
+// entry u runs on XCD u % 8.  Shorter queues are padded with empty units
+// (pair -1), which the kernel skips.
+static std::vector<int2> xcd_grouped(const std::vector<int2>& units) {
+  constexpr int kX = 8;
+  std::vector<std::vector<int2>> q(kX);
+  size_t i = 0;
+  while (i < units.size()) {
+    size_t j = i;
+    while (j < units.size() && units[j].x == units[i].x) ++j;
+    int best = 0;
+    for (int x = 1; x < kX; ++x)
+      if (q[x].size() < q[best].size()) best = x;
+    q[best].insert(q[best].end(), units.begin() + (long)i, units.begin() + (long)j);
+    i = j;
+  }
+  size_t len = 0;
+  for (const auto& v : q) len = std::max(len, v.size());
+  std::vector<int2> out(len * kX, make_int2(-1, 0));
+  for (int x = 0; x < kX; ++x)
+    for (size_t k = 0; k < q[x].size(); ++k) out[k * kX + x] = q[x][k];
+  return out;
+}
+
 tb_status build_core_tables(Plan& p) {
   const int d = p.d;
   p.nT = 1LL << (d * p.Lt);
@@ -193,6 +220,7 @@ tb_status build_core_tables(Plan& p) {
       for (int c0 = 0; c0 < RS; c0 += 256) p.mfma_adj_units.push_back(make_int2((int)pr, c0));
       for (int c0 = 0; c0 < RS; c0 += 64) p.adj_units.push_back(make_int2((int)pr, c0));
     }
+  for (auto& v : p.fwd_units) v = xcd_grouped(v);
   p.core_total = off;
   p.col_total = cols;
   TB_TRY(upload(p, &p.pair_meta_d, p.pair_meta));

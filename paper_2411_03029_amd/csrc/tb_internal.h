@@ -99,7 +99,8 @@ struct LaunchCfg {
   int core = 0;   // core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = FP32 MFMA;
                   // 4 = BF16 MFMA (BF16 cores); 5-7 = BF16 MFMA, second form (three
                   // tiles); 8, 9 = adjoint vector kernel, 16-lane column groups, 1 / 4 RHS
-  int alt = 0;    // fan-in: 1 = children in turn, mode 0 in registers
+  int alt = 0;    // fan-in: 1 = children in turn, mode 0 in registers; 2 = children in
+                  // turn, mode 0 first; fan-out or fan-in, FP32: 3 = flat staging
   int mfma = 0;   // transfer levels: 1 = mode products on the matrix cores
   int V = 0;      // transfer: right-hand sides per thread (1 or 4; 4 needs QT >= 4)
 };
