@@ -47,6 +47,11 @@
  *                (a, b, den) = (3, 1, 100) unless set.
  *            Non-uniform DFT, type 2 (section 4.3, d = 2, 3): K = exp(2 pi i x.y),
  *              y = j/n, x_k = X[k][i_k] from tb_options.nudft_x.
+ *            Uniform DFT (section 4.3, d = 2 .. 6): K = exp(2 pi i br(i).br(j)/n),
+ *              the bit-reversal ordering of every mode; phase exact in integers.
+ *            Applies with d > 3 run FP64 or FP32 with stored cores, on kernels
+ *            generic in the number of modes (no autotuning, no on-the-fly or
+ *            compressed cores).
  */
 #ifndef TB_H
 #define TB_H
@@ -72,8 +77,12 @@ typedef enum {
   TB_KERNEL_FOURIER = 0,
   TB_KERNEL_HELMHOLTZ = 1,
   TB_KERNEL_RADON = 2,
-  TB_KERNEL_NUDFT = 3   /* type-2 non-uniform DFT, section 4.3: K = exp(2 pi i x.y),
+  TB_KERNEL_NUDFT = 3,  /* type-2 non-uniform DFT, section 4.3: K = exp(2 pi i x.y),
                            y = j/n, x_k = X[k][i_k] from tb_options.nudft_x */
+  TB_KERNEL_DFT = 4     /* uniform DFT of section 4.3, d = 2 .. 6: K = exp(2 pi i x.y)
+                           with x = br(i), y = br(j)/n per mode, br reversing the
+                           log2(n) bits (the bit-reversal ordering of each
+                           dimension); n a power of two */
 } tb_kernel;
 
 /* Element type of the apply.  TB_C128: complex128 arrays, FP64 factors,
@@ -156,7 +165,8 @@ typedef struct {
 } tb_plan_info_t;
 
 /* Build the factorisation on the GPU (Algorithm 1).
- *   kind, d:  operator, d in {2, 3} for every kind.  Fourier: K =
+ *   kind, d:  operator, d in {2, 3} for every kind; also 4 .. 6 for
+ *             TB_KERNEL_DFT.  Fourier: K =
  *             exp(-2 pi i x.k), x = i/n, k = j - n/2 (section 4.3).
  *             Helmholtz: exp(+i omega rho)/rho; d = 3 two unit cubes with
  *             centres 2 apart along x1, d = 2 two parallel facing unit

@@ -92,8 +92,10 @@ def proxies(lo: int, length: int, p: int) -> np.ndarray:
 
 def default_proxy_counts(d: int, leaf: int) -> tuple:
     """(p_pair, p_other) used when none are given: the paired mode takes
-    p_pair samples per ID column, every other mode p_other samples."""
-    return 2, (4 * leaf if d == 2 else 4)
+    p_pair samples per ID column, every other mode p_other samples (an ID's
+    unfolding has 2d - 1 sampled modes, so p_other shrinks with d: 4 leaf
+    for d = 2, 4 for d = 3, 2 from d = 4 on)."""
+    return 2, (4 * leaf if d == 2 else (4 if d == 3 else 2))
 
 
 DEFAULT_ID_TOL_SCALE = 0.3

@@ -20,7 +20,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .kernels import FOURIER, HELMHOLTZ, Operator
+from .kernels import DFT, FOURIER, HELMHOLTZ, Operator, bit_reverse
 
 
 def grid_indices(n: int, d: int) -> np.ndarray:
@@ -96,6 +96,41 @@ def adjoint_fourier_fft(n: int, d: int, g: np.ndarray) -> np.ndarray:
     return np.fft.fftshift(np.fft.ifftn(g, axes=axes), axes=axes) * float(n) ** d
 
 
+def apply_dft_fft(op: Operator, f: np.ndarray) -> np.ndarray:
+    """Uniform DFT of section 4.3 by FFT: with the grids in natural order
+    u = n^d ifftn(f); the bit-reversal ordering permutes each mode of the
+    input before and of the output after (the permutation is its own
+    inverse)."""
+    n, d = op.n, op.d
+    f = _as_batch(f, n, d)
+    axes = tuple(range(1, d + 1))
+    if op.bitrev:
+        perm = bit_reverse(np.arange(n), n)
+        for ax in axes:
+            f = np.take(f, perm, axis=ax)
+    u = np.fft.ifftn(f, axes=axes) * float(n) ** d
+    if op.bitrev:
+        for ax in axes:
+            u = np.take(u, perm, axis=ax)
+    return u
+
+
+def adjoint_dft_fft(op: Operator, g: np.ndarray) -> np.ndarray:
+    """v_j = sum_i conj(K(i, j)) g_i = fftn of g in natural order."""
+    n, d = op.n, op.d
+    g = _as_batch(g, n, d)
+    axes = tuple(range(1, d + 1))
+    if op.bitrev:
+        perm = bit_reverse(np.arange(n), n)
+        for ax in axes:
+            g = np.take(g, perm, axis=ax)
+    v = np.fft.fftn(g, axes=axes)
+    if op.bitrev:
+        for ax in axes:
+            v = np.take(v, perm, axis=ax)
+    return v
+
+
 def _helmholtz_difference_kernel(op: Operator) -> np.ndarray:
     """h[delta] = K(x_i, y_j) for delta = i - j in (-n, n)^d, stored on a
     (2n)^d periodic grid (negative offsets wrapped)."""
@@ -148,6 +183,8 @@ def apply_exact(op: Operator, f: np.ndarray) -> np.ndarray:
         return apply_fourier_fft(op.n, op.d, f)
     if op.kind == HELMHOLTZ:
         return apply_helmholtz_fft(op, f)
+    if op.kind == DFT:
+        return apply_dft_fft(op, f)
     return apply_brute(op, f)
 
 
@@ -156,6 +193,8 @@ def adjoint_exact(op: Operator, g: np.ndarray) -> np.ndarray:
         return adjoint_fourier_fft(op.n, op.d, g)
     if op.kind == HELMHOLTZ:
         return adjoint_helmholtz_fft(op, g)
+    if op.kind == DFT:
+        return adjoint_dft_fft(op, g)
     return adjoint_brute(op, g)
 
 

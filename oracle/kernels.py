@@ -30,6 +30,11 @@ radon      K = exp(2 pi i phi(x, k)), x = i/n, k = j - n/2 (section 4.2).
            d = 3: phi = x.k + c(x)|k|,
            c = (a + b sin(2 pi x1) sin(2 pi x2) sin(2 pi x3))/den with the
            paper's a=3, b=1, den=100 as the default.
+dft        K = exp(2 pi i x.y), the uniform DFT of section 4.3 (any d): x = i,
+           y = j/n, with the bit-reversal ordering for each dimension: the
+           multi-index i_k stands for the grid point br(i_k), br reversing
+           the log2(n) bits (bitrev=False keeps the natural order).  The
+           phase br(i).br(j)/n is reduced exactly in integers modulo n.
 nudft      K = exp(2 pi i x.y), the type-2 non-uniform DFT of section 4.3:
            y = j/n and x_k = X[k][i_k], with X[k] n given coordinates in
            [0, n - 1] per mode (random in the paper; passed in here, sorted
@@ -46,8 +51,10 @@ FOURIER = 0
 HELMHOLTZ = 1
 RADON = 2
 NUDFT = 3
+DFT = 4
 
-KIND_NAMES = {FOURIER: "fourier", HELMHOLTZ: "helmholtz", RADON: "radon", NUDFT: "nudft"}
+KIND_NAMES = {FOURIER: "fourier", HELMHOLTZ: "helmholtz", RADON: "radon", NUDFT: "nudft",
+              DFT: "dft"}
 
 
 @dataclass(frozen=True)
@@ -62,6 +69,7 @@ class Operator:
     radon_b: float | None = None  # None: (2, 1, 3) for d = 2, (3, 1, 100)
     radon_den: float | None = None  # for d = 3
     nudft_x: tuple | None = None  # NUDFT target coordinates, d tuples of n
+    bitrev: bool = True         # DFT: bit-reversal ordering of both grids
 
     def __post_init__(self):
         if self.nudft_x is not None:
@@ -85,6 +93,8 @@ class Operator:
                                  self.radon_den)
         if self.kind == NUDFT:
             return nudft_entries(self.n, np.asarray(self.nudft_x), ti, sj)
+        if self.kind == DFT:
+            return dft_entries(self.n, ti, sj, self.bitrev)
         raise ValueError(f"unknown kernel kind {self.kind}")
 
 
@@ -158,3 +168,24 @@ def nudft_entries(n: int, xs: np.ndarray, ti: np.ndarray, sj: np.ndarray) -> np.
     for k in range(d):
         phase = phase + xs[k][ti[..., k]] * sj[..., k].astype(np.float64) / n
     return np.exp(2j * np.pi * np.mod(phase, 1.0))
+
+
+def bit_reverse(i: np.ndarray, n: int) -> np.ndarray:
+    """Reverse the log2(n) low bits of each index (n a power of two)."""
+    bits = int(n).bit_length() - 1
+    if (1 << bits) != n:
+        raise ValueError("bit-reversal ordering needs n a power of two")
+    i = np.asarray(i, dtype=np.int64)
+    out = np.zeros_like(i)
+    for b in range(bits):
+        out |= ((i >> b) & 1) << (bits - 1 - b)
+    return out
+
+
+def dft_entries(n: int, ti: np.ndarray, sj: np.ndarray, bitrev: bool = True) -> np.ndarray:
+    # x = i, y = j/n per mode (after the bit-reversal ordering): the phase
+    # x.y = (sum_k x_k y_k n)/n is an integer over n, reduced modulo n
+    x = bit_reverse(ti, n) if bitrev else np.asarray(ti, dtype=np.int64)
+    y = bit_reverse(sj, n) if bitrev else np.asarray(sj, dtype=np.int64)
+    p = np.sum(x * y, axis=-1) % n
+    return np.exp(2j * np.pi * (p.astype(np.float64) / n))

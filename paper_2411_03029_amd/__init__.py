@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import TBError
 
 KINDS = {"fourier": _lib.TB_KERNEL_FOURIER, "helmholtz": _lib.TB_KERNEL_HELMHOLTZ,
-         "radon": _lib.TB_KERNEL_RADON, "nudft": _lib.TB_KERNEL_NUDFT}
+         "radon": _lib.TB_KERNEL_RADON, "nudft": _lib.TB_KERNEL_NUDFT, "dft": _lib.TB_KERNEL_DFT}
 DTYPES = {"c128": _lib.TB_C128, "c64": _lib.TB_C64, "cbf16": _lib.TB_CBF16,
           "c64otf": _lib.TB_C64_OTF, "cq16": _lib.TB_CQ16}
 STORE = {"c128": _lib.TB_STORE_C128, "c64": _lib.TB_STORE_C64,
@@ -229,7 +229,8 @@ def construct(kind, d: int, n: int, tol: float, omega: float | None = None,
               stream=None, **opts) -> Plan:
     """Build the butterfly of operator ``kind`` on the GPU (Algorithm 1).
 
-    ``kind``: "fourier", "helmholtz", "radon" or "nudft".  ``omega`` defaults
+    ``kind``: "fourier", "helmholtz", "radon", "nudft" or "dft" (the uniform
+    DFT with the bit-reversal ordering, d = 2 .. 6).  ``omega`` defaults
     to 4 points per wavelength for Helmholtz.  Options: leaf, lt, proxy_pair,
     proxy_other, id_tol_scale, store (tuple of "c128"/"c64"/"cbf16"/"cq16"/
     "otf"), max_rank, max_device_bytes, radon=(a, b, den), nudft_x (the

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libtb.so")
 
 TB_OK, TB_ERR_INVALID_ARG, TB_ERR_UNSUPPORTED, TB_ERR_OOM, TB_ERR_HIP, \
     TB_ERR_NUMERIC, TB_ERR_IO = range(7)
-TB_KERNEL_FOURIER, TB_KERNEL_HELMHOLTZ, TB_KERNEL_RADON, TB_KERNEL_NUDFT = range(4)
+TB_KERNEL_FOURIER, TB_KERNEL_HELMHOLTZ, TB_KERNEL_RADON, TB_KERNEL_NUDFT, TB_KERNEL_DFT = range(5)
 TB_C128, TB_C64, TB_CBF16, TB_C64_OTF, TB_CQ16 = range(5)
 TB_STORE_C128, TB_STORE_C64, TB_STORE_CBF16, TB_STORE_OTF, TB_STORE_CQ16 = 1, 2, 4, 8, 16
 

@@ -1154,7 +1154,7 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     rt[k] = m[3 + k];
-    rs[k] = m[6 + k];
+    rs[k] = m[kMetaRs + k];
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
@@ -1278,7 +1278,7 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     rt[k] = m[3 + k];
-    rs[k] = m[6 + k];
+    rs[k] = m[kMetaRs + k];
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
@@ -1405,7 +1405,7 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     rt[k] = m[3 + k];
-    rs[k] = m[6 + k];
+    rs[k] = m[kMetaRs + k];
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
@@ -1658,7 +1658,7 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     rt[k] = m[3 + k];
-    rs[k] = m[6 + k];
+    rs[k] = m[kMetaRs + k];
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
@@ -1741,7 +1741,7 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     rt[k] = m[3 + k];
-    rs[k] = m[6 + k];
+    rs[k] = m[kMetaRs + k];
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
@@ -1858,7 +1858,7 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     rt[k] = m[3 + k];
-    rs[k] = m[6 + k];
+    rs[k] = m[kMetaRs + k];
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
@@ -1945,7 +1945,7 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     rt[k] = m[3 + k];
-    rs[k] = m[6 + k];
+    rs[k] = m[kMetaRs + k];
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
@@ -2063,7 +2063,7 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     rt[k] = m[3 + k];
-    rs[k] = m[6 + k];
+    rs[k] = m[kMetaRs + k];
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
@@ -2163,7 +2163,7 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     rt[k] = m[3 + k];
-    rs[k] = m[6 + k];
+    rs[k] = m[kMetaRs + k];
   }
   const long long t = pair / a.nS, s = pair % a.nS;
   const long long sitem = s * a.nT + t, titem = t * a.nS + s;
@@ -2292,8 +2292,8 @@ __global__ void __launch_bounds__(kThreads)
   int mr[D], kr[D], MR[D], KR[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    mr[k] = ADJ ? m[6 + k] : m[3 + k];
-    kr[k] = ADJ ? m[3 + k] : m[6 + k];
+    mr[k] = ADJ ? m[kMetaRs + k] : m[3 + k];
+    kr[k] = ADJ ? m[3 + k] : m[kMetaRs + k];
     MR[k] = ADJ ? a.Rs[k] : a.Rt[k];
     KR[k] = ADJ ? a.Rt[k] : a.Rs[k];
   }
@@ -3448,6 +3448,8 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
 // 1 or 2 picks 1 or 4 right-hand sides per pass.
 static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const void* in, void* out,
                                  hipStream_t stream, const LaunchCfg& cfg) {
+  if (p.kind == TB_KERNEL_DFT)
+    return fail(TB_ERR_UNSUPPORTED, "no on-the-fly cores for the bit-reversed uniform DFT");
   const int d = p.d;
   const Level& st = p.src[p.Lt];
   const Level& tt = p.tgt[p.Ls];
@@ -3602,14 +3604,111 @@ static tb_status build_steps(Plan& p, const void* in, void* out, long long nrhs,
 
 static int steps_per_direction(const Plan& p) { return p.Lt + p.Ls + 3; }
 
+// The same sequence for d above the tuned kernels' 3 modes, on the generic
+// kernels (apply_generic.hip): FP64 or FP32 with stored cores.  The stage
+// scratch follows the level buffers in the workspace.
+template <class T>
+static tb_status build_steps_generic(Plan& p, const void* in, void* out, long long nrhs, bool adjoint,
+                                     const void* cores, hipStream_t stream, std::vector<Step>* steps,
+                                     void* ws_ext, size_t ws_cap) {
+  using C = typename CplxOf<T>::type;
+  const size_t esz = sizeof(C);
+  const bool fp64 = sizeof(T) == 8;
+  Buffers b = layout(p, nrhs, esz);
+  const int rhs = (int)nrhs;
+  const int d = p.d;
+  size_t scr = 0;
+  auto scratch_of = [&](const Level& lv, const Level* coarse, bool source, bool fanout, int n_items) {
+    StageArgs a = stage_args(p, lv, coarse, source, rhs, false);
+    scr = std::max(scr, gen_stage_scratch(a, d, fanout, n_items, esz));
+  };
+  for (int l = 0; l <= p.Lt; ++l) {
+    scratch_of(p.src[l], l ? &p.src[l - 1] : nullptr, true, true, p.src[l].nitems);
+    scratch_of(p.src[l], l ? &p.src[l - 1] : nullptr, true, false, l ? p.src[l - 1].nitems : p.src[l].nitems);
+  }
+  for (int l = 0; l <= p.Ls; ++l) {
+    scratch_of(p.tgt[l], l ? &p.tgt[l - 1] : nullptr, false, true, p.tgt[l].nitems);
+    scratch_of(p.tgt[l], l ? &p.tgt[l - 1] : nullptr, false, false, l ? p.tgt[l - 1].nitems : p.tgt[l].nitems);
+  }
+  const size_t scr_off = (b.total + 255) / 256 * 256;
+  const size_t total = scr_off + scr;
+  if (ws_ext) {
+    if (total > ws_cap)
+      return fail(TB_ERR_OOM, "apply needs " + std::to_string(total) +
+                                  " bytes of workspace; the allocation-free scratch holds " +
+                                  std::to_string(ws_cap));
+  } else {
+    TB_TRY(ensure_workspace(p, total));
+  }
+  char* ws = static_cast<char*>(ws_ext ? ws_ext : p.ws.base);
+  void* scratch = ws + scr_off;
+  auto S = [ws, b](int l) { return (void*)(ws + b.src_off[l]); };
+  auto Tb = [ws, b](int l) { return (void*)(ws + b.tgt_off[l]); };
+  auto mats = [](const Level& lv) -> const void* {
+    return sizeof(T) == 8 ? (const void*)lv.X64 : (const void*)lv.X32;
+  };
+  Plan* pp = &p;
+  auto stage = [&](int id, const Level& lv, const Level* coarse, bool source, bool conj, bool fanout,
+                   int n_items, const void* src, void* dst) {
+    StageArgs a = stage_args(p, lv, coarse, source, rhs, conj);
+    const void* m = mats(lv);
+    steps->push_back({id, false, fanout, [=](const LaunchCfg&) {
+                        return launch_gen_stage(fp64, a, d, fanout, n_items, src, dst, m, scratch, stream);
+                      }});
+  };
+  GenCoreArgs g{};
+  g.d = d;
+  g.nrhs = rhs;
+  g.nS = p.nS;
+  g.nT = p.nT;
+  g.Es = p.src[p.Lt].E;
+  g.Et = p.tgt[p.Ls].E;
+  for (int k = 0; k < d; ++k) {
+    g.Rs[k] = p.src[p.Lt].R[k];
+    g.Rt[k] = p.tgt[p.Ls].R[k];
+  }
+  auto core = [&](bool adj, const void* src, void* dst) {
+    steps->push_back({adj ? TB_STAGE_CORE_ADJ : TB_STAGE_CORE, true, false, [=](const LaunchCfg&) {
+                        return launch_gen_core(fp64, g, adj, cores, pp->core_off_d, pp->pair_meta_d,
+                                               pp->npairs, src, dst, stream);
+                      }});
+  };
+  steps->clear();
+  if (!adjoint) {
+    for (int l = 0; l <= p.Lt; ++l)
+      stage(l ? TB_STAGE_SRC_TRANSFER : TB_STAGE_SRC_LEAF, p.src[l], l ? &p.src[l - 1] : nullptr, true,
+            false, true, p.src[l].nitems, l ? S(l - 1) : in, S(l));
+    core(false, S(p.Lt), Tb(p.Ls));
+    for (int l = p.Ls; l >= 0; --l)
+      stage(l ? TB_STAGE_TGT_TRANSFER : TB_STAGE_TGT_LEAF, p.tgt[l], l ? &p.tgt[l - 1] : nullptr, false,
+            false, false, l ? p.tgt[l - 1].nitems : p.tgt[l].nitems, Tb(l), l ? Tb(l - 1) : out);
+  } else {
+    for (int l = 0; l <= p.Ls; ++l)
+      stage(l ? TB_STAGE_TGT_TRANSFER_ADJ : TB_STAGE_TGT_LEAF_ADJ, p.tgt[l], l ? &p.tgt[l - 1] : nullptr,
+            false, true, true, p.tgt[l].nitems, l ? Tb(l - 1) : in, Tb(l));
+    core(true, Tb(p.Ls), S(p.Lt));
+    for (int l = p.Lt; l >= 0; --l)
+      stage(l ? TB_STAGE_SRC_TRANSFER_ADJ : TB_STAGE_SRC_LEAF_ADJ, p.src[l], l ? &p.src[l - 1] : nullptr,
+            true, true, false, l ? p.src[l - 1].nitems : p.src[l].nitems, S(l), l ? S(l - 1) : out);
+  }
+  return TB_OK;
+}
+
 // With a caller workspace (ws_ext) no event is recorded: per-stage timing
 // creates events, and that path promises to allocate nothing.
 template <class T, class CS>
 static tb_status apply_typed(Plan& p, tb_dtype io, const void* in, void* out, long long nrhs, bool adjoint,
                              const void* cores, hipStream_t stream, void* ws_ext, size_t ws_cap) {
   std::vector<Step> steps;
-  const tb_status built = build_steps<T, CS>(p, in, out, nrhs, adjoint, cores, stream, &steps,
-                                             io == TB_C64_OTF, ws_ext, ws_cap);
+  tb_status built;
+  if (p.d > kMaxDTuned) {
+    if (io != TB_C128 && io != TB_C64)
+      return fail(TB_ERR_UNSUPPORTED, "d > 3 applies run in FP64 or FP32 with stored cores");
+    built = build_steps_generic<T>(p, in, out, nrhs, adjoint, cores, stream, &steps, ws_ext, ws_cap);
+  } else {
+    built = build_steps<T, CS>(p, in, out, nrhs, adjoint, cores, stream, &steps, io == TB_C64_OTF, ws_ext,
+                               ws_cap);
+  }
   TB_TRY(built);
   const auto it = p.tuned.find({(int)io, nrhs});
   const LaunchCfg none{};
@@ -3717,6 +3816,10 @@ static uint64_t plan_signature(const Plan& p) {
     for (const Level& lv : *side) {
       const long long dims[] = {lv.nitems, lv.nb, lv.R[0], lv.R[1], lv.R[2], lv.A[0], lv.A[1], lv.A[2]};
       h = fnv1a(h, dims, sizeof(dims));
+      for (int k = 3; k < p.d; ++k) {
+        const long long more[] = {lv.R[k], lv.A[k]};
+        h = fnv1a(h, more, sizeof(more));
+      }
       for (const IdRec& id : lv.ids) {
         const int rc[] = {id.r, id.c};
         h = fnv1a(h, rc, sizeof(rc));
@@ -3930,6 +4033,8 @@ tb_status run_autotune(Plan& p, long long nrhs, tb_dtype io, const char* cache, 
   if (nrhs < 1 || nrhs > (1 << 20)) return fail(TB_ERR_INVALID_ARG, "nrhs must be in [1, 2^20]");
   if (!valid_io(io)) return fail(TB_ERR_INVALID_ARG, "unknown tb_dtype");
   if (!has_cores(p, io)) return fail(TB_ERR_INVALID_ARG, "the plan holds no cores of the requested precision");
+  if (p.d > kMaxDTuned)
+    return fail(TB_ERR_UNSUPPORTED, "d > 3 applies have one launch shape (nothing to tune)");
   int count = 0;
   const uint64_t sig = plan_signature(p);
   const size_t nslots = 2 * (size_t)steps_per_direction(p);

@@ -58,6 +58,20 @@ __device__ double2 entry(const KernelSpec& ks, const int* ti, const int* sj) {
     sincospi(-2.0 * (double)p / (double)ks.n, &s, &c);
     return make_double2(c, s);
   }
+  if (ks.kind == TB_KERNEL_DFT) {
+    // exp(2 pi i br(i).br(j)/n): the bit-reversed indices' product is
+    // reduced exactly modulo the power-of-two n
+    const int bits = 63 - __clzll((unsigned long long)ks.n);
+    unsigned long long p = 0;
+    for (int k = 0; k < ks.d; ++k) {
+      const unsigned long long x = __brev((unsigned)ti[k]) >> (32 - bits);
+      const unsigned long long y = __brev((unsigned)sj[k]) >> (32 - bits);
+      p += x * y;
+    }
+    p &= (unsigned long long)ks.n - 1;
+    sincospi(2.0 * (double)p / (double)ks.n, &s, &c);
+    return make_double2(c, s);
+  }
   if (ks.kind == TB_KERNEL_HELMHOLTZ) {
     // exp(+i omega rho)/rho; d = 3: x = i/n, y = j/n + (2, 0, 0) (cubes);
     // d = 2: x = (i/n, 0), y = (j/n, 1) (parallel plates 1 apart)
@@ -411,7 +425,7 @@ __global__ void __launch_bounds__(256)
       int ti[kMaxD], sj[kMaxD];
       int fr = row, fc = col;
       for (int k = d - 1; k >= 0; --k) {
-        int rt = m[3 + k], rs = m[6 + k];
+        int rt = m[3 + k], rs = m[kMetaRs + k];
         ti[k] = tskel[(titem * d + k) * a.Rt + fr % rt];
         sj[k] = sskel[(sitem * d + k) * a.Rs + fc % rs];
         fr /= rt;
@@ -757,18 +771,21 @@ extern "C" tb_status tb_construct(tb_kernel kind, int d, long long n, double ome
   tb_options o;
   std::memset(&o, 0, sizeof(o));
   if (opt) o = *opt;
-  if (kind < TB_KERNEL_FOURIER || kind > TB_KERNEL_NUDFT)
+  if (kind < TB_KERNEL_FOURIER || kind > TB_KERNEL_DFT)
     return fail(TB_ERR_INVALID_ARG, "unknown kernel kind");
   if (kind == TB_KERNEL_NUDFT && !o.nudft_x)
     return fail(TB_ERR_INVALID_ARG, "the non-uniform DFT needs tb_options.nudft_x");
   if (d < 1 || d > 8) return fail(TB_ERR_INVALID_ARG, "d must be in [1, 8]");
-  if (d < 2 || d > 3)
-    return fail(TB_ERR_UNSUPPORTED, "kernel/dimension pair not built (every kernel has d = 2 and 3)");
+  if (d < 2 || d > (kind == TB_KERNEL_DFT ? kMaxD : 3))
+    return fail(TB_ERR_UNSUPPORTED,
+                "kernel/dimension pair not built (every kernel has d = 2 and 3, the uniform DFT 2 .. 6)");
   if (!(tol > 0.0 && tol < 1.0)) return fail(TB_ERR_INVALID_ARG, "tol must be in (0, 1)");
   if (kind == TB_KERNEL_HELMHOLTZ && !(omega > 0.0)) return fail(TB_ERR_INVALID_ARG, "omega must be > 0");
   const int leaf = o.leaf_size ? o.leaf_size : 8;
   if (leaf < 1 || leaf > 64) return fail(TB_ERR_INVALID_ARG, "leaf_size must be in [1, 64]");
   if (n < leaf || n > (1LL << 20)) return fail(TB_ERR_INVALID_ARG, "n out of range");
+  if (kind == TB_KERNEL_DFT && (n < 2 || (n & (n - 1)) != 0))
+    return fail(TB_ERR_INVALID_ARG, "the bit-reversal ordering needs n a power of two");
   int L = 0;
   while (((long long)leaf << L) < n) ++L;
   if (((long long)leaf << L) != n) return fail(TB_ERR_INVALID_ARG, "n must equal leaf_size * 2^L");
@@ -786,7 +803,7 @@ extern "C" tb_status tb_construct(tb_kernel kind, int d, long long n, double ome
   p.tol = tol;
   p.eps_id = tol * (o.id_tol_scale > 0 ? o.id_tol_scale : 0.3);
   p.proxy_pair = o.proxy_pair == 0 ? 2 : o.proxy_pair;
-  p.proxy_other = o.proxy_other == 0 ? (d == 2 ? 4 * leaf : 4) : o.proxy_other;
+  p.proxy_other = o.proxy_other == 0 ? (d == 2 ? 4 * leaf : (d == 3 ? 4 : 2)) : o.proxy_other;
   if (o.radon_custom) {
     p.ra = o.radon_a;
     p.rb = o.radon_b;

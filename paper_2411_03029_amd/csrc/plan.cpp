@@ -202,7 +202,7 @@ tb_status build_core_tables(Plan& p) {
         int rt = ttop.id((int)(t * p.nS + s), k, 0, d).r;
         int rs = stop.id((int)(s * p.nT + t), k, 0, d).r;
         m[3 + k] = rt;
-        m[6 + k] = rs;
+        m[kMetaRs + k] = rs;
         RT *= rt;
         RS *= rs;
       }
@@ -490,8 +490,10 @@ extern "C" tb_status tb_plan_load(const char* path, const tb_options* opt,
   p.rden = dh[4];
   if (p.d < 2 || p.d > kMaxD || p.L < 0 || p.L > 12 || p.leaf < 1 || p.Lt < 0 ||
       p.Ls < 0 || p.Lt + p.Ls != p.L || ((long long)p.leaf << p.L) != p.n ||
-      p.kind < 0 || p.kind > TB_KERNEL_NUDFT)
+      p.kind < 0 || p.kind > TB_KERNEL_DFT || (p.kind != TB_KERNEL_DFT && p.d > 3))
     return fail(TB_ERR_IO, "plan header is inconsistent");
+  if (p.kind == TB_KERNEL_DFT && (p.n < 2 || (p.n & (p.n - 1)) != 0))
+    return fail(TB_ERR_IO, "a uniform DFT plan needs n a power of two");
   if (p.kind == TB_KERNEL_NUDFT) {
     std::vector<double> x((size_t)p.d * p.n);
     for (double& v : x) v = rd.get<double>();

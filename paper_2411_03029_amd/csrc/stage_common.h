@@ -231,12 +231,27 @@ __device__ __forceinline__ StageBid stage_bid(const StageArgs& a, int QT) {
   return s;
 }
 
-constexpr int kMaxChildren = 1 << kMaxD;
+constexpr int kMaxChildren = 1 << kMaxDTuned;  // fan-in children of the tuned kernels
 
 // Flat-staged transfer stages (stage_flat.hip), FP32, one right-hand side
 // per workgroup; mode 1 = slices for about 1024 workgroups, 2 = whole blocks.
 long long flat_lds_elems(const StageArgs& a, int d, bool fanout, int chunk);
 tb_status launch_stage_flat_f32(StageArgs a, int d, bool fanout, int n_items, const void* in, void* out,
                                 const void* mats, hipStream_t stream, int mode, int lds_limit);
+
+// Generic apply for any number of modes (apply_generic.hip): per-workgroup
+// scratch in global memory, FP64 (fp64) or FP32.
+struct GenCoreArgs {
+  int d, nrhs;
+  long long nS, nT;              // middle multi-sets per side
+  long long Es, Et;              // entries per top-level item (source / target)
+  int Rs[kMaxD], Rt[kMaxD];      // padded ranks of the top levels
+};
+size_t gen_stage_scratch(const StageArgs& a, int d, bool fanout, int n_items, size_t esz);
+tb_status launch_gen_stage(bool fp64, const StageArgs& a, int d, bool fanout, int n_items, const void* in,
+                           void* out, const void* mats, void* scratch, hipStream_t stream);
+tb_status launch_gen_core(bool fp64, const GenCoreArgs& g, bool adjoint, const void* cores,
+                          const long long* core_off, const int* meta, long long npairs, const void* in,
+                          void* out, hipStream_t stream);
 
 }  // namespace tb

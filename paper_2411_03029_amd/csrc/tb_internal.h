@@ -15,7 +15,8 @@
 
 namespace tb {
 
-constexpr int kMaxD = 3;          // modes handled by the kernels
+constexpr int kMaxD = 6;          // modes handled by the construction and the generic apply
+constexpr int kMaxDTuned = 3;     // modes handled by the tuned apply kernels
 constexpr int kMaxCols = 88;      // widest ID (columns) the GPU QR accepts
 
 using cd = std::complex<double>;
@@ -64,11 +65,11 @@ struct IdRec {
 //        right-hand side innermost.
 struct Level {
   int l = 0, nitems = 0, nb = 1;
-  int R[kMaxD] = {0, 0, 0};
-  int A[kMaxD] = {0, 0, 0};
+  int R[kMaxD] = {};
+  int A[kMaxD] = {};
   std::vector<IdRec> ids;  // [item][k][blk]
   long long mat_item_stride = 0;        // complex elements per item
-  long long mat_k_off[kMaxD] = {0, 0, 0};
+  long long mat_k_off[kMaxD] = {};
   long long E = 0;                      // entries per item tensor
   double2* X64 = nullptr;
   float2* X32 = nullptr;
@@ -78,8 +79,10 @@ struct Level {
   }
 };
 
-// Per-pair metadata for the cores, device side: RT, RS, RTp, rt[3], rs[3].
-constexpr int kPairMeta = 9;
+// Per-pair metadata for the cores, device side: RT, RS, RTp, rt[kMaxD] (at
+// 3), rs[kMaxD] (at kMetaRs).
+constexpr int kMetaRs = 3 + kMaxD;
+constexpr int kPairMeta = 3 + 2 * kMaxD;
 
 struct StageEvent {
   int stage;

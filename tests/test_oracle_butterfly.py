@@ -312,3 +312,54 @@ def test_radon3_ranks_follow_table3_trend():
     off = _offsets([row[2] for row in rows], ours)
     assert max(off) - min(off) <= 1, (ours, off)
     assert all(b >= a for a, b in zip(ours, ours[1:])) and ours[-1] > ours[0]
+
+
+# ----------------------------------------- uniform DFT, d = 4 .. 6 (§4.3) --
+
+@pytest.mark.parametrize("d,n,leaf", [(4, 8, 4), (4, 16, 4), (5, 8, 4), (6, 4, 4)])
+def test_highd_dft_butterfly_is_exact(d, n, leaf):
+    # With the bit-reversal ordering a node pair of the DFT is a block
+    # exp(2 pi i (c + 2^l a)(c' + 2^(L-l) b)/n) whose a-b factor
+    # exp(2 pi i a b/C_b) is periodic with period C_b in a and b: every
+    # unfolding has rank at most the leaf size, so the IDs are exact and the
+    # butterfly reproduces the operator (checked against the FFT route,
+    # forward and adjoint), with every rank at most the leaf size.
+    op = Operator(kernels.DFT, d, n)
+    plan = bf.construct(op, 1e-3, leaf=leaf)
+    assert int(plan.ranks().max()) <= leaf
+    f = _rand((2,) + (n,) * d, 40)
+    assert _relerr(bf.apply(plan, f), dense.apply_dft_fft(op, f)) <= 1e-12
+    assert _relerr(bf.apply_adjoint(plan, f), dense.adjoint_dft_fft(op, f)) <= 1e-12
+
+
+def test_highd_dft_factors_equal_one_dimensional_ids():
+    # Section 3.3: separability again; each source-side ID of the d = 4 DFT
+    # equals the ID of the 1-D block exp(2 pi i br(x) br(y)/n) over the paired
+    # mode's proxies and the ID's columns.
+    d, n, leaf = 4, 16, 4
+    plan = bf.construct(Operator(kernels.DFT, d, n), 1e-3, leaf=leaf)
+    eps = plan.eps_id
+    checked = 0
+    for l, lev in enumerate(plan.src):
+        for (s_flat, tau_flat), per_k in lev.items():
+            tau = bf.unflatten(tau_flat, l, d)
+            for k in range(d):
+                for nu, sk in enumerate(per_k[k]):
+                    if l == 0:
+                        s = bf.unflatten(s_flat, plan.Ls, d)
+                        nu_abs = s[k] * (1 << plan.Lt) + nu
+                        cols = np.arange(nu_abs * leaf, (nu_abs + 1) * leaf)
+                    else:
+                        ptau = bf.flatten([b >> 1 for b in tau], l - 1)
+                        par = plan.src[l - 1][(s_flat, ptau)][k]
+                        cols = np.concatenate([par[2 * nu].skel, par[2 * nu + 1].skel])
+                    lo, ln = bf.node_range(l, tau[k], n)
+                    x = kernels.bit_reverse(bf.proxies(lo, ln, 2 * len(cols)), n)
+                    y = kernels.bit_reverse(cols, n)
+                    B = np.exp(2j * np.pi * (np.outer(x, y) % n) / n)
+                    ref = column_id(B, eps)
+                    assert ref.rank == sk.rank
+                    assert list(cols[ref.skel]) == list(sk.skel)
+                    np.testing.assert_allclose(ref.X, sk.X, atol=1e-8)
+                    checked += 1
+    assert checked > 0

@@ -333,3 +333,60 @@ def test_radon3_speed_at_quarter_points():
     op3 = Operator(kernels.RADON, 3, n, radon_a=2.0, radon_b=1.0, radon_den=3.0)
     assert op3.entries(np.array([[4, 4, 4]]), np.array([h + k]))[0] == pytest.approx(
         -1j, abs=1e-12)
+
+
+# ------------------------------------------------------- uniform DFT, any d --
+# section 4.3: K = exp(2 pi i x.y), x = i, y = j/n, bit-reversal ordering
+
+def test_bit_reversal_values_and_involution():
+    np.testing.assert_array_equal(kernels.bit_reverse(np.arange(8), 8), [0, 4, 2, 6, 1, 5, 3, 7])
+    for n in (2, 4, 16, 64):
+        i = np.arange(n)
+        np.testing.assert_array_equal(kernels.bit_reverse(kernels.bit_reverse(i, n), n), i)
+    with pytest.raises(ValueError):
+        kernels.bit_reverse(np.arange(6), 6)
+
+
+@pytest.mark.parametrize("d,n,bitrev", [(2, 8, True), (2, 8, False), (3, 4, True), (4, 4, True),
+                                        (5, 2, True)])
+def test_dft_fft_equals_brute(d, n, bitrev):
+    op = Operator(kernels.DFT, d, n, bitrev=bitrev)
+    f = _rand((2,) + (n,) * d, 21)
+    np.testing.assert_allclose(dense.apply_dft_fft(op, f), dense.apply_brute(op, f),
+                               rtol=0, atol=1e-10)
+    np.testing.assert_allclose(dense.adjoint_dft_fft(op, f), dense.adjoint_brute(op, f),
+                               rtol=0, atol=1e-10)
+
+
+def test_dft_plane_waves_and_special_values():
+    # a unit impulse at source j0 gives exp(2 pi i br(i).br(j0)/n); j0 = 0
+    # gives the constant 1; the natural order is the plain n^d ifftn
+    n, d = 8, 3
+    op = Operator(kernels.DFT, d, n)
+    j0 = (1, 6, 3)                      # br = (4, 3, 6)
+    f = np.zeros((n,) * d, complex)
+    f[j0] = 1.0
+    u = dense.apply_dft_fft(op, f)[0]
+    i = dense.grid_indices(n, d)
+    br = np.array([4, 3, 6])
+    expect = np.exp(2j * np.pi * ((kernels.bit_reverse(i, n) @ br) % n) / n).reshape((n,) * d)
+    np.testing.assert_allclose(u, expect, atol=1e-12)
+    assert op.entries(np.array([[5, 2, 7]]), np.zeros((1, 3), np.int64))[0] == pytest.approx(1.0)
+    # at n = 8, br(1) = 4, br(2) = 2, br(6) = 3: the phase br(1) br(2) = 8 is
+    # 0 mod 8 (K = 1), br(1) br(6) = 12 is 4 mod 8 (K = exp(i pi) = -1)
+    assert op.entries(np.array([[1, 0, 0]]), np.array([[2, 0, 0]]))[0] == pytest.approx(1.0)
+    assert op.entries(np.array([[1, 0, 0]]), np.array([[6, 0, 0]]))[0] == pytest.approx(-1.0)
+    nat = Operator(kernels.DFT, 2, n, bitrev=False)
+    g = _rand((1, n, n), 22)
+    np.testing.assert_allclose(dense.apply_dft_fft(nat, g), np.fft.ifftn(g, axes=(1, 2)) * n * n,
+                               atol=1e-10)
+
+
+@pytest.mark.parametrize("d,n", [(2, 8), (4, 4)])
+def test_dft_dense_adjoint_identity(d, n):
+    op = Operator(kernels.DFT, d, n)
+    f = _rand((1,) + (n,) * d, 23)
+    g = _rand((1,) + (n,) * d, 24)
+    lhs = np.vdot(g, dense.apply_brute(op, f))
+    rhs = np.vdot(dense.adjoint_brute(op, g), f)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
