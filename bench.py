@@ -821,6 +821,12 @@ OPERATOR_TABLE = [
     ("nudft2_n1024", "nudft", 2, 1024, 1e-6, ("c64", "cq16")),
     ("nudft3_n32", "nudft", 3, 32, 1e-3, ("c64", "cq16")),
     ("nudft3_n64", "nudft", 3, 64, 1e-3, ("c64", "cq16")),
+    # the uniform DFT with the bit-reversal ordering, d = 4 .. 6 (generic
+    # kernels, leaf 4: every rank is the leaf size and the butterfly exact)
+    ("dft4_n16", "dft", 4, 16, 1e-3, ("c64",)),
+    ("dft4_n32", "dft", 4, 32, 1e-3, ("c64",)),
+    ("dft5_n8", "dft", 5, 8, 1e-3, ("c64",)),
+    ("dft6_n4", "dft", 6, 4, 1e-3, ("c64",)),
 ]
 
 
@@ -832,7 +838,8 @@ def run_operator_table(args, tb, inputs, torch, np) -> dict:
     is not in --only (comma separated, default all) are skipped."""
     from oracle import dense, kernels
     only = set(args.only.split(",")) if args.only else None
-    kid = {"helmholtz": kernels.HELMHOLTZ, "radon": kernels.RADON, "nudft": kernels.NUDFT}
+    kid = {"helmholtz": kernels.HELMHOLTZ, "radon": kernels.RADON, "nudft": kernels.NUDFT,
+           "dft": kernels.DFT}
     rows = {}
     for label, kind, d, n, tol, stores in OPERATOR_TABLE:
         if only is not None and label not in only:
@@ -842,6 +849,8 @@ def run_operator_table(args, tb, inputs, torch, np) -> dict:
         if kind == "nudft":
             xs = inputs.nudft_points(n, d)
             extra["nudft_x"] = xs
+        if kind == "dft":
+            extra["leaf"] = 4
         print(f"[bench] {label}: construct", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         plan = tb.construct(kind, d, n, tol, store=stores, **extra)
@@ -853,17 +862,22 @@ def run_operator_table(args, tb, inputs, torch, np) -> dict:
         om = kernels.helmholtz_omega(n) if kind == "helmholtz" else 0.0
         op = kernels.Operator(kid[kind], d, n, omega=om, nudft_x=xs)
         sel = np.sort(np.random.default_rng(8).choice(n ** d, 64, replace=False))
-        exact = dense.apply_brute(op, f_host, rows=sel).reshape(-1)
+        if kind == "dft":   # exact route: FFT
+            exact = dense.apply_dft_fft(op, f_host).reshape(-1)[sel]
+        else:
+            exact = dense.apply_brute(op, f_host, rows=sel).reshape(-1)
         row = {"kind": kind, "d": d, "n": n, "tol": tol, "construct_s": round(construct_s, 3),
                "r_min": info["r_min"], "r_max": info["r_max"], "core_entries": info["core_entries"],
                "device_bytes": info["device_bytes"]}
         for st in stores:
             dt = {"c64": "c64", "otf": "c64otf", "cq16": "cq16"}[st]
-            plan.autotune(1, dtype=dt, cache=args.tune_cache)
+            if d <= 3:      # d > 3 has one launch shape
+                plan.autotune(1, dtype=dt, cache=args.tune_cache)
             steps = max(3, min(args.steps, 50))
             t = time_steps(plan, x, dt, steps, 2, torch)
             u = plan.apply(x, dtype=dt).cpu().numpy().astype(np.complex128).reshape(-1)
             row[dt] = {"ms_fwd_adj": round(1e3 * t / steps, 3),
+                       "points_per_s": n ** d * steps / t,
                        "sampled_err": _relerr(u[sel], exact)}
         plan.close()
         torch.cuda.empty_cache()

@@ -3667,10 +3667,15 @@ static tb_status build_steps_generic(Plan& p, const void* in, void* out, long lo
     g.Rs[k] = p.src[p.Lt].R[k];
     g.Rt[k] = p.tgt[p.Ls].R[k];
   }
+  int max_rt = 0, max_rs = 0;
+  for (long long pr = 0; pr < p.npairs; ++pr) {
+    max_rt = std::max(max_rt, p.pair_meta[(size_t)pr * kPairMeta]);
+    max_rs = std::max(max_rs, p.pair_meta[(size_t)pr * kPairMeta + 1]);
+  }
   auto core = [&](bool adj, const void* src, void* dst) {
     steps->push_back({adj ? TB_STAGE_CORE_ADJ : TB_STAGE_CORE, true, false, [=](const LaunchCfg&) {
                         return launch_gen_core(fp64, g, adj, cores, pp->core_off_d, pp->pair_meta_d,
-                                               pp->npairs, src, dst, stream);
+                                               pp->npairs, max_rt, max_rs, src, dst, stream);
                       }});
   };
   steps->clear();

@@ -293,16 +293,37 @@ __device__ __forceinline__ long long padded_pos_rt(int flat, const int* r, const
   return pos;
 }
 
-// forward: G_{t,s} = C F (rows per thread); adjoint: F_{t,s} = C^H G
-// (columns per thread).  Cores column-major, RTp rows per column.
+// forward: G_{t,s} = C F, one workgroup per (pair, panel of kGenThreads
+// rows, right-hand side), a row per thread, the contracted F values (and
+// their padded positions) staged in LDS kGenChunk at a time; adjoint:
+// F_{t,s} = C^H G, one workgroup per (pair, panel of kGenCols columns,
+// right-hand side), a column per wave at a time with the lanes over the
+// rows (coalesced core reads) and a wave reduction, G staged likewise.
+// Cores column-major, RTp rows per column.
+constexpr int kGenChunk = 2048;
+constexpr int kGenCols = 64;
+
+template <class C>
+__device__ __forceinline__ C wave_sum_c(C v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+
 template <class T>
 __global__ void __launch_bounds__(kGenThreads)
-    gen_core(GenCoreArgs g, int adjoint, const typename CplxOf<T>::type* __restrict__ cores,
+    gen_core(GenCoreArgs g, int adjoint, int npanels, const typename CplxOf<T>::type* __restrict__ cores,
              const long long* __restrict__ core_off, const int* __restrict__ meta,
              const typename CplxOf<T>::type* __restrict__ in, typename CplxOf<T>::type* __restrict__ out) {
   using C = typename CplxOf<T>::type;
+  __shared__ C xs[kGenChunk];
   const int q = blockIdx.x % g.nrhs;
-  const int pair = blockIdx.x / g.nrhs;
+  const int rest = blockIdx.x / g.nrhs;
+  const int panel = rest % npanels;
+  const int pair = rest / npanels;
   const int D = g.d;
   const int* m = meta + (long long)pair * kPairMeta;
   const int RT = m[0], RS = m[1], RTp = m[2];
@@ -315,20 +336,45 @@ __global__ void __launch_bounds__(kGenThreads)
   const long long sitem = s * g.nT + t, titem = t * g.nS + s;
   const C* cp = cores + core_off[pair];
   if (!adjoint) {
-    for (int r = threadIdx.x; r < RT; r += kGenThreads) {
-      C acc = czero<C>();
-      for (int b = 0; b < RS; ++b)
-        acc = cfma(acc, cp[(long long)b * RTp + r],
-                   in[(sitem * g.Es + padded_pos_rt(b, rs, g.Rs, D)) * g.nrhs + q]);
-      out[(titem * g.Et + padded_pos_rt(r, rt, g.Rt, D)) * g.nrhs + q] = acc;
+    const int r = panel * kGenThreads + threadIdx.x;
+    if (panel * kGenThreads >= RT) return;  // whole workgroup
+    C acc = czero<C>();
+    for (int b0 = 0; b0 < RS; b0 += kGenChunk) {
+      const int nb = min(kGenChunk, RS - b0);
+      __syncthreads();
+      for (int i = threadIdx.x; i < nb; i += kGenThreads)
+        xs[i] = in[(sitem * g.Es + padded_pos_rt(b0 + i, rs, g.Rs, D)) * g.nrhs + q];
+      __syncthreads();
+      if (r < RT)
+        for (int i = 0; i < nb; ++i) acc = cfma(acc, cp[(long long)(b0 + i) * RTp + r], xs[i]);
     }
+    if (r < RT) out[(titem * g.Et + padded_pos_rt(r, rt, g.Rt, D)) * g.nrhs + q] = acc;
   } else {
-    for (int b = threadIdx.x; b < RS; b += kGenThreads) {
-      C acc = czero<C>();
-      for (int r = 0; r < RT; ++r)
-        acc = cfma_conj(acc, cp[(long long)b * RTp + r],
-                        in[(titem * g.Et + padded_pos_rt(r, rt, g.Rt, D)) * g.nrhs + q]);
-      out[(sitem * g.Es + padded_pos_rt(b, rs, g.Rs, D)) * g.nrhs + q] = acc;
+    const int c0 = panel * kGenCols;
+    if (c0 >= RS) return;  // whole workgroup
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int kWaves = kGenThreads / 64;
+    constexpr int kPer = kGenCols / kWaves;  // columns per wave
+    C acc[kPer];
+    for (int i = 0; i < kPer; ++i) acc[i] = czero<C>();
+    for (int r0 = 0; r0 < RT; r0 += kGenChunk) {
+      const int nr = min(kGenChunk, RT - r0);
+      __syncthreads();
+      for (int i = threadIdx.x; i < nr; i += kGenThreads)
+        xs[i] = in[(titem * g.Et + padded_pos_rt(r0 + i, rt, g.Rt, D)) * g.nrhs + q];
+      __syncthreads();
+      for (int i = 0; i < kPer; ++i) {
+        const int b = c0 + w * kPer + i;
+        if (b >= RS) break;  // wave-uniform
+        const C* col = cp + (long long)b * RTp + r0;
+        for (int r = lane; r < nr; r += 64) acc[i] = cfma_conj(acc[i], col[r], xs[r]);
+      }
+    }
+    for (int i = 0; i < kPer; ++i) {
+      const int b = c0 + w * kPer + i;
+      if (b >= RS) break;
+      const C v = wave_sum_c(acc[i]);
+      if (lane == 0) out[(sitem * g.Es + padded_pos_rt(b, rs, g.Rs, D)) * g.nrhs + q] = v;
     }
   }
 }
@@ -369,16 +415,17 @@ size_t gen_stage_scratch(const StageArgs& a, int d, bool fanout, int n_items, si
 }
 
 tb_status launch_gen_core(bool fp64, const GenCoreArgs& g, bool adjoint, const void* cores,
-                          const long long* core_off, const int* meta, long long npairs, const void* in,
-                          void* out, hipStream_t stream) {
-  const long long nwg = npairs * g.nrhs;
+                          const long long* core_off, const int* meta, long long npairs, int max_rt,
+                          int max_rs, const void* in, void* out, hipStream_t stream) {
+  const int npanels = adjoint ? (max_rs + kGenCols - 1) / kGenCols : (max_rt + kGenThreads - 1) / kGenThreads;
+  const long long nwg = npairs * npanels * g.nrhs;
   if (nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many right-hand sides for one launch");
   if (fp64)
     gen_core<double><<<dim3((unsigned)nwg), kGenThreads, 0, stream>>>(
-        g, adjoint ? 1 : 0, (const double2*)cores, core_off, meta, (const double2*)in, (double2*)out);
+        g, adjoint ? 1 : 0, npanels, (const double2*)cores, core_off, meta, (const double2*)in, (double2*)out);
   else
     gen_core<float><<<dim3((unsigned)nwg), kGenThreads, 0, stream>>>(
-        g, adjoint ? 1 : 0, (const float2*)cores, core_off, meta, (const float2*)in, (float2*)out);
+        g, adjoint ? 1 : 0, npanels, (const float2*)cores, core_off, meta, (const float2*)in, (float2*)out);
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;
 }

@@ -153,22 +153,34 @@ tb_status set_nudft_points(Plan& p, const double* x) {
 
 // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  The
 // row panels of one pair share the cache lines where its columns meet and the
-// pair's slice of F, so all panels of a pair go to one XCD: pairs are dealt to
-// the XCD with the fewest panels so far, and the list is interleaved so that
-// entry u runs on XCD u % 8.  Shorter queues are padded with empty units
-// (pair -1), which the kernel skips.
-static std::vector<int2> xcd_grouped(const std::vector<int2>& units) {
+// pair's slice of F, so all panels of a pair go to one XCD.  Pairs are taken
+// in decreasing order of their bytes (longest first) and each is dealt to the
+// XCD with the fewest bytes so far; the list is interleaved so that entry u
+// runs on XCD u % 8, each XCD's panels in that order.  Shorter queues are
+// padded with empty units (pair -1), which the kernels skip.
+static std::vector<int2> xcd_grouped(const std::vector<int2>& units, const std::vector<long long>& pair_bytes) {
   constexpr int kX = 8;
-  std::vector<std::vector<int2>> q(kX);
+  struct Run {
+    size_t i, j;
+    long long w;
+  };
+  std::vector<Run> runs;
   size_t i = 0;
   while (i < units.size()) {
     size_t j = i;
     while (j < units.size() && units[j].x == units[i].x) ++j;
+    runs.push_back({i, j, pair_bytes[(size_t)units[i].x]});
+    i = j;
+  }
+  std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.w > b.w; });
+  std::vector<std::vector<int2>> q(kX);
+  std::vector<long long> load(kX, 0);
+  for (const Run& r : runs) {
     int best = 0;
     for (int x = 1; x < kX; ++x)
-      if (q[x].size() < q[best].size()) best = x;
-    q[best].insert(q[best].end(), units.begin() + (long)i, units.begin() + (long)j);
-    i = j;
+      if (load[x] < load[best]) best = x;
+    q[best].insert(q[best].end(), units.begin() + (long)r.i, units.begin() + (long)r.j);
+    load[best] += r.w;
   }
   size_t len = 0;
   for (const auto& v : q) len = std::max(len, v.size());
@@ -220,7 +232,12 @@ tb_status build_core_tables(Plan& p) {
       for (int c0 = 0; c0 < RS; c0 += 256) p.mfma_adj_units.push_back(make_int2((int)pr, c0));
       for (int c0 = 0; c0 < RS; c0 += 64) p.adj_units.push_back(make_int2((int)pr, c0));
     }
-  for (auto& v : p.fwd_units) v = xcd_grouped(v);
+  {
+    std::vector<long long> bytes((size_t)p.npairs);
+    for (long long pr = 0; pr < p.npairs; ++pr)
+      bytes[(size_t)pr] = (long long)p.pair_meta[(size_t)pr * kPairMeta + 2] * p.pair_meta[(size_t)pr * kPairMeta + 1];
+    for (auto& v : p.fwd_units) v = xcd_grouped(v, bytes);
+  }
   p.core_total = off;
   p.col_total = cols;
   TB_TRY(upload(p, &p.pair_meta_d, p.pair_meta));

@@ -251,7 +251,7 @@ size_t gen_stage_scratch(const StageArgs& a, int d, bool fanout, int n_items, si
 tb_status launch_gen_stage(bool fp64, const StageArgs& a, int d, bool fanout, int n_items, const void* in,
                            void* out, const void* mats, void* scratch, hipStream_t stream);
 tb_status launch_gen_core(bool fp64, const GenCoreArgs& g, bool adjoint, const void* cores,
-                          const long long* core_off, const int* meta, long long npairs, const void* in,
-                          void* out, hipStream_t stream);
+                          const long long* core_off, const int* meta, long long npairs, int max_rt,
+                          int max_rs, const void* in, void* out, hipStream_t stream);
 
 }  // namespace tb
