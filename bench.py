@@ -472,6 +472,15 @@ def batched_leg(args, tb, inputs, torch, np) -> dict:
     autotune_s = time.perf_counter() - t0
     x = torch.from_numpy(inputs.rhs_batch(n, d, nrhs, config=5)).to("cuda", torch.complex64)
     steps = max(3, min(args.steps, 20))
+    # the same step with the cores evaluated on the fly on the matrix cores
+    plan.autotune(nrhs, dtype="c64otf", cache=args.tune_cache)
+    t_otf = time_steps(plan, x, "c64otf", steps, 2, torch)
+    plan.set_timing(True)
+    time_steps(plan, x, "c64otf", 1, 0, torch)
+    st_otf = _stage_ms(plan)
+    plan.set_timing(False)
+    otf_core_ms = st_otf["core"][0] + st_otf["core_adj"][0]
+    otf_core_flops = _stage_flops(info, "core", nrhs) + _stage_flops(info, "core_adj", nrhs)
     t = time_steps(plan, x, "c64", steps, 2, torch)
     plan.set_timing(True)
     time_steps(plan, x, "c64", 1, 0, torch)
@@ -488,7 +497,13 @@ def batched_leg(args, tb, inputs, torch, np) -> dict:
            "step": "tb_apply + tb_apply_adjoint, complex FP32",
            "whole_step_TFLOPs": round(flops / (t / steps) / 1e12, 2),
            "dominant_stage": dom, "dominant_frac_fp32_mfma": per[dom]["frac_fp32_mfma"],
-           "stages": per, "construct_s": round(construct_s, 3), "autotune_s": round(autotune_s, 3)}
+           "stages": per, "construct_s": round(construct_s, 3), "autotune_s": round(autotune_s, 3),
+           "on_the_fly_cores": {
+               "value": nrhs * n ** d * steps / t_otf, "ms_per_step": 1e3 * t_otf / steps,
+               "core_fwd_adj_ms": round(otf_core_ms, 3),
+               "core_TFLOPs": round(otf_core_flops / (otf_core_ms * 1e-3) / 1e12, 2),
+               "note": "K(tbar,sbar) evaluated inside the matrix-core contraction (FP64 phase, "
+                       "FP32 sin/cos, complex products on FP32 MFMA); 8 flops per entry and RHS"}}
     plan.close()
     torch.cuda.empty_cache()
     return out

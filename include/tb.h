@@ -260,7 +260,8 @@ typedef struct {
   int rhs_tile;           /* transfer stages: right-hand sides per workgroup, 1/2/4/8 */
   int whole_blocks;       /* transfer stages: 1 = one workgroup per block (no slices) */
   int core_kernel;        /* core: 1 = vector, 1 RHS per pass; 2 = vector, 4; 3 = FP32 matrix
-                             cores; 4 = BF16 matrix cores (BF16 applies; right-hand sides split
+                             cores (stored or, for TB_C64_OTF, on-the-fly entries); 4 = BF16
+                             matrix cores (BF16 applies; right-hand sides split
                              into bf16 hi + lo); 5, 6, 7 = BF16 matrix cores, second form, with
                              256 x 32, 128 x 64, 128 x 32 (rows x right-hand sides) per
                              workgroup; 8, 9 = adjoint vector

@@ -2012,6 +2012,202 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// On-the-fly cores on the matrix cores (many right-hand sides): the
+// kernels above with every A fragment evaluated as K(tbar, sbar) from the
+// skeleton points instead of loaded, FP64 phase and FP32 sine and cosine as
+// in the vector on-the-fly kernels.  At nrhs right-hand sides each entry
+// serves nrhs complex products, so its evaluation amortises.
+//
+// Forward: each lane keeps the target points of its kMT rows in registers;
+// the source points of a chunk of kMKC columns are staged in LDS beside F.
+template <int KIND, int D>
+__global__ void __launch_bounds__(kThreads)
+    core_fwd_mfma_otf(CoreArgs a, OtfSpec o, const int* __restrict__ meta, const int2* __restrict__ units,
+                      const int* __restrict__ sskel, const int* __restrict__ tskel,
+                      const float2* __restrict__ F, float2* __restrict__ G) {
+  using P = typename OtfPoint<KIND>::V;
+  __shared__ float2 fs[kMKC * kMQ];
+  __shared__ P sp[kMKC];
+  const int nqt = (a.nrhs + kMQ - 1) / kMQ;
+  const int item = xcd_item(blockIdx.x, gridDim.x, nqt);
+  const int2 u = units[item / nqt];
+  const int pair = u.x, r0 = u.y;
+  const int* m = meta + pair * kPairMeta;
+  const int RT = m[0], RS = m[1];
+  int rt[D], rs[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    rt[k] = m[3 + k];
+    rs[k] = m[kMetaRs + k];
+  }
+  const long long t = pair / a.nS, s = pair % a.nS;
+  const long long sitem = s * a.nT + t, titem = t * a.nS + s;
+  const int q0 = (item % nqt) * kMQ;
+  const int Qa = min(kMQ, a.nrhs - q0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  v4f accr[kMT][2], acci[kMT][2];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      accr[i][c] = v4f{0, 0, 0, 0};
+      acci[i][c] = v4f{0, 0, 0, 0};
+    }
+  bool live[kMT];
+  P tp[kMT];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) {
+    const int tile0 = r0 + (w + 4 * i) * 16;
+    live[i] = tile0 < RT;
+    int ti[D];
+    otf_index<D>(tskel, titem, o.Rt_sk, rt, min(tile0 + (lane & 15), RT - 1), ti);
+    tp[i] = otf_target<KIND, D>(o, ti);
+  }
+  for (int kc = 0; kc < RS; kc += kMKC) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kMKC * kMQ; idx += kThreads) {
+      const int kk = kc + idx / kMQ, q = idx % kMQ;
+      fs[idx] = (kk < RS && q < Qa) ? F[(sitem * a.Es + padded_pos<D>(kk, rs, a.Rs)) * a.nrhs + q0 + q]
+                                    : make_float2(0.f, 0.f);
+    }
+    for (int idx = threadIdx.x; idx < kMKC; idx += kThreads) {
+      int sj[D];  // columns past the pair take the last one's point (their F is zero)
+      otf_index<D>(sskel, sitem, o.Rs_sk, rs, min(kc + idx, RS - 1), sj);
+      sp[idx] = otf_source<KIND, D>(o, sj);
+    }
+    __syncthreads();
+    const int kend = min(kMKC, RS - kc);
+    for (int ks = 0; ks < kend; ks += 4) {
+      const P y = sp[ks + (lane >> 4)];
+      float2 av[kMT];
+#pragma unroll
+      for (int i = 0; i < kMT; ++i) av[i] = otf_entry<KIND, D>(o, tp[i], y);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const float2 bv = fs[(ks + (lane >> 4)) * kMQ + c * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < kMT; ++i)
+          if (live[i]) cmfma(accr[i][c], acci[i][c], av[i], bv);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) {
+    if (!live[i]) continue;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = r0 + (w + 4 * i) * 16 + 4 * (lane >> 4) + j;
+        const int col = c * 16 + (lane & 15);
+        if (row < RT && col < Qa)
+          G[(titem * a.Et + padded_pos<D>(row, rt, a.Rt)) * a.nrhs + q0 + col] =
+              make_float2(accr[i][c][j], acci[i][c][j]);
+      }
+  }
+}
+
+// Adjoint: the source points of the workgroup's 256 columns are staged once,
+// the target points of each 16-row slab beside G, and the slab of entries is
+// evaluated into LDS where the stored-core kernel loads it.
+template <int KIND, int D>
+__global__ void __launch_bounds__(kThreads)
+    core_adj_mfma_otf(CoreArgs a, OtfSpec o, const int* __restrict__ meta, const int2* __restrict__ units,
+                      const int* __restrict__ sskel, const int* __restrict__ tskel,
+                      const float2* __restrict__ G, float2* __restrict__ F) {
+  using P = typename OtfPoint<KIND>::V;
+  constexpr int kCols = 4 * kMT * 16;           // 256
+  constexpr int kLd = kMKA + 1;                 // padded column length in LDS
+  __shared__ float2 cs_[kCols * kLd];
+  __shared__ float2 gs[kMKA * kMQ];
+  __shared__ P sp[kCols];
+  __shared__ P tpl[kMKA];
+  const int nqt = (a.nrhs + kMQ - 1) / kMQ;
+  const int item = xcd_item(blockIdx.x, gridDim.x, nqt);
+  const int2 u = units[item / nqt];
+  const int pair = u.x, c0 = u.y;
+  const int* m = meta + pair * kPairMeta;
+  const int RT = m[0], RS = m[1];
+  int rt[D], rs[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    rt[k] = m[3 + k];
+    rs[k] = m[kMetaRs + k];
+  }
+  const long long t = pair / a.nS, s = pair % a.nS;
+  const long long sitem = s * a.nT + t, titem = t * a.nS + s;
+  const int q0 = (item % nqt) * kMQ;
+  const int Qa = min(kMQ, a.nrhs - q0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int idx = threadIdx.x; idx < kCols; idx += kThreads) {
+    int sj[D];  // columns past the pair take the last one's point (never used)
+    otf_index<D>(sskel, sitem, o.Rs_sk, rs, min(c0 + idx, RS - 1), sj);
+    sp[idx] = otf_source<KIND, D>(o, sj);
+  }
+  v4f accr[kMT][2], acci[kMT][2];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      accr[i][c] = v4f{0, 0, 0, 0};
+      acci[i][c] = v4f{0, 0, 0, 0};
+    }
+  bool live[kMT];
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) live[i] = c0 + (w + 4 * i) * 16 < RS;
+  for (int k0 = 0; k0 < RT; k0 += kMKA) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kMKA; idx += kThreads) {
+      int ti[D];
+      otf_index<D>(tskel, titem, o.Rt_sk, rt, min(k0 + idx, RT - 1), ti);
+      tpl[idx] = otf_target<KIND, D>(o, ti);
+    }
+    for (int idx = threadIdx.x; idx < kMKA * kMQ; idx += kThreads) {
+      const int r = idx / kMQ, q = idx % kMQ;
+      const int gr = k0 + r;
+      gs[idx] = (gr < RT && q < Qa) ? G[(titem * a.Et + padded_pos<D>(gr, rt, a.Rt)) * a.nrhs + q0 + q]
+                                    : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    // slab of entries: rows k0..k0+15 of columns c0..c0+255 (zero past the pair)
+    for (int idx = threadIdx.x; idx < kCols * kMKA; idx += kThreads) {
+      const int col = idx / kMKA, r = idx % kMKA;
+      float2 v = make_float2(0.f, 0.f);
+      if (c0 + col < RS && k0 + r < RT) v = otf_entry<KIND, D>(o, tpl[r], sp[col]);
+      cs_[col * kLd + r] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kMKA; ks += 4) {
+      float2 bv[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) bv[c] = gs[(ks + (lane >> 4)) * kMQ + c * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < kMT; ++i) {
+        if (!live[i]) continue;
+        float2 av = cs_[((w + 4 * i) * 16 + (lane & 15)) * kLd + ks + (lane >> 4)];
+        av.y = -av.y;  // conj(C)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) cmfma(accr[i][c], acci[i][c], av, bv[c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kMT; ++i) {
+    if (!live[i]) continue;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = c0 + (w + 4 * i) * 16 + 4 * (lane >> 4) + j;
+        const int q = c * 16 + (lane & 15);
+        if (col < RS && q < Qa)
+          F[(sitem * a.Es + padded_pos<D>(col, rs, a.Rs)) * a.nrhs + q0 + q] =
+              make_float2(accr[i][c][j], acci[i][c][j]);
+      }
+  }
+}
+
 // BF16 cores on BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32
 // accumulation).  A complex product is one real product per output part
 // with real and imaginary parts interleaved along k: with k' = 2 k + p,
@@ -3445,7 +3641,8 @@ static tb_status launch_core(const Plan& p, bool adjoint, int nrhs, const void* 
 }
 
 // Core contraction with the cores evaluated on the fly (TB_C64_OTF); cfg.core
-// 1 or 2 picks 1 or 4 right-hand sides per pass.
+// 1 or 2 picks the vector kernels with 1 or 4 right-hand sides per pass, 3
+// (the default from kMfmaMinRhs right-hand sides) the FP32 matrix cores.
 static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const void* in, void* out,
                                  hipStream_t stream, const LaunchCfg& cfg) {
   if (p.kind == TB_KERNEL_DFT)
@@ -3477,7 +3674,33 @@ static tb_status launch_core_otf(const Plan& p, bool adjoint, int nrhs, const vo
     maxRT = std::max(maxRT, p.pair_meta[(size_t)pr * kPairMeta]);
     maxRS = std::max(maxRS, p.pair_meta[(size_t)pr * kPairMeta + 1]);
   }
-  if (cfg.core >= 3) return fail(TB_ERR_UNSUPPORTED, "on-the-fly cores take core kernel 1 or 2");
+  if (cfg.core > 3) return fail(TB_ERR_UNSUPPORTED, "on-the-fly cores take core kernel 1, 2 or 3");
+  if (cfg.core == 3 || (cfg.core == 0 && nrhs >= kMfmaMinRhs)) {  // matrix cores
+    if (p.kind == TB_KERNEL_FOURIER && p.n > (1 << 15))
+      return fail(TB_ERR_UNSUPPORTED, "on-the-fly Fourier cores need n <= 32768");
+    const unsigned gy = (unsigned)((nrhs + kMQ - 1) / kMQ);
+    const std::vector<int2>& mu = adjoint ? p.mfma_adj_units : p.mfma_fwd_units;
+    const int2* mu_d = adjoint ? p.mfma_adj_units_d : p.mfma_fwd_units_d;
+    const unsigned grid = (unsigned)(mu.size() * gy);
+    auto go = [&](auto kern) -> tb_status {
+      kern<<<grid, kThreads, 0, stream>>>(a, o, p.pair_meta_d, mu_d, p.top_src_skel_d, p.top_tgt_skel_d,
+                                          (const float2*)in, (float2*)out);
+      TB_HIP_TRY(hipGetLastError());
+      return TB_OK;
+    };
+    auto by_kind = [&](auto kind_tag) -> tb_status {
+      constexpr int K = decltype(kind_tag)::value;
+      if (d == 2) return adjoint ? go(core_adj_mfma_otf<K, 2>) : go(core_fwd_mfma_otf<K, 2>);
+      return adjoint ? go(core_adj_mfma_otf<K, 3>) : go(core_fwd_mfma_otf<K, 3>);
+    };
+    switch (p.kind) {
+      case TB_KERNEL_FOURIER: return by_kind(std::integral_constant<int, TB_KERNEL_FOURIER>{});
+      case TB_KERNEL_HELMHOLTZ: return by_kind(std::integral_constant<int, TB_KERNEL_HELMHOLTZ>{});
+      case TB_KERNEL_NUDFT: return by_kind(std::integral_constant<int, TB_KERNEL_NUDFT>{});
+      case TB_KERNEL_RADON: return by_kind(std::integral_constant<int, TB_KERNEL_RADON>{});
+      default: return fail(TB_ERR_UNSUPPORTED, "no on-the-fly entries for this kernel");
+    }
+  }
   const int QT = (cfg.core == 2 || (cfg.core == 0 && nrhs >= 4)) ? 4 : 1;
   int limit = 0;
   TB_TRY(lds_limit(&limit));
@@ -3897,7 +4120,7 @@ static std::vector<LaunchCfg> core_candidates(long long nrhs, tb_dtype io) {
       out.push_back(c);
     }
   }
-  if (io != TB_C128 && io != TB_C64_OTF && io != TB_CQ16 && nrhs >= 4) {
+  if (io != TB_C128 && io != TB_CQ16 && nrhs >= 4) {  // FP32 matrix cores (stored or on the fly)
     c.core = 3;
     out.push_back(c);
   }

@@ -327,13 +327,14 @@ def test_on_the_fly_cores_match_oracle(name, tmp_path):
     # the cores K(tbar, sbar) evaluated inside the contraction (phase reduced
     # to a fraction of a turn in FP64, sine and cosine in FP32) from the
     # oracle's skeletons: the oracle's apply to the FP32 bound, per RHS, on a
-    # plan that stores no cores at all
+    # plan that stores no cores at all; from 8 right-hand sides on the FP32
+    # matrix cores
     torch = torch_gpu()
     import paper_2411_03029_amd as tb
     op = oracle_plan(name)
     plan = gpu_plan(name, tmp_path, store=("otf",))
     n, d = op.n, op.d
-    for nrhs in (1, 5):
+    for nrhs in (1, 5, 12):
         f = inputs.rhs_batch(n, d, nrhs, config=95)
         say(f"[gpu] on-the-fly cores {name} nrhs={nrhs}")
         x = to_dev(f, torch.complex64)

@@ -73,7 +73,7 @@ def _candidates(stage, nrhs, dtype):
         out = [dict(core_kernel=1)]
         if nrhs >= 2:
             out.append(dict(core_kernel=2))
-        if dtype not in ("c128", "c64otf") and nrhs >= 4:
+        if dtype != "c128" and nrhs >= 4:   # FP32 matrix cores, stored or on the fly
             out.append(dict(core_kernel=3))
         if dtype == "cbf16" and nrhs >= 4:
             out += [dict(core_kernel=v) for v in (4, 5, 6, 7)]
