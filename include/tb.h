@@ -274,11 +274,15 @@ typedef struct {
                              products on the matrix cores, one block per workgroup */
   int rhs_per_thread;     /* fan-out / fan-in kernels: 1 or 4 right-hand sides per thread
                              (4 needs a right-hand-side tile of 4 or 8) */
-  int flat_stage;         /* transfer stages and leaves, FP32 applies: 1 = flat staging, one
+  int flat_stage;         /* transfer stages and leaves: 1 = flat staging (FP32 applies), one
                              right-hand side per workgroup: the block (fan-out: the coarse
                              block; fan-in: all children's blocks) and every matrix loaded
                              into LDS in one pass, then all mode products from LDS; slices
-                             for about 1024 workgroups, or whole blocks with whole_blocks = 1 */
+                             for about 1024 workgroups, or whole blocks with whole_blocks = 1;
+                             2 = register fibers (FP32 or FP64), one right-hand side per
+                             workgroup: each mode product loads fibers of its contracted mode
+                             into registers and reads the matrices from LDS; contracted
+                             extents up to 32; slices, or whole blocks with whole_blocks = 1 */
 } tb_launch_cfg;
 
 /* Set the configuration of launch `slot` for applies of p with exactly this

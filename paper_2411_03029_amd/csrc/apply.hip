@@ -3116,6 +3116,25 @@ static StageArgs stage_args(const Plan& p, const Level& fine, const Level* coars
   a.outer_block = (int)(p.n >> a.outer_level);
   a.nrhs = nrhs;
   a.conj = conj ? 1 : 0;
+  // longest contracted extents: a fan-out contracts the coarse block's true
+  // extents (two sibling skeletons, or the dense leaf boxes), a fan-in the
+  // fine ranks
+  a.fib_in = 0;
+  for (int k = 0; k < d; ++k) a.fib_in = std::max(a.fib_in, fine.R[k]);
+  if (coarse) {
+    if (coarse->pair_max < 0) {
+      int m = 0;
+      for (int it = 0; it < coarse->nitems; ++it)
+        for (int k = 0; k < d; ++k)
+          for (int b = 0; b + 1 < coarse->nb; b += 2)
+            m = std::max(m, coarse->id(it, k, b, d).r + coarse->id(it, k, b + 1, d).r);
+      coarse->pair_max = m;
+    }
+    a.fib_out = coarse->pair_max;
+  } else {
+    a.fib_out = 0;
+    for (int k = 0; k < d; ++k) a.fib_out = std::max(a.fib_out, fine.A[k]);
+  }
   return a;
 }
 
@@ -3414,10 +3433,39 @@ static tb_status launch_stage_turn(const Plan& p, StageArgs a, int n_items, cons
 // largest RHS tile QT <= 8 that fits the LDS budget, G = 8 from QT = 4 on,
 // and slices of the first mode until about kTargetWorkgroups workgroups
 // exist (split = 1: one slice per block when it fits).
+// Register-fiber stages (stage_fiber.hip): one right-hand side per
+// workgroup, slices of the first output mode for about kTargetWorkgroups
+// workgroups (or whole blocks), two workgroups' LDS per CU where possible.
+template <class T>
+static tb_status launch_stage_fiber(const Plan& p, StageArgs a, bool fanout, int n_items, const void* in,
+                                    void* out, const void* mats, hipStream_t stream, const LaunchCfg& cfg) {
+  using C = typename CplxOf<T>::type;
+  const int d = p.d;
+  int limit = 0;
+  TB_TRY(lds_limit(&limit));
+  const long long budget = std::min<long long>(limit, 80 * 1024);
+  const long long blocks = (long long)n_items * a.nblk * a.nrhs;
+  const int dim = fanout ? a.R[0] : a.A[0];
+  int chunk = cfg.split == 1
+                  ? dim
+                  : (int)std::max<long long>(1, (dim * blocks + kTargetWorkgroups - 1) / kTargetWorkgroups);
+  chunk = std::max(1, std::min(chunk, dim));
+  while (chunk > 1 && stage_lds_elems(a, d, fanout, chunk, 1, true) * (long long)sizeof(C) > budget) --chunk;
+  const size_t lds = (size_t)stage_lds_elems(a, d, fanout, chunk, 1, true) * sizeof(C);
+  if (lds + 256 > (size_t)limit)
+    return fail(TB_ERR_UNSUPPORTED, "transfer block exceeds the per-workgroup LDS budget");
+  a.chunk = chunk;
+  a.nsplit = (dim + chunk - 1) / chunk;
+  const long long nwg = blocks * a.nsplit;
+  return launch_stage_fib(sizeof(T) == 8, a, d, fanout, fanout ? a.fib_out : a.fib_in, nwg, lds, in, out,
+                          mats, stream);
+}
+
 template <class T>
 static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_items, const void* in,
                               void* out, const void* mats, hipStream_t stream, const LaunchCfg& cfg) {
   using C = typename CplxOf<T>::type;
+  if (cfg.alt == 4) return launch_stage_fiber<T>(p, a, fanout, n_items, in, out, mats, stream, cfg);
   if (cfg.alt == 3) {  // flat staging, one right-hand side per workgroup
     if constexpr (sizeof(T) != 4) {
       return fail(TB_ERR_UNSUPPORTED, "flat-staged transfer stages are FP32 only");
@@ -4100,6 +4148,13 @@ static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout, bool
       c.split = split;
       out.push_back(c);
     }
+  if (nrhs <= 4)
+    for (int split : {0, 1}) {  // register fibers, one right-hand side per workgroup
+      LaunchCfg c;
+      c.alt = 4;
+      c.split = split;
+      out.push_back(c);
+    }
   return out;
 }
 
@@ -4484,7 +4539,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
       cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 9 ||
       cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 2 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1 ||
       !(cfg->rhs_per_thread == 0 || cfg->rhs_per_thread == 1 || cfg->rhs_per_thread == 4) ||
-      cfg->flat_stage < 0 || cfg->flat_stage > 1 || (cfg->flat_stage && cfg->fanin_in_turn))
+      cfg->flat_stage < 0 || cfg->flat_stage > 2 || (cfg->flat_stage && cfg->fanin_in_turn))
     return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");
   auto& v = p->tuned[{(int)io, nrhs}];
   if ((int)v.size() != nslots) v.assign(nslots, tb::LaunchCfg{});
@@ -4493,7 +4548,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   c.QT = q;
   c.split = cfg->whole_blocks;
   c.core = cfg->core_kernel;
-  c.alt = cfg->flat_stage ? 3 : cfg->fanin_in_turn;
+  c.alt = cfg->flat_stage == 2 ? 4 : cfg->flat_stage ? 3 : cfg->fanin_in_turn;
   c.mfma = cfg->transfer_mfma;
   c.V = cfg->rhs_per_thread;
   v[slot] = c;

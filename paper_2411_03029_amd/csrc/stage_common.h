@@ -31,6 +31,7 @@ struct StageArgs {
   const int* rank_c;              // true ranks of the coarse level (null: leaves)
   int nb_c;                       // blocks per mode of a coarse item
   int Rc[kMaxD];                  // padded ranks of the coarse level
+  int fib_out, fib_in;            // longest contracted extent of a fan-out / fan-in mode product
 };
 
 // True extent of mode k of the coarse block beta_k: the two children's
@@ -238,6 +239,12 @@ constexpr int kMaxChildren = 1 << kMaxDTuned;  // fan-in children of the tuned k
 long long flat_lds_elems(const StageArgs& a, int d, bool fanout, int chunk);
 tb_status launch_stage_flat_f32(StageArgs a, int d, bool fanout, int n_items, const void* in, void* out,
                                 const void* mats, hipStream_t stream, int mode, int lds_limit);
+
+// Register-fiber transfer stages (stage_fiber.hip), FP32 or FP64, one
+// right-hand side per workgroup; xm bounds the contracted extents.
+constexpr int kFibMaxLen = 32;
+tb_status launch_stage_fib(bool fp64, const StageArgs& a, int d, bool fanout, int xm, long long nwg,
+                           size_t lds, const void* in, void* out, const void* mats, hipStream_t stream);
 
 // Generic apply for any number of modes (apply_generic.hip): per-workgroup
 // scratch in global memory, FP64 (fp64) or FP32.

@@ -74,6 +74,7 @@ struct Level {
   double2* X64 = nullptr;
   float2* X32 = nullptr;
   int* rank_d = nullptr;                // true ranks [item][k][blk]
+  mutable int pair_max = -1;            // largest sum of two sibling blocks' ranks (-1: not yet known)
   const IdRec& id(int item, int k, int blk, int d) const {
     return ids[((size_t)item * d + k) * nb + blk];
   }
@@ -103,7 +104,8 @@ struct LaunchCfg {
                   // 4 = BF16 MFMA (BF16 cores); 5-7 = BF16 MFMA, second form (three
                   // tiles); 8, 9 = adjoint vector kernel, 16-lane column groups, 1 / 4 RHS
   int alt = 0;    // fan-in: 1 = children in turn, mode 0 in registers; 2 = children in
-                  // turn, mode 0 first; fan-out or fan-in, FP32: 3 = flat staging
+                  // turn, mode 0 first; fan-out or fan-in, FP32: 3 = flat staging;
+                  // fan-out or fan-in: 4 = register fibers
   int mfma = 0;   // transfer levels: 1 = mode products on the matrix cores
   int V = 0;      // transfer: right-hand sides per thread (1 or 4; 4 needs QT >= 4)
 };

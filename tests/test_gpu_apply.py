@@ -103,6 +103,39 @@ def test_apply_matches_oracle_fp32(name, tmp_path):
         assert_parity(v, bf.apply_adjoint(op, f), 2e-5, "adjoint")
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_register_fiber_stages_match_oracle(name, tmp_path):
+    # every transfer and leaf launch of both directions on the register-fiber
+    # kernels (slices, then whole blocks); a stage whose block does not fit
+    # the kernel's LDS is rejected with TB_ERR_UNSUPPORTED, and FP32 must run
+    torch = torch_gpu()
+    import paper_2411_03029_amd as tb
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path)
+    n, d = op.n, op.d
+    slots = [s for s, st in enumerate(plan.launch_slots()) if not st.startswith("core")]
+    ran = set()
+    for whole in (0, 1):
+        for dt, cdt, bound, nrhs in (("c128", torch.complex128, 1e-12, 2), ("c64", torch.complex64, 2e-5, 1),
+                                     ("c64", torch.complex64, 2e-5, 3)):
+            for s in slots:
+                plan.set_launch(nrhs, s, dtype=dt, flat_stage=2, whole_blocks=whole)
+            f = inputs.rhs_batch(n, d, nrhs, config=93)
+            x = to_dev(f, cdt)
+            say(f"[gpu] register fibers {name} {dt} nrhs={nrhs} whole={whole}")
+            try:
+                u = to_host(plan.apply(x, dtype=dt))
+                v = to_host(plan.apply_adjoint(x, dtype=dt))
+                torch.cuda.synchronize()
+            except tb.TBError as e:
+                assert e.status == 2, str(e)   # TB_ERR_UNSUPPORTED: the block exceeds the LDS
+                continue
+            assert_parity(u, bf.apply(op, f), bound, f"forward {dt} whole={whole}")
+            assert_parity(v, bf.apply_adjoint(op, f), bound, f"adjoint {dt} whole={whole}")
+            ran.add(dt)
+    assert "c64" in ran
+
+
 def test_single_input_shape_and_batched_rhs_consistency(tmp_path):
     torch = torch_gpu()
     name = "helm3_n32"
