@@ -265,15 +265,44 @@ def _stage_ms(plan) -> dict:
     return {k: (ms, c) for k, (ms, c) in plan.stage_times().items() if c}
 
 
+def _one_step_stage_ms(plan, x, dtype, torch) -> dict:
+    """HIP-event times per stage family of exactly one tb_apply +
+    tb_apply_adjoint (outputs allocated beforehand, untimed)."""
+    u = plan.apply(x, dtype=dtype)
+    v = plan.apply_adjoint(u, dtype=dtype)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.apply(x, out=u, dtype=dtype)
+    plan.apply_adjoint(u, out=v, dtype=dtype)
+    torch.cuda.synchronize()
+    st = _stage_ms(plan)
+    plan.set_timing(False)
+    return st
+
+
 def _stage_flops(info, stage: str, nrhs: int) -> float:
     """Algorithmic flops of one stage family (8 real flops per complex
     multiply-add, oracle mode order, true ranks) for nrhs right-hand sides."""
-    fwd = {"src_leaf": 0, "src_transfer": 1, "core": 2, "tgt_transfer": 3, "tgt_leaf": 4}
-    mirror = {"tgt_leaf_adj": "src_leaf", "tgt_transfer_adj": "src_transfer",
-              "core_adj": "core", "src_transfer_adj": "tgt_transfer",
-              "src_leaf_adj": "tgt_leaf"}
-    key = mirror.get(stage, stage)
-    return 8.0 * info["stage_cmacs"][fwd[key]] * nrhs
+    return 8.0 * info["stage_cmacs"][_STAGE_FAMILY[stage]] * nrhs
+
+
+# forward stage family of each launch slot name: an adjoint stage applies the
+# conjugate transposes of the same matrices as its forward namesake, with the
+# same multiply-add count and the same tensors read and written
+_STAGE_FAMILY = {"src_leaf": 0, "src_transfer": 1, "core": 2, "tgt_transfer": 3, "tgt_leaf": 4,
+                 "src_leaf_adj": 0, "src_transfer_adj": 1, "core_adj": 2, "tgt_transfer_adj": 3,
+                 "tgt_leaf_adj": 4}
+
+
+def _stage_bytes(info, stage: str, nrhs: int, esz: int = 8) -> float:
+    """Algorithmic HBM bytes of one stage family for nrhs right-hand sides:
+    the tensors it reads and writes at true ranks, each once (the core
+    family: F and G, plus every stored core entry)."""
+    f = _STAGE_FAMILY[stage]
+    b = float(esz) * info["stage_io_entries"][f] * nrhs
+    if f == 2:
+        b += esz * info["core_entries"]
+    return b
 
 
 def _relerr(a, b) -> float:
@@ -397,8 +426,10 @@ def run_single(args, tb, inputs, torch, np) -> dict:
     # input and writing the output, over the summed stage times of one step
     fwd = ("src_leaf", "src_transfer", "core", "tgt_transfer", "tgt_leaf")
     apply_bytes = 8 * (info["factor_entries"] + info["core_entries"] + 2 * n ** d * nrhs)
-    t_fwd = sum(stages[k][0] for k in fwd) / args.steps * 1e-3
-    t_adj = sum(ms for k, (ms, c) in stages.items() if k not in fwd) / args.steps * 1e-3
+    # the instrumented pass applies steps + 1 times (time_steps' first pair
+    # allocates the outputs)
+    t_fwd = sum(stages[k][0] for k in fwd) / (args.steps + 1) * 1e-3
+    t_adj = sum(ms for k, (ms, c) in stages.items() if k not in fwd) / (args.steps + 1) * 1e-3
     apply_hbm = {"bytes_per_direction": apply_bytes,
                  "fwd_us": round(t_fwd * 1e6, 1), "adj_us": round(t_adj * 1e6, 1),
                  "frac_fwd": round(apply_bytes / t_fwd / 1e9 / HBM_PEAK_GBS, 4),
@@ -475,21 +506,25 @@ def batched_leg(args, tb, inputs, torch, np) -> dict:
     # the same step with the cores evaluated on the fly on the matrix cores
     plan.autotune(nrhs, dtype="c64otf", cache=args.tune_cache)
     t_otf = time_steps(plan, x, "c64otf", steps, 2, torch)
-    plan.set_timing(True)
-    time_steps(plan, x, "c64otf", 1, 0, torch)
-    st_otf = _stage_ms(plan)
-    plan.set_timing(False)
+    st_otf = _one_step_stage_ms(plan, x, "c64otf", torch)
     otf_core_ms = st_otf["core"][0] + st_otf["core_adj"][0]
     otf_core_flops = _stage_flops(info, "core", nrhs) + _stage_flops(info, "core_adj", nrhs)
     t = time_steps(plan, x, "c64", steps, 2, torch)
-    plan.set_timing(True)
-    time_steps(plan, x, "c64", 1, 0, torch)
-    st = _stage_ms(plan)
-    plan.set_timing(False)
-    per = {k: {"ms": round(ms, 3), "launches": c,
-               "TFLOP/s": round(_stage_flops(info, k, nrhs) / (ms * 1e-3) / 1e12, 2),
-               "frac_fp32_mfma": round(_stage_flops(info, k, nrhs) / (ms * 1e-3) / 1e12 / 157.3, 4)}
-           for k, (ms, c) in st.items()}
+    st = _one_step_stage_ms(plan, x, "c64", torch)
+    # per stage: matrix-core rate, and the roofline of the stage as a whole:
+    # min(FP32 matrix-core peak, HBM peak x flops per algorithmic byte)
+    per = {}
+    for k, (ms, c) in st.items():
+        fl, by = _stage_flops(info, k, nrhs), _stage_bytes(info, k, nrhs)
+        sec = ms * 1e-3
+        attain = min(157.3, HBM_PEAK_GBS * fl / by / 1e3)
+        per[k] = {"ms": round(ms, 3), "launches": c,
+                  "TFLOP/s": round(fl / sec / 1e12, 2),
+                  "frac_fp32_mfma": round(fl / sec / 1e12 / 157.3, 4),
+                  "GB/s": round(by / sec / 1e9, 1),
+                  "flop_per_byte": round(fl / by, 2),
+                  "roofline_TFLOPs": round(attain, 1),
+                  "frac_roofline": round(fl / sec / 1e12 / attain, 4)}
     dom = max(st, key=lambda k: st[k][0])
     flops = 8.0 * info["apply_cmacs"] * nrhs * 2
     out = {"value": nrhs * n ** d * steps / t, "unit": "points/s",
@@ -497,6 +532,7 @@ def batched_leg(args, tb, inputs, torch, np) -> dict:
            "step": "tb_apply + tb_apply_adjoint, complex FP32",
            "whole_step_TFLOPs": round(flops / (t / steps) / 1e12, 2),
            "dominant_stage": dom, "dominant_frac_fp32_mfma": per[dom]["frac_fp32_mfma"],
+           "dominant_frac_roofline": per[dom]["frac_roofline"],
            "stages": per, "construct_s": round(construct_s, 3), "autotune_s": round(autotune_s, 3),
            "on_the_fly_cores": {
                "value": nrhs * n ** d * steps / t_otf, "ms_per_step": 1e3 * t_otf / steps,

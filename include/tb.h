@@ -162,6 +162,11 @@ typedef struct {
                                  leaf, source transfers (all levels), core,
                                  target transfers, target leaf; the adjoint
                                  stage mirroring each has the same count    */
+  long long stage_io_entries[5]; /* per RHS, the same split: entries of the
+                                 tensors the stage family reads and writes
+                                 (true ranks, each tensor once; the leaves
+                                 include the n^d array, the core family F
+                                 and G but not the cores)                   */
 } tb_plan_info_t;
 
 /* Build the factorisation on the GPU (Algorithm 1).

@@ -87,6 +87,7 @@ class Plan:
         _lib.check(_lib.load().tb_plan_info(self._h, ctypes.byref(info)))
         out = {name: getattr(info, name) for name, _ in info._fields_}
         out["stage_cmacs"] = list(out["stage_cmacs"])
+        out["stage_io_entries"] = list(out["stage_io_entries"])
         return out
 
     @property

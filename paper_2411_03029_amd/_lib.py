@@ -56,7 +56,8 @@ class TbPlanInfo(ctypes.Structure):
                 ("apply_cmacs", ctypes.c_longlong), ("omega", ctypes.c_double),
                 ("tol", ctypes.c_double), ("eps_id", ctypes.c_double),
                 ("store_mask", ctypes.c_uint), ("device_bytes", ctypes.c_size_t),
-                ("construct_ms", ctypes.c_double), ("stage_cmacs", ctypes.c_longlong * 5)]
+                ("construct_ms", ctypes.c_double), ("stage_cmacs", ctypes.c_longlong * 5),
+                ("stage_io_entries", ctypes.c_longlong * 5)]
 
 
 class TBError(RuntimeError):

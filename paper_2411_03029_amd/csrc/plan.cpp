@@ -334,6 +334,37 @@ long long apply_cmacs(const Plan& p, long long* per_stage) {
   return total;
 }
 
+// Entries of the tensors each forward stage family reads and writes, per
+// right-hand side, at true ranks: an item tensor holds, per mode, the
+// concatenated ranks of its blocks, and every tensor counts once (a parent
+// read by its 2^d children is one read).  The leaves read or write the
+// caller's n^d array; the core family counts F and G, not the cores.
+void stage_io_entries(const Plan& p, long long* out5) {
+  const int d = p.d;
+  auto level_entries = [&](const Level& L) {
+    long long e = 0;
+    for (int it = 0; it < L.nitems; ++it) {
+      long long prod = 1;
+      for (int k = 0; k < d; ++k) {
+        long long len = 0;
+        for (int b = 0; b < L.nb; ++b) len += L.id(it, k, b, d).r;
+        prod *= len;
+      }
+      e += prod;
+    }
+    return e;
+  };
+  long long nd = 1;
+  for (int k = 0; k < d; ++k) nd *= p.n;
+  for (int i = 0; i < 5; ++i) out5[i] = 0;
+  if (p.src.empty() || p.tgt.empty()) return;
+  out5[0] = nd + level_entries(p.src[0]);
+  for (size_t l = 1; l < p.src.size(); ++l) out5[1] += level_entries(p.src[l - 1]) + level_entries(p.src[l]);
+  out5[2] = level_entries(p.src.back()) + level_entries(p.tgt.back());
+  for (size_t l = 1; l < p.tgt.size(); ++l) out5[3] += level_entries(p.tgt[l]) + level_entries(p.tgt[l - 1]);
+  out5[4] = level_entries(p.tgt[0]) + nd;
+}
+
 // ------------------------------------------------------------- plan file --
 static uint32_t crc32_table[256];
 static bool crc32_ready = false;
@@ -448,6 +479,7 @@ extern "C" tb_status tb_plan_info(tb_plan ph, tb_plan_info_t* info) {
     info->core_cols += p.pair_meta[(size_t)pr * kPairMeta + 1];
   }
   info->apply_cmacs = apply_cmacs(p, info->stage_cmacs);
+  stage_io_entries(p, info->stage_io_entries);
   info->omega = p.omega;
   info->tol = p.tol;
   info->eps_id = p.eps_id;

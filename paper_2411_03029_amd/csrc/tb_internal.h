@@ -170,6 +170,7 @@ tb_status finalize_plan(Plan& p, hipStream_t stream);  // pads + uploads factors
 tb_status build_core_tables(Plan& p);
 tb_status set_nudft_points(Plan& p, const double* x);  // checks, copies, uploads
 long long apply_cmacs(const Plan& p, long long* per_stage = nullptr);
+void stage_io_entries(const Plan& p, long long* out5);
 
 // kernels launched by host code
 tb_status launch_core_eval(Plan& p, hipStream_t stream, const double2* host_cores);

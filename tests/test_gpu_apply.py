@@ -136,6 +136,28 @@ def test_register_fiber_stages_match_oracle(name, tmp_path):
     assert "c64" in ran
 
 
+@pytest.mark.parametrize("name", ["helm3_n32_leaf4", "radon2_n64_leaf4"])
+def test_stage_io_entries_follow_the_plan(name, tmp_path):
+    # the tensor sizes the bench's per-stage byte counts use, against the
+    # oracle plan's ranks: an item tensor holds per mode the concatenated
+    # ranks of its blocks
+    torch_gpu()
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path)
+
+    def entries(level):
+        tot = 0
+        for per_k in level.values():
+            tot += int(np.prod([sum(sk.rank for sk in per_k[k]) for k in range(op.d)]))
+        return tot
+
+    nd = op.n ** op.d
+    src, tgt = [entries(lv) for lv in op.src], [entries(lv) for lv in op.tgt]
+    want = [nd + src[0], sum(src[l - 1] + src[l] for l in range(1, len(src))), src[-1] + tgt[-1],
+            sum(tgt[l] + tgt[l - 1] for l in range(1, len(tgt))), tgt[0] + nd]
+    assert plan.info()["stage_io_entries"] == want
+
+
 def test_single_input_shape_and_batched_rhs_consistency(tmp_path):
     torch = torch_gpu()
     name = "helm3_n32"
