@@ -261,6 +261,81 @@ def summarize(trace_dir, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, c
     return 0
 
 
+def _dispatch_groups(directory: str) -> dict:
+    """rocprofv3 --pmc CSV rows grouped by (kernel, grid size): per group the
+    per-dispatch counter sums (counters summed over the rows of a dispatch)
+    and the dispatch durations."""
+    disp = {}
+    for r in _rocprof_rows(directory, "counter_collection.csv"):
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        d = disp.setdefault(key, {"name": r["Kernel_Name"], "grid": int(r["Grid_Size"]),
+                                  "wg": int(r["Workgroup_Size"]), "c": {},
+                                  "us": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3})
+        d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    groups = {}
+    for d in disp.values():
+        g = groups.setdefault((d["name"], d["grid"] // max(d["wg"], 1)), {"n": 0, "us": 0.0, "c": {}})
+        g["n"] += 1
+        g["us"] += d["us"]
+        for k, v in d["c"].items():
+            g["c"][k] = g["c"].get(k, 0.0) + v
+    return groups
+
+
+def summarize_counters(sq_dir, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes,
+                       workload, command, min_dispatches=8, clock_mhz=2400.0) -> int:
+    """profiles/stage_counters_<workload>.md: per transfer / core launch shape
+    (kernel, workgroups) with at least min_dispatches dispatches, the SQ
+    counters of the waves (lifetime, resident waves per SIMD, shares of the
+    lifetime spent waiting, issuing, in VALU and LDS instructions) and the
+    HBM bytes per dispatch (FETCH_SIZE / WRITE_SIZE scaled by a plain copy).
+    SQ_WAVE_CYCLES counts quad cycles; the shader clock is taken as
+    clock_mhz."""
+    sq, fe, wr = _dispatch_groups(sq_dir), _dispatch_groups(fetch_dir), _dispatch_groups(write_dir)
+    fetch_scale = copy_bytes / _counter_per_dispatch(copy_fetch_dir, "FETCH_SIZE", "copy")
+    write_scale = copy_bytes / _counter_per_dispatch(copy_write_dir, "WRITE_SIZE", "copy")
+    lines = [f"# Wave and traffic counters per launch shape: workload {workload}", "",
+             "commands:", ""] + [f"- {k}: `{v}`" for k, v in command.items()] + [
+             "", f"Launch shapes of the stage and core kernels with at least {min_dispatches} "
+             "dispatches (the autotuner's trials of other shapes are left out).  Per dispatch "
+             "averages; lifetime and waves per SIMD take the shader clock as "
+             f"{clock_mhz:.0f} MHz; shares are of the waves' lifetime (SQ_WAIT_ANY, "
+             "SQ_ACTIVE_INST_ANY, SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_LDS over SQ_WAVE_CYCLES); "
+             "bytes are FETCH_SIZE and WRITE_SIZE scaled by the same counters over a copy of "
+             f"{copy_bytes} bytes.", "",
+             "| kernel | WGs | dispatches | us | waves | wave lifetime (us) | waves / SIMD | "
+             "waiting | issuing | VALU | LDS | fetch MB | write MB | GB/s |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    rows = []
+    for (name, nwg), g in sq.items():
+        if g["n"] < min_dispatches or not ("stage_" in name or "core_" in name):
+            continue
+        n = g["n"]
+        c = {k: v / n for k, v in g["c"].items()}
+        us = g["us"] / n
+        waves = c.get("SQ_WAVES", 0.0)
+        life_us = 4.0 * c.get("SQ_WAVE_CYCLES", 0.0) / max(waves, 1.0) / clock_mhz
+        per_simd = 4.0 * c.get("SQ_WAVE_CYCLES", 0.0) / clock_mhz / max(us, 1e-9) / 1024.0
+        wc = max(c.get("SQ_WAVE_CYCLES", 0.0), 1.0)
+        f = fe.get((name, nwg))
+        w = wr.get((name, nwg))
+        fmb = f["c"].get("FETCH_SIZE", 0.0) / f["n"] * fetch_scale / 1e6 if f else float("nan")
+        wmb = w["c"].get("WRITE_SIZE", 0.0) / w["n"] * write_scale / 1e6 if w else float("nan")
+        short = name.split("(")[0].replace("void ", "").replace("HIP_vector_type<float, 2u>", "float2")
+        rows.append((-us * n, f"| {short} | {nwg} | {n} | {us:.2f} | {waves:.0f} | {life_us:.2f} | "
+                              f"{per_simd:.2f} | {c.get('SQ_WAIT_ANY', 0) / wc:.2f} | "
+                              f"{c.get('SQ_ACTIVE_INST_ANY', 0) / wc:.2f} | "
+                              f"{c.get('SQ_ACTIVE_INST_VALU', 0) / wc:.2f} | "
+                              f"{c.get('SQ_ACTIVE_INST_LDS', 0) / wc:.2f} | {fmb:.2f} | {wmb:.2f} | "
+                              f"{(fmb + wmb) * 1e3 / us:.0f} |"))
+    lines += [r for _, r in sorted(rows)]
+    path = os.path.join(ROOT, "profiles", f"stage_counters_{workload}.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(path)
+    return 0
+
+
 def _stage_ms(plan) -> dict:
     return {k: (ms, c) for k, (ms, c) in plan.stage_times().items() if c}
 
@@ -790,6 +865,9 @@ def main() -> int:
     ap.add_argument("--summarize", nargs=5, metavar="DIR",
                     help="write profiles/ from rocprofv3 CSV dirs: trace fetch write "
                          "copy_fetch copy_write")
+    ap.add_argument("--summarize-counters", nargs=5, metavar="DIR",
+                    help="write profiles/stage_counters_<workload>.md from rocprofv3 --pmc "
+                         "output: SQ counters, FETCH_SIZE, WRITE_SIZE, copy FETCH_SIZE, copy WRITE_SIZE")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="write profiles/kernel_stats_<workload>.md from a rocprofv3 trace dir")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
@@ -797,6 +875,9 @@ def main() -> int:
     args = ap.parse_args()
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
+    if args.summarize_counters:
+        return summarize_counters(*args.summarize_counters, args.copy_bytes, args.workload,
+                                  json.loads(args.commands_json))
     if args.summarize_stats:
         return summarize_stats(args.summarize_stats, args.workload, args.commands_json)
     if args.summarize:
