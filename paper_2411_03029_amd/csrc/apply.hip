@@ -58,10 +58,12 @@ __global__ void __launch_bounds__(kThreads)
   for (int k = 0; k < D; ++k) r[k] = a.rank_f[((long long)fi * D + k) * a.nb + beta[k]];
   const int lo = sb.split * a.chunk;
   const int na = min(r[0], lo + a.chunk) - lo;
-  if (na <= 0) return;
+  // the coarse segments do not depend on the fine ranks: their loads are
+  // issued before the slice test, in the same memory round trip
   const int citem = a.coarse_global ? (fi >> (D * a.lvl)) : parent_of<D>(fi, a.lvl);
   Seg sg[D];
   coarse_segs<D>(a, citem, beta, sg);
+  if (na <= 0) return;
   const int q0 = sb.q0;
   const int Qa = min(QT, a.nrhs - q0);
   CoarseAddr<D> ca;
@@ -324,7 +326,6 @@ __global__ void __launch_bounds__(kThreads)
   coarse_segs<D>(a, ci, beta, sg);
   const int lo = sb.split * a.chunk;
   const int na = min(sg[0].c, lo + a.chunk) - lo;
-  if (na <= 0) return;
   const int q0 = sb.q0;
   const int Qa = min(QT, a.nrhs - q0);
   const int nchild = a.coarse_global ? 1 : (1 << D);
@@ -340,6 +341,9 @@ __global__ void __launch_bounds__(kThreads)
     long long fs_[D];
     cfb[c] = fine_base<D>(a, fi, beta, q0, fs_);
   }
+  // tested after the children's rank loads are issued (one round trip for
+  // both); uniform over the workgroup, before any barrier
+  if (na <= 0) return;
   long long fs[D];
   (void)fine_base<D>(a, 0, beta, 0, fs);   // strides only
   __syncthreads();
@@ -593,7 +597,6 @@ __global__ void __launch_bounds__(kThreads)
   coarse_segs<D>(a, ci, beta, sg);
   const int lo = sb.split * a.chunk;
   const int na = min(sg[0].c, lo + a.chunk) - lo;
-  if (na <= 0) return;
   const int q0 = sb.q0;
   const int Qa = min(QT, a.nrhs - q0);
   const int nchild = a.coarse_global ? 1 : (1 << D);
@@ -608,6 +611,9 @@ __global__ void __launch_bounds__(kThreads)
     long long fs_[D];
     cfb[c] = fine_base<D>(a, fi, beta, q0, fs_);
   }
+  // tested after the children's rank loads are issued (one round trip for
+  // both); uniform over the workgroup, before any barrier
+  if (na <= 0) return;
   long long fs[D];
   (void)fine_base<D>(a, 0, beta, 0, fs);   // strides only
   __syncthreads();
@@ -871,7 +877,6 @@ __global__ void __launch_bounds__(kThreads)
   coarse_segs<D>(a, ci, beta, sg);
   const int lo = sb.split * a.chunk;
   const int na = min(sg[0].c, lo + a.chunk) - lo;
-  if (na <= 0) return;
   const int q0 = sb.q0;
   const int Qa = min(QT, a.nrhs - q0);
   const int nchild = a.coarse_global ? 1 : (1 << D);
@@ -886,6 +891,9 @@ __global__ void __launch_bounds__(kThreads)
     long long fs_[D];
     cfb[c] = fine_base<D>(a, fi, beta, q0, fs_);
   }
+  // tested after the children's rank loads are issued (one round trip for
+  // both); uniform over the workgroup, before any barrier
+  if (na <= 0) return;
   long long fs[D];
   (void)fine_base<D>(a, 0, beta, 0, fs);  // strides only
   __syncthreads();
@@ -3465,6 +3473,14 @@ template <class T>
 static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_items, const void* in,
                               void* out, const void* mats, hipStream_t stream, const LaunchCfg& cfg) {
   using C = typename CplxOf<T>::type;
+  if (fanout) {  // item blocks per outer middle multi-set (fine items): the
+                 // fan-outs of one side read what the previous fan-out wrote
+                 // for the same outer multi-set; a fan-in reads the core's or
+                 // its children's outputs, written from every XCD, and keeps
+                 // the balanced round-robin map (measured slower with it)
+    const long long per = (1LL << (p.d * a.lvl)) * a.nblk;
+    a.aff_blocks = per < (1LL << 30) ? (int)per : 0;
+  }
   if (cfg.alt == 4) return launch_stage_fiber<T>(p, a, fanout, n_items, in, out, mats, stream, cfg);
   if (cfg.alt == 3) {  // flat staging, one right-hand side per workgroup
     if constexpr (sizeof(T) != 4) {

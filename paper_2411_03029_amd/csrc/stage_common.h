@@ -32,6 +32,7 @@ struct StageArgs {
   int nb_c;                       // blocks per mode of a coarse item
   int Rc[kMaxD];                  // padded ranks of the coarse level
   int fib_out, fib_in;            // longest contracted extent of a fan-out / fan-in mode product
+  int aff_blocks;                 // item blocks of one outer middle multi-set in the launch (0: none)
 };
 
 // True extent of mode k of the coarse block beta_k: the two children's
@@ -215,15 +216,30 @@ __device__ __forceinline__ int xcd_item(int b, int n, int g) {
   return ((i / g) * kXcds + x) * g + i % g;
 }
 
+// Workgroup b of n -> work item, so that the items of one outer middle
+// multi-set (s on the source side, t on the target side; `per` consecutive
+// items each) all run on XCD (outer mod 8): successive launches of one side
+// then read their inputs from the L2 that wrote them.  Needs n to be a
+// multiple of 8 per; otherwise the XCD-grouped map of groups of g.
+__device__ __forceinline__ int xcd_outer(int b, int n, long long per, int g) {
+  const long long span = kXcds * per;
+  if (per <= 0 || n % span != 0) return xcd_item(b, n, g);
+  const int x = b % kXcds, r = b / kXcds;
+  const long long outer = x + (long long)kXcds * (r / per);
+  return (int)(outer * per + r % per);
+}
+
 // Workgroup -> (block, slice, right-hand-side tile); the tile index runs
-// fastest and the enumeration is XCD-contiguous, so that workgroups sharing
-// cache lines of the q-innermost intermediates run in the same L2.
+// fastest, and the blocks of one outer middle multi-set share an XCD (or,
+// when their count does not allow it, groups of one block's slices and
+// tiles do), so that workgroups sharing cache lines run in the same L2.
 struct StageBid {
   int item_blk, split, q0;
 };
 __device__ __forceinline__ StageBid stage_bid(const StageArgs& a, int QT) {
   const int nqt = (a.nrhs + QT - 1) / QT;
-  int bid = xcd_item(blockIdx.x, gridDim.x, nqt * a.nsplit);
+  const int g = nqt * a.nsplit;
+  int bid = xcd_outer(blockIdx.x, gridDim.x, (long long)a.aff_blocks * g, g);
   StageBid s;
   s.q0 = (bid % nqt) * QT;
   bid /= nqt;

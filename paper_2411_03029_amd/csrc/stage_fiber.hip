@@ -84,10 +84,10 @@ __global__ void __launch_bounds__(kThreads)
   for (int k = 0; k < D; ++k) r[k] = a.rank_f[((long long)fi * D + k) * a.nb + beta[k]];
   const int lo = sb.split * a.chunk;
   const int na = min(r[0], lo + a.chunk) - lo;
-  if (na <= 0) return;  // uniform over the workgroup
   const int citem = a.coarse_global ? (fi >> (D * a.lvl)) : parent_of<D>(fi, a.lvl);
   Seg sg[D];
-  coarse_segs<D>(a, citem, beta, sg);
+  coarse_segs<D>(a, citem, beta, sg);  // loads issued with the fine ranks'
+  if (na <= 0) return;                 // uniform over the workgroup
   CoarseAddr<D> ca;
   ca.init(a, citem, beta, sb.q0);
   long long fs[D];
@@ -231,7 +231,6 @@ __global__ void __launch_bounds__(kThreads)
   coarse_segs<D>(a, ci, beta, sg);
   const int lo = sb.split * a.chunk;
   const int na = min(sg[0].c, lo + a.chunk) - lo;
-  if (na <= 0) return;  // uniform over the workgroup
   const int q0 = sb.q0;
   const int nchild = a.coarse_global ? 1 : (1 << D);
   __shared__ int cfi[kMaxChildren], crk[kMaxChildren][kMaxDTuned];
@@ -245,6 +244,7 @@ __global__ void __launch_bounds__(kThreads)
     long long fs_[D];
     cfb[c] = fine_base<D>(a, fi, beta, q0, fs_);
   }
+  if (na <= 0) return;  // after the children's rank loads; uniform, before any barrier
   long long fs[D];
   (void)fine_base<D>(a, 0, beta, 0, fs);  // strides only
   CoarseAddr<D> ca;
