@@ -3482,6 +3482,11 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
     a.aff_blocks = per < (1LL << 30) ? (int)per : 0;
   }
   if (cfg.alt == 4) return launch_stage_fiber<T>(p, a, fanout, n_items, in, out, mats, stream, cfg);
+  if (cfg.alt == 5) {  // leaves: one wave per leaf box
+    int limit = 0;
+    TB_TRY(lds_limit(&limit));
+    return launch_leaf_wave(sizeof(T) == 8, a, p.d, fanout, n_items, in, out, mats, stream, limit);
+  }
   if (cfg.alt == 3) {  // flat staging, one right-hand side per workgroup
     if constexpr (sizeof(T) != 4) {
       return fail(TB_ERR_UNSUPPORTED, "flat-staged transfer stages are FP32 only");
@@ -4164,13 +4169,17 @@ static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout, bool
       c.split = split;
       out.push_back(c);
     }
-  if (nrhs <= 4)
+  if (nrhs <= 4) {
     for (int split : {0, 1}) {  // register fibers, one right-hand side per workgroup
       LaunchCfg c;
       c.alt = 4;
       c.split = split;
       out.push_back(c);
     }
+    LaunchCfg w;  // leaves: one wave per box (transfer levels reject it)
+    w.alt = 5;
+    out.push_back(w);
+  }
   return out;
 }
 
@@ -4555,7 +4564,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
       cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 9 ||
       cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 2 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1 ||
       !(cfg->rhs_per_thread == 0 || cfg->rhs_per_thread == 1 || cfg->rhs_per_thread == 4) ||
-      cfg->flat_stage < 0 || cfg->flat_stage > 2 || (cfg->flat_stage && cfg->fanin_in_turn))
+      cfg->flat_stage < 0 || cfg->flat_stage > 3 || (cfg->flat_stage && cfg->fanin_in_turn))
     return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");
   auto& v = p->tuned[{(int)io, nrhs}];
   if ((int)v.size() != nslots) v.assign(nslots, tb::LaunchCfg{});
@@ -4564,7 +4573,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   c.QT = q;
   c.split = cfg->whole_blocks;
   c.core = cfg->core_kernel;
-  c.alt = cfg->flat_stage == 2 ? 4 : cfg->flat_stage ? 3 : cfg->fanin_in_turn;
+  c.alt = cfg->flat_stage == 3 ? 5 : cfg->flat_stage == 2 ? 4 : cfg->flat_stage ? 3 : cfg->fanin_in_turn;
   c.mfma = cfg->transfer_mfma;
   c.V = cfg->rhs_per_thread;
   v[slot] = c;

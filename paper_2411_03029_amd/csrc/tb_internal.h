@@ -105,7 +105,7 @@ struct LaunchCfg {
                   // tiles); 8, 9 = adjoint vector kernel, 16-lane column groups, 1 / 4 RHS
   int alt = 0;    // fan-in: 1 = children in turn, mode 0 in registers; 2 = children in
                   // turn, mode 0 first; fan-out or fan-in, FP32: 3 = flat staging;
-                  // fan-out or fan-in: 4 = register fibers
+                  // fan-out or fan-in: 4 = register fibers; leaves: 5 = one wave per box
   int mfma = 0;   // transfer levels: 1 = mode products on the matrix cores
   int V = 0;      // transfer: right-hand sides per thread (1 or 4; 4 needs QT >= 4)
 };

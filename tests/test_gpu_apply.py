@@ -53,8 +53,9 @@ _PLANS = {}
 
 def oracle_plan(name):
     if name not in _PLANS:
-        kind, d, n, tol, leaf = CASES[name][:5]
-        lt = CASES[name][5] if len(CASES[name]) > 5 else None
+        spec = CASES[name] if name in CASES else LEAF16[name]
+        kind, d, n, tol, leaf = spec[:5]
+        lt = spec[5] if len(spec) > 5 else None
         om = kernels.helmholtz_omega(n) if kind == kernels.HELMHOLTZ else 0.0
         xs = inputs.nudft_points(n, d) if kind == kernels.NUDFT else None
         _PLANS[name] = bf.construct(Operator(kind, d, n, omega=om, nudft_x=xs), tol, leaf=leaf,
@@ -134,6 +135,34 @@ def test_register_fiber_stages_match_oracle(name, tmp_path):
             assert_parity(v, bf.apply_adjoint(op, f), bound, f"adjoint {dt} whole={whole}")
             ran.add(dt)
     assert "c64" in ran
+
+
+LEAF16 = {"fourier2_n64_leaf16": (kernels.FOURIER, 2, 64, 1e-6, 16),
+          "helm3_n32_leaf16": (kernels.HELMHOLTZ, 3, 32, 1e-4, 16)}
+
+
+@pytest.mark.parametrize("name", list(CASES) + list(LEAF16))
+def test_wave_per_box_leaves_match_oracle(name, tmp_path):
+    # the four leaf launches (source and target, both directions) on the
+    # one-wave-per-box kernels; leaf sizes 4, 8 and 16
+    torch = torch_gpu()
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path)
+    n, d = op.n, op.d
+    slots = [s for s, st in enumerate(plan.launch_slots()) if "leaf" in st]
+    assert len(slots) == 4
+    for dt, cdt, bound, nrhs in (("c128", torch.complex128, 1e-12, 2), ("c64", torch.complex64, 2e-5, 1),
+                                 ("c64", torch.complex64, 2e-5, 3)):
+        for s in slots:
+            plan.set_launch(nrhs, s, dtype=dt, flat_stage=3)
+        f = inputs.rhs_batch(n, d, nrhs, config=94)
+        x = to_dev(f, cdt)
+        say(f"[gpu] wave-per-box leaves {name} {dt} nrhs={nrhs}")
+        u = to_host(plan.apply(x, dtype=dt))
+        v = to_host(plan.apply_adjoint(x, dtype=dt))
+        torch.cuda.synchronize()
+        assert_parity(u, bf.apply(op, f), bound, f"forward {dt}")
+        assert_parity(v, bf.apply_adjoint(op, f), bound, f"adjoint {dt}")
 
 
 @pytest.mark.parametrize("name", ["helm3_n32_leaf4", "radon2_n64_leaf4"])

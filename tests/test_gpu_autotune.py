@@ -102,8 +102,8 @@ def _candidates(stage, nrhs, dtype):
             out.append(dict(rhs_tile=qt, transfer_mfma=1))
     if dtype != "c128":   # flat staging, one right-hand side per workgroup
         out += [dict(flat_stage=1), dict(flat_stage=1, whole_blocks=1)]
-    if nrhs <= 4:   # register fibers, one right-hand side per workgroup
-        out += [dict(flat_stage=2), dict(flat_stage=2, whole_blocks=1)]
+    if nrhs <= 4:   # register fibers, one right-hand side per workgroup; wave per leaf box
+        out += [dict(flat_stage=2), dict(flat_stage=2, whole_blocks=1), dict(flat_stage=3)]
     return out
 
 
