@@ -288,9 +288,10 @@ typedef struct {
                              workgroup: each mode product loads fibers of its contracted mode
                              into registers and reads the matrices from LDS; contracted
                              extents up to 32; slices, or whole blocks with whole_blocks = 1;
-                             3 = one wave per leaf box (leaf stages only, FP32 or FP64, leaf
-                             sizes 4, 8, 16): the box or the padded fine block, the padded
-                             matrices and the ranks requested in one memory round trip */
+                             3 = one workgroup per leaf box (leaf stages only, FP32 or FP64,
+                             leaf sizes 4, 8, 16), one wave, or four with whole_blocks = 1:
+                             the box or the padded fine block, the padded matrices and the
+                             ranks requested in one memory round trip */
 } tb_launch_cfg;
 
 /* Set the configuration of launch `slot` for applies of p with exactly this

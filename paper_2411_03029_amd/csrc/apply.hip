@@ -3485,7 +3485,8 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
   if (cfg.alt == 5) {  // leaves: one wave per leaf box
     int limit = 0;
     TB_TRY(lds_limit(&limit));
-    return launch_leaf_wave(sizeof(T) == 8, a, p.d, fanout, n_items, in, out, mats, stream, limit);
+    return launch_leaf_wave(sizeof(T) == 8, a, p.d, fanout, cfg.split == 1 ? 4 : 1, n_items, in, out, mats,
+                            stream, limit);
   }
   if (cfg.alt == 3) {  // flat staging, one right-hand side per workgroup
     if constexpr (sizeof(T) != 4) {
@@ -4176,9 +4177,12 @@ static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout, bool
       c.split = split;
       out.push_back(c);
     }
-    LaunchCfg w;  // leaves: one wave per box (transfer levels reject it)
-    w.alt = 5;
-    out.push_back(w);
+    for (int split : {0, 1}) {  // leaves: one workgroup of 1 or 4 waves per box (transfers reject it)
+      LaunchCfg w;
+      w.alt = 5;
+      w.split = split;
+      out.push_back(w);
+    }
   }
   return out;
 }

@@ -262,11 +262,12 @@ constexpr int kFibMaxLen = 32;
 tb_status launch_stage_fib(bool fp64, const StageArgs& a, int d, bool fanout, int xm, long long nwg,
                            size_t lds, const void* in, void* out, const void* mats, hipStream_t stream);
 
-// Leaf stages with one wave per leaf box (stage_leaf.hip), FP32 or FP64, one
-// right-hand side per wave; leaf sizes 4, 8 and 16.
+// Leaf stages with one workgroup of 1 or 4 waves per leaf box
+// (stage_leaf.hip), FP32 or FP64, one right-hand side per workgroup; leaf
+// sizes 4, 8 and 16.
 long long leaf_wave_lds_elems(const StageArgs& a, int d, bool fanout);
-tb_status launch_leaf_wave(bool fp64, const StageArgs& a, int d, bool fanout, int n_items, const void* in,
-                           void* out, const void* mats, hipStream_t stream, int lds_limit);
+tb_status launch_leaf_wave(bool fp64, const StageArgs& a, int d, bool fanout, int waves, int n_items,
+                           const void* in, void* out, const void* mats, hipStream_t stream, int lds_limit);
 
 // Generic apply for any number of modes (apply_generic.hip): per-workgroup
 // scratch in global memory, FP64 (fp64) or FP32.

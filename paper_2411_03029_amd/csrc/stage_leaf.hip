@@ -32,8 +32,8 @@ __device__ __forceinline__ C cmask(C v, bool keep) {
 }
 
 // ------------------------------------------------------------- fan-out --
-template <class T, int D, int AL>
-__global__ void __launch_bounds__(kWave)
+template <class T, int D, int AL, int NT>
+__global__ void __launch_bounds__(NT)
     leaf_fanout_wave(StageArgs a, const typename CplxOf<T>::type* __restrict__ box,
                      typename CplxOf<T>::type* __restrict__ fine,
                      const typename CplxOf<T>::type* __restrict__ mats) {
@@ -59,12 +59,12 @@ __global__ void __launch_bounds__(kWave)
   C* M2 = M1 + R1 * AL;
   C* T1 = M2 + (D == 3 ? R2 * AL : 0);
   constexpr int kRows = D == 3 ? AL * AL : AL;   // box rows along the last mode
-  constexpr int kRowsPerLane = (kRows + kWave - 1) / kWave;
+  constexpr int kRowsPerLane = (kRows + NT - 1) / NT;
   // the box rows, the matrices and the ranks: one round trip
   C x[kRowsPerLane][AL];
 #pragma unroll
   for (int i = 0; i < kRowsPerLane; ++i) {
-    const int row = lane + i * kWave;
+    const int row = lane + i * NT;
     if (row < kRows) {
       long long base = ca.base;
       if constexpr (D == 3)
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(kWave)
   {
     const C* mb = mats + (long long)fi * a.mat_item_stride;
     const int n0 = R0 * AL, n1 = R1 * AL, n2 = D == 3 ? R2 * AL : 0;
-    for (int e = lane; e < n0 + n1 + n2; e += kWave) {
+    for (int e = lane; e < n0 + n1 + n2; e += NT) {
       C v;
       if (e < n0)
         v = mb[a.mat_k_off[0] + (long long)beta[0] * R0 * AL + e];
@@ -90,12 +90,12 @@ __global__ void __launch_bounds__(kWave)
       sm[e] = v;
     }
   }
-  __syncthreads();  // one wave: orders the LDS stores before the reads
+  __syncthreads();
   if constexpr (D == 3) {
     // T1[p0][p1][a2] = sum_p2 M2[a2][p2] box[p0][p1][p2]
 #pragma unroll
     for (int i = 0; i < kRowsPerLane; ++i) {
-      const int row = lane + i * kWave;
+      const int row = lane + i * NT;
       if (row < kRows)
         for (int a2 = 0; a2 < r[2]; ++a2) {
           C acc = czero<C>();
@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(kWave)
     __syncthreads();
     // T2[p0][a1][a2] = sum_p1 M1[a1][p1] T1[p0][p1][a2]
     C* T2 = T1 + AL * AL * R2;
-    for (int it = lane; it < AL * r[2]; it += kWave) {
+    for (int it = lane; it < AL * r[2]; it += NT) {
       const int p0 = it / r[2], a2 = it % r[2];
       C t[AL];
 #pragma unroll
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(kWave)
     }
     __syncthreads();
     // fine[a0][a1][a2] = sum_p0 M0[a0][p0] T2[p0][a1][a2], true entries only
-    for (int it = lane; it < r[1] * r[2]; it += kWave) {
+    for (int it = lane; it < r[1] * r[2]; it += NT) {
       const int a1 = it / r[2], a2 = it % r[2];
       C t[AL];
 #pragma unroll
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(kWave)
     // T1[p0][a1] = sum_p1 M1[a1][p1] box[p0][p1]
 #pragma unroll
     for (int i = 0; i < kRowsPerLane; ++i) {
-      const int row = lane + i * kWave;
+      const int row = lane + i * NT;
       if (row < kRows)
         for (int a1 = 0; a1 < r[1]; ++a1) {
           C acc = czero<C>();
@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kWave)
     }
     __syncthreads();
     // fine[a0][a1] = sum_p0 M0[a0][p0] T1[p0][a1]
-    for (int a1 = lane; a1 < r[1]; a1 += kWave) {
+    for (int a1 = lane; a1 < r[1]; a1 += NT) {
       C t[AL];
 #pragma unroll
       for (int p = 0; p < AL; ++p) t[p] = T1[p * R1 + a1];
@@ -165,8 +165,8 @@ __global__ void __launch_bounds__(kWave)
 }
 
 // -------------------------------------------------------------- fan-in --
-template <class T, int D, int AL>
-__global__ void __launch_bounds__(kWave)
+template <class T, int D, int AL, int NT>
+__global__ void __launch_bounds__(NT)
     leaf_fanin_wave(StageArgs a, const typename CplxOf<T>::type* __restrict__ fine,
                     typename CplxOf<T>::type* __restrict__ box,
                     const typename CplxOf<T>::type* __restrict__ mats) {
@@ -194,12 +194,12 @@ __global__ void __launch_bounds__(kWave)
   // true ranks are read but masked), the matrices and the ranks: one round
   // trip; AL >= every padded rank
   constexpr int kFib = D == 3 ? AL * AL : AL;
-  constexpr int kFibPerLane = (kFib + kWave - 1) / kWave;
+  constexpr int kFibPerLane = (kFib + NT - 1) / NT;
   C x[kFibPerLane][AL];
   const int nfib = R1 * R2;
 #pragma unroll
   for (int i = 0; i < kFibPerLane; ++i) {
-    const int f = lane + i * kWave;
+    const int f = lane + i * NT;
     if (f < nfib) {
       const int a1 = f / R2, a2 = f % R2;
       const C* src = fine + fb + (long long)a1 * fs[1] + (D == 3 ? (long long)a2 * fs[D - 1] : 0);
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(kWave)
   {
     const C* mb = mats + (long long)fi * a.mat_item_stride;
     const int n0 = R0 * AL, n1 = R1 * AL, n2 = D == 3 ? R2 * AL : 0;
-    for (int e = lane; e < n0 + n1 + n2; e += kWave) {
+    for (int e = lane; e < n0 + n1 + n2; e += NT) {
       C v;
       if (e < n0)
         v = mb[a.mat_k_off[0] + (long long)beta[0] * R0 * AL + e];
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(kWave)
     // T1[p0][a1][a2] = sum_a0 M0[a0][p0] fine[a0][a1][a2]
 #pragma unroll
     for (int i = 0; i < kFibPerLane; ++i) {
-      const int f = lane + i * kWave;
+      const int f = lane + i * NT;
       const int a1 = f / R2, a2 = f % R2;
       if (f < nfib && a1 < r[1] && a2 < r[2]) {  // true entries only from here on
 #pragma unroll
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(kWave)
     __syncthreads();
     // T2[p0][p1][a2] = sum_a1 M1[a1][p1] T1[p0][a1][a2]
     C* T2 = T1 + AL * R1 * R2;
-    for (int it = lane; it < AL * r[2]; it += kWave) {
+    for (int it = lane; it < AL * r[2]; it += NT) {
       const int p0 = it / r[2], a2 = it % r[2];
       C t[AL];
 #pragma unroll
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(kWave)
     }
     __syncthreads();
     // box[p0][p1][p2] = sum_a2 M2[a2][p2] T2[p0][p1][a2]: one row per lane
-    for (int row = lane; row < AL * AL; row += kWave) {
+    for (int row = lane; row < AL * AL; row += NT) {
       C t[AL];
 #pragma unroll
       for (int j = 0; j < AL; ++j) t[j] = j < r[2] ? T2[row * R2 + j] : czero<C>();
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(kWave)
     // T1[p0][a1] = sum_a0 M0[a0][p0] fine[a0][a1]
 #pragma unroll
     for (int i = 0; i < kFibPerLane; ++i) {
-      const int a1 = lane + i * kWave;
+      const int a1 = lane + i * NT;
       if (a1 < nfib && a1 < r[1]) {  // true entries only from here on
 #pragma unroll
         for (int j = 0; j < AL; ++j) x[i][j] = cmask(x[i][j], j < r[0]);
@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(kWave)
     }
     __syncthreads();
     // box[p0][p1] = sum_a1 M1[a1][p1] T1[p0][a1]
-    for (int p0 = lane; p0 < AL; p0 += kWave) {
+    for (int p0 = lane; p0 < AL; p0 += NT) {
       C t[AL];
 #pragma unroll
       for (int j = 0; j < AL; ++j) t[j] = j < r[1] ? T1[p0 * R1 + j] : czero<C>();
@@ -320,36 +320,43 @@ long long leaf_wave_lds_elems(const StageArgs& a, int d, bool fanout) {
   return e;
 }
 
-template <class T, int D, int AL>
+template <class T, int D, int AL, int NT>
 static tb_status leaf_go(const StageArgs& a, bool fanout, long long nwg, size_t lds, const void* in, void* out,
                          const void* mats, hipStream_t stream) {
   using C = typename CplxOf<T>::type;
-  const void* k = fanout ? reinterpret_cast<const void*>(leaf_fanout_wave<T, D, AL>)
-                         : reinterpret_cast<const void*>(leaf_fanin_wave<T, D, AL>);
+  const void* k = fanout ? reinterpret_cast<const void*>(leaf_fanout_wave<T, D, AL, NT>)
+                         : reinterpret_cast<const void*>(leaf_fanin_wave<T, D, AL, NT>);
   if (lds > 65536)
     TB_HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   const dim3 grid((unsigned)nwg);
   if (fanout)
-    leaf_fanout_wave<T, D, AL><<<grid, kWave, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+    leaf_fanout_wave<T, D, AL, NT><<<grid, NT, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
   else
-    leaf_fanin_wave<T, D, AL><<<grid, kWave, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
+    leaf_fanin_wave<T, D, AL, NT><<<grid, NT, lds, stream>>>(a, (const C*)in, (C*)out, (const C*)mats);
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;
 }
 
-template <class T, int D>
+template <class T, int D, int NT>
 static tb_status leaf_go_al(const StageArgs& a, bool fanout, long long nwg, size_t lds, const void* in,
                             void* out, const void* mats, hipStream_t stream) {
   switch (a.A[0]) {
-    case 4: return leaf_go<T, D, 4>(a, fanout, nwg, lds, in, out, mats, stream);
-    case 8: return leaf_go<T, D, 8>(a, fanout, nwg, lds, in, out, mats, stream);
-    case 16: return leaf_go<T, D, 16>(a, fanout, nwg, lds, in, out, mats, stream);
+    case 4: return leaf_go<T, D, 4, NT>(a, fanout, nwg, lds, in, out, mats, stream);
+    case 8: return leaf_go<T, D, 8, NT>(a, fanout, nwg, lds, in, out, mats, stream);
+    case 16: return leaf_go<T, D, 16, NT>(a, fanout, nwg, lds, in, out, mats, stream);
   }
   return fail(TB_ERR_UNSUPPORTED, "wave-per-box leaves take leaf sizes 4, 8 and 16");
 }
 
-tb_status launch_leaf_wave(bool fp64, const StageArgs& a, int d, bool fanout, int n_items, const void* in,
-                           void* out, const void* mats, hipStream_t stream, int lds_limit) {
+template <class T, int D>
+static tb_status leaf_go_nt(const StageArgs& a, bool fanout, int waves, long long nwg, size_t lds,
+                            const void* in, void* out, const void* mats, hipStream_t stream) {
+  return waves == 4 ? leaf_go_al<T, D, 4 * kWave>(a, fanout, nwg, lds, in, out, mats, stream)
+                    : leaf_go_al<T, D, kWave>(a, fanout, nwg, lds, in, out, mats, stream);
+}
+
+tb_status launch_leaf_wave(bool fp64, const StageArgs& a, int d, bool fanout, int waves, int n_items,
+                           const void* in, void* out, const void* mats, hipStream_t stream, int lds_limit) {
   if (!a.coarse_global) return fail(TB_ERR_UNSUPPORTED, "wave-per-box kernels run the leaf stages only");
   for (int k = 0; k < d; ++k)
     if (a.A[k] != a.A[0] || a.R[k] > a.A[0])
@@ -363,10 +370,10 @@ tb_status launch_leaf_wave(bool fp64, const StageArgs& a, int d, bool fanout, in
   const long long nwg = (long long)n_items * a.nblk * a.nrhs;
   if (nwg < 1 || nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many workgroups for one launch");
   if (d == 2)
-    return fp64 ? leaf_go_al<double, 2>(b, fanout, nwg, lds, in, out, mats, stream)
-                : leaf_go_al<float, 2>(b, fanout, nwg, lds, in, out, mats, stream);
-  return fp64 ? leaf_go_al<double, 3>(b, fanout, nwg, lds, in, out, mats, stream)
-              : leaf_go_al<float, 3>(b, fanout, nwg, lds, in, out, mats, stream);
+    return fp64 ? leaf_go_nt<double, 2>(b, fanout, waves, nwg, lds, in, out, mats, stream)
+                : leaf_go_nt<float, 2>(b, fanout, waves, nwg, lds, in, out, mats, stream);
+  return fp64 ? leaf_go_nt<double, 3>(b, fanout, waves, nwg, lds, in, out, mats, stream)
+              : leaf_go_nt<float, 3>(b, fanout, waves, nwg, lds, in, out, mats, stream);
 }
 
 }  // namespace tb

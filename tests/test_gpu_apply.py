@@ -144,20 +144,21 @@ LEAF16 = {"fourier2_n64_leaf16": (kernels.FOURIER, 2, 64, 1e-6, 16),
 @pytest.mark.parametrize("name", list(CASES) + list(LEAF16))
 def test_wave_per_box_leaves_match_oracle(name, tmp_path):
     # the four leaf launches (source and target, both directions) on the
-    # one-wave-per-box kernels; leaf sizes 4, 8 and 16
+    # box-per-workgroup kernels (one wave or four); leaf sizes 4, 8 and 16
     torch = torch_gpu()
     op = oracle_plan(name)
     plan = gpu_plan(name, tmp_path)
     n, d = op.n, op.d
     slots = [s for s, st in enumerate(plan.launch_slots()) if "leaf" in st]
     assert len(slots) == 4
-    for dt, cdt, bound, nrhs in (("c128", torch.complex128, 1e-12, 2), ("c64", torch.complex64, 2e-5, 1),
-                                 ("c64", torch.complex64, 2e-5, 3)):
-        for s in slots:
-            plan.set_launch(nrhs, s, dtype=dt, flat_stage=3)
+    for (dt, cdt, bound, nrhs), waves4 in zip(
+            (("c128", torch.complex128, 1e-12, 2), ("c64", torch.complex64, 2e-5, 1),
+             ("c64", torch.complex64, 2e-5, 3), ("c64", torch.complex64, 2e-5, 2)), (0, 0, 1, 1)):
+        for s in slots:   # one wave per box, or four (whole_blocks = 1)
+            plan.set_launch(nrhs, s, dtype=dt, flat_stage=3, whole_blocks=waves4)
         f = inputs.rhs_batch(n, d, nrhs, config=94)
         x = to_dev(f, cdt)
-        say(f"[gpu] wave-per-box leaves {name} {dt} nrhs={nrhs}")
+        say(f"[gpu] wave-per-box leaves {name} {dt} nrhs={nrhs} four waves={waves4}")
         u = to_host(plan.apply(x, dtype=dt))
         v = to_host(plan.apply_adjoint(x, dtype=dt))
         torch.cuda.synchronize()

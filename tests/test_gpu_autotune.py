@@ -103,7 +103,8 @@ def _candidates(stage, nrhs, dtype):
     if dtype != "c128":   # flat staging, one right-hand side per workgroup
         out += [dict(flat_stage=1), dict(flat_stage=1, whole_blocks=1)]
     if nrhs <= 4:   # register fibers, one right-hand side per workgroup; wave per leaf box
-        out += [dict(flat_stage=2), dict(flat_stage=2, whole_blocks=1), dict(flat_stage=3)]
+        out += [dict(flat_stage=2), dict(flat_stage=2, whole_blocks=1), dict(flat_stage=3),
+                dict(flat_stage=3, whole_blocks=1)]
     return out
 
 
