@@ -308,7 +308,7 @@ def summarize_counters(sq_dir, fetch_dir, write_dir, copy_fetch_dir, copy_write_
              "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
     rows = []
     for (name, nwg), g in sq.items():
-        if g["n"] < min_dispatches or not ("stage_" in name or "core_" in name):
+        if g["n"] < min_dispatches or not ("stage_" in name or "core_" in name or "leaf_" in name):
             continue
         n = g["n"]
         c = {k: v / n for k, v in g["c"].items()}
