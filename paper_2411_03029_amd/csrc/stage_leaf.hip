@@ -1,4 +1,5 @@
-// Leaf stages with one wave per leaf box, one right-hand side per wave
+// Leaf stages with one workgroup per leaf box and right-hand side, of one
+// wave or four (NT threads; the kernels keep the names of the one-wave form)
 // (Algorithm 2 steps 1 and 3: the source leaf V and the target leaf U, and
 // the same stages of the adjoint).
 //
@@ -6,9 +7,10 @@
 // matrices are stored zero-padded to the level's largest rank, so every
 // address a leaf stage reads is known before its ranks are: the box (or the
 // padded fine block) and the three padded matrices are requested together
-// with the ranks, in one memory round trip.  The mode products then run in
-// one wave, through LDS, with no workgroup barrier, over the true ranks
-// only: intermediates at padded positions are neither written nor read.
+// with the ranks, in one memory round trip.  The mode products then run
+// through LDS over the true ranks only (intermediates at padded positions
+// are neither written nor read); with one wave the barriers between them
+// cost next to nothing.
 //
 //   fan-out (source leaf; target leaf of the adjoint): fine(a) = sum_p
 //     M_0[a_0][p_0] .. M_{D-1}[a_{D-1}][p_{D-1}] box(p), the last mode first;
