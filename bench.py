@@ -214,19 +214,41 @@ def _counter_per_dispatch(directory: str, counter: str, name_part: str) -> float
     return sum(vals.values()) / len(vals)
 
 
-def summarize_stats(trace_dir, workload, command) -> int:
+# construction kernels (interpolative decompositions, core evaluation and
+# encoding): left out of the apply statistics of the batched workloads
+CONSTRUCTION_KERNELS = ("id_kernel", "core_eval", "core_encode")
+
+
+def summarize_stats(trace_dir, workload, command, exclude=()) -> int:
     """profiles/kernel_stats_<workload>.md from rocprofv3 --kernel-trace
-    --stats CSV output (autotuning trials included: they run the same
-    kernels)."""
-    stats = _rocprof_rows(trace_dir, "kernel_stats.csv")
+    --stats CSV output; kernels whose name contains one of `exclude` are
+    dropped and the percentages taken over the rest."""
+    stats = [r for r in _rocprof_rows(trace_dir, "kernel_stats.csv")
+             if not any(e in r["Name"] for e in exclude)]
     lines = [f"# rocprofv3 kernel statistics: workload {workload}", "",
-             f"command: {command}", "",
-             "| kernel | calls | total (us) | average (us) | percent |", "|---|---|---|---|---|"]
+             f"command: {command}", ""]
+    if exclude:
+        # torch's own kernels (input generation, the step's vector updates,
+        # norms) are summed into one row
+        torch_rows = [r for r in stats if "at::native" in r["Name"] or "abs_kernel" in r["Name"]
+                      or not r["Name"].strip()]
+        stats = [r for r in stats if r not in torch_rows]
+        if torch_rows:
+            tot = sum(float(r["TotalDurationNs"]) for r in torch_rows)
+            calls = sum(int(r["Calls"]) for r in torch_rows)
+            stats.append({"Name": "torch kernels: input generation, vector updates, norms",
+                          "Calls": str(calls), "TotalDurationNs": str(tot),
+                          "AverageNs": str(tot / max(calls, 1))})
+        lines += [f"Construction kernels left out ({', '.join(exclude)}); torch's own kernels "
+                  "summed in one row; percentages are of the kernel time listed.", ""]
+    total = sum(float(r["TotalDurationNs"]) for r in stats) or 1.0
+    lines += ["| kernel | calls | total (us) | average (us) | percent |", "|---|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0))):
         name = r["Name"]
         short = name.split("(")[0].replace("void ", "")
         lines.append(f"| {short} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
-                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['Percentage']):.1f} |")
+                     f"{float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{100 * float(r['TotalDurationNs']) / total:.1f} |")
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"kernel_stats_{workload}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -662,6 +684,11 @@ def run_mix(args, tb, inputs, torch, np) -> dict:
         return time.perf_counter() - t, xs, us
 
     t_bf, _, _ = timed("cbf16", torch.complex64, args.steps, args.warmup)
+    if args.timed_only:
+        return _line(
+            args, "tb_apply_batched n^d·RHS points/s (fwd+adjoint), uneven multi-operator mix",
+            points * args.steps / t_bf, "points/s", 1000 * t_bf / args.steps, "bf16",
+            {"workload": args.workload, "nrhs": counts, "timed_only": True}, cpu_baseline=None)
     t_32, _, _ = timed("c64", torch.complex64, args.steps, args.warmup)
     t_64, _, _ = timed("c128", torch.complex128, max(1, args.steps // 4), args.warmup)
     s64 = max(1, args.steps // 4)
@@ -802,6 +829,11 @@ def run_lsq(args, tb, inputs, torch, np) -> dict:
         step()
     torch.cuda.synchronize()
     t = time.perf_counter() - t
+    if args.timed_only:
+        return _line(
+            args, "least-squares gradient steps, n^d·RHS points/s (K f - b, K^H r)",
+            nrhs * n ** d * args.steps / t, "points/s", 1000 * t / args.steps, "f32",
+            {"workload": args.workload, "nrhs": nrhs, "timed_only": True}, cpu_baseline=None)
     loss1 = float((plan.apply(f) - b).abs().pow(2).sum())
 
     # accuracy of K f_true against the exact operator (FFT convolution), 2 RHS
@@ -870,6 +902,11 @@ def main() -> int:
                          "output: SQ counters, FETCH_SIZE, WRITE_SIZE, copy FETCH_SIZE, copy WRITE_SIZE")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="write profiles/kernel_stats_<workload>.md from a rocprofv3 trace dir")
+    ap.add_argument("--apply-only-stats", action="store_true",
+                    help="--summarize-stats: leave the construction kernels out")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="uneven_mix_bf16, helmholtz_cubes_n128_lsq: run only the timed steps of "
+                         "the headline precision (for kernel traces)")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--commands-json", default="{}")
     args = ap.parse_args()
@@ -879,7 +916,8 @@ def main() -> int:
         return summarize_counters(*args.summarize_counters, args.copy_bytes, args.workload,
                                   json.loads(args.commands_json))
     if args.summarize_stats:
-        return summarize_stats(args.summarize_stats, args.workload, args.commands_json)
+        return summarize_stats(args.summarize_stats, args.workload, args.commands_json,
+                               CONSTRUCTION_KERNELS if args.apply_only_stats else ())
     if args.summarize:
         return summarize(*args.summarize, args.copy_bytes, args.workload,
                          json.loads(args.commands_json))
