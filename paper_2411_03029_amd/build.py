@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtb.so")
 SOURCES = ["plan.cpp", "apply.hip", "construct.hip", "stage_flat.hip", "apply_generic.hip",
-           "stage_fiber.hip", "stage_leaf.hip"]
+           "stage_fiber.hip", "stage_leaf.hip", "stage_mfma4.hip"]
 ARCH = os.environ.get("TB_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

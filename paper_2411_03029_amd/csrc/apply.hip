@@ -3498,6 +3498,14 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
                                    limit);
     }
   }
+  if (cfg.mfma == 2) {  // fan-in on 4 x 4 matrix-core blocks, d = 3
+    if constexpr (sizeof(T) != 4) {
+      return fail(TB_ERR_UNSUPPORTED, "the matrix-core fan-in is FP32 only");
+    } else {
+      if (fanout) return fail(TB_ERR_UNSUPPORTED, "the 4 x 4 matrix-core form is a fan-in");
+      return launch_fanin_m4(a, p.d, n_items, in, out, mats, stream);
+    }
+  }
   if (cfg.mfma == 1) return launch_stage_xmfma<T>(p, a, fanout, n_items, in, out, mats, stream, cfg);
   if (cfg.alt == 1 || cfg.alt == 2) {
     if (fanout) return fail(TB_ERR_UNSUPPORTED, "no in-turn variant of the fan-out");
@@ -4163,6 +4171,11 @@ static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout, bool
       out.push_back(c);
     }
   }
+  if (fp32 && !fanout && nrhs >= 2) {  // fan-in on 4 x 4 matrix-core blocks (d = 3 transfers)
+    LaunchCfg c;
+    c.mfma = 2;
+    out.push_back(c);
+  }
   if (fp32)
     for (int split : {0, 1}) {  // flat staging, one right-hand side per workgroup
       LaunchCfg c;
@@ -4566,7 +4579,7 @@ extern "C" tb_status tb_plan_set_launch(tb_plan ph, long long nrhs, tb_dtype io,
   const int g = cfg->outputs_per_thread, q = cfg->rhs_tile;
   if (!(g == 0 || g == 1 || g == 8) || !(q == 0 || q == 1 || q == 2 || q == 4 || q == 8) ||
       cfg->whole_blocks < 0 || cfg->whole_blocks > 1 || cfg->core_kernel < 0 || cfg->core_kernel > 9 ||
-      cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 2 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 1 ||
+      cfg->fanin_in_turn < 0 || cfg->fanin_in_turn > 2 || cfg->transfer_mfma < 0 || cfg->transfer_mfma > 2 ||
       !(cfg->rhs_per_thread == 0 || cfg->rhs_per_thread == 1 || cfg->rhs_per_thread == 4) ||
       cfg->flat_stage < 0 || cfg->flat_stage > 3 || (cfg->flat_stage && cfg->fanin_in_turn))
     return tb::fail(TB_ERR_INVALID_ARG, "launch configuration field out of range");

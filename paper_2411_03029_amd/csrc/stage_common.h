@@ -269,6 +269,13 @@ long long leaf_wave_lds_elems(const StageArgs& a, int d, bool fanout);
 tb_status launch_leaf_wave(bool fp64, const StageArgs& a, int d, bool fanout, int waves, int n_items,
                            const void* in, void* out, const void* mats, hipStream_t stream, int lds_limit);
 
+// Fan-in transfer stage on the matrix cores (stage_mfma4.hip), d = 3, FP32:
+// four right-hand sides per workgroup on 4 x 4 matrix-core blocks, the
+// children in turn, the coarse block accumulated in registers; fine ranks
+// up to 8 and coarse blocks up to 16 per mode, transfer levels only.
+tb_status launch_fanin_m4(const StageArgs& a, int d, int n_items, const void* in, void* out,
+                          const void* mats, hipStream_t stream);
+
 // Generic apply for any number of modes (apply_generic.hip): per-workgroup
 // scratch in global memory, FP64 (fp64) or FP32.
 struct GenCoreArgs {

@@ -1,0 +1,322 @@
+// Fan-in transfer stage on the matrix cores, d = 3, FP32 (Algorithm 2 step
+// 3: the 2^d children's tensors carried into their parent block, target side
+// of the forward apply; with M^H, the source side of the adjoint).
+//
+//   coarse(a_0, a_1, a_2, q) = sum_children sum_j M0_c[j_0][a_0] M1_c[j_1][a_1]
+//                              M2_c[j_2][a_2] fine_c(j_0, j_1, j_2, q)
+//
+// One workgroup of four waves takes one coarse block and four right-hand
+// sides.  Every mode product runs on v_mfma_f32_4x4x1f32: one instruction
+// forms 16 independent 4 x 4 outer products, each of four entries of one
+// matrix column (four rows of the output mode) with one input entry of the
+// four right-hand sides.  A block of the instruction is one position of the
+// two modes not being contracted, so the contracted mode needs no padding
+// (K = 1) and the output mode is padded only to a multiple of four.  A
+// complex product is four real instructions.
+//
+// The children are taken in turn.  Per child: mode 0 reads its input from
+// global memory into registers (issued one child ahead, so the loads overlap
+// the previous child's products) and writes LDS; then each wave takes its
+// a_0 rows (w, w + 4, ..) one at a time through mode 1, into LDS of its own,
+// and mode 2, into accumulators that stay in registers for the whole block
+// (16 x 16 x 16 entries of four right-hand sides over 256 lanes: 32 complex
+// values per lane).  Two workgroup barriers per child.  The
+// matrices of all eight children come into LDS at the start, in the same
+// memory round trip as the ranks: they are staged at their padded columns,
+// so their addresses do not depend on any rank.
+//
+// Limits (the host rejects other blocks): fine ranks up to 8 per mode,
+// coarse blocks up to 16 per mode, coarse output an intermediate level (not
+// the caller's array).
+#include <hip/hip_runtime.h>
+
+#include "stage_common.h"
+
+namespace tb {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kR = 8;    // largest padded fine rank per mode
+constexpr int kC = 16;   // largest coarse block extent per mode
+constexpr int kQ = 4;    // right-hand sides per workgroup
+constexpr int kNch = 8;  // children of a coarse block (2^3)
+
+__device__ __forceinline__ v4f mf(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+struct CAcc {
+  v4f re, im;
+};
+
+__device__ __forceinline__ void czero4(CAcc& d) {
+  d.re = v4f{0.f, 0.f, 0.f, 0.f};
+  d.im = v4f{0.f, 0.f, 0.f, 0.f};
+}
+
+// column of the padded matrix that holds compact coarse entry e of mode k,
+// for an output row past the true extent column 0 (its results are dropped)
+__device__ __forceinline__ int pcol(const Seg& s, int e) { return e < s.c ? s.pos(e) : 0; }
+
+// d[t] += M[k][col[t]] (x) x_k over k < nk for NT tiles of four output rows:
+// x_k = src[k * xs] is this lane's input entry (its block's position, its
+// right-hand side), M[k][col[t]] the matrix entry of its row in tile t.
+// The tile count is a template parameter so that no branch separates the
+// matrix-core instructions; the four real products of the tiles are
+// interleaved so that consecutive instructions use different accumulators.
+template <int NT>
+__device__ __forceinline__ void tiles_lds(CAcc (&d)[4], const float2* src, int xs, const float2* M,
+                                          const int (&col)[4], int nk) {
+  for (int k = 0; k < nk; ++k) {
+    const float2 x = src[k * xs];
+    float2 m[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) m[t] = M[k * kC + col[t]];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) d[t].re = mf(m[t].x, x.x, d[t].re);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) d[t].im = mf(m[t].x, x.y, d[t].im);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) d[t].re = mf(-m[t].y, x.y, d[t].re);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) d[t].im = mf(m[t].y, x.x, d[t].im);
+  }
+}
+
+__device__ __forceinline__ void tiles_lds_n(int nt, CAcc (&d)[4], const float2* src, int xs, const float2* M,
+                                            const int (&col)[4], int nk) {
+  switch (nt) {
+    case 1: tiles_lds<1>(d, src, xs, M, col, nk); break;
+    case 2: tiles_lds<2>(d, src, xs, M, col, nk); break;
+    case 3: tiles_lds<3>(d, src, xs, M, col, nk); break;
+    default: tiles_lds<4>(d, src, xs, M, col, nk); break;
+  }
+}
+
+// the same with the input entries in registers (b[k], k < nk <= kR)
+template <int NT>
+__device__ __forceinline__ void tiles_reg(CAcc (&d)[4], const float2 (&b)[kR], const float2* M,
+                                          const int (&col)[4], int nk) {
+#pragma unroll
+  for (int k = 0; k < kR; ++k) {
+    if (k < nk) {
+      float2 m[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) m[t] = M[k * kC + col[t]];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) d[t].re = mf(m[t].x, b[k].x, d[t].re);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) d[t].im = mf(m[t].x, b[k].y, d[t].im);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) d[t].re = mf(-m[t].y, b[k].y, d[t].re);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) d[t].im = mf(m[t].y, b[k].x, d[t].im);
+    }
+  }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(256, 2)
+    stage_fanin_m4(StageArgs a, const float2* __restrict__ fine, float2* __restrict__ coarse,
+                   const float2* __restrict__ mats) {
+  __shared__ float2 smat[kNch * 3 * kR * kC];  // [child][mode][row j][padded column]
+  __shared__ float2 sbuf1[kC * kR * kR * kQ];  // mode 0 output [a0][j1][j2][q]
+  __shared__ float2 sbuf2[4 * kR * kC * kQ];   // mode 1 output of one a_0 row per wave [w][j2][a1][q]
+  __shared__ int srk[kNch][3];
+
+  const StageBid sb = stage_bid(a, kQ);
+  const int ci = sb.item_blk / a.nblk;
+  int beta[3];
+  unflatten_blk<3>(sb.item_blk % a.nblk, a.nb, beta);
+  Seg sg[3];
+  coarse_segs<3>(a, ci, beta, sg);
+  const int q0 = sb.q0;
+  const int Qa = min(kQ, a.nrhs - q0);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int blk = lane >> 2, qn = lane & 3;
+  const int qc = min(qn, Qa - 1);
+  const int R0 = a.R[0], R1 = a.R[1], R2 = a.R[2];
+  long long fs[3];
+  (void)fine_base<3>(a, 0, beta, 0, fs);  // strides only
+
+  // this lane's mode-0 input of child c: rows j0 < kR at position
+  // p = 16 w + blk of the padded (j1, j2) grid, right-hand side q0 + qc
+  auto load_b = [&](int c, float2 (&b)[kR]) {
+    const int fi = child_of<3>(ci, a.lvl, c);
+    long long f_[3];
+    const long long base = fine_base<3>(a, fi, beta, q0, f_);
+    const int p = min(16 * w + blk, R1 * R2 - 1);
+    const float2* src = fine + base + (p / R2) * fs[1] + (p % R2) * fs[2] + qc;
+#pragma unroll
+    for (int k = 0; k < kR; ++k) b[k] = src[min(k, R0 - 1) * fs[0]];
+  };
+  float2 b[kR];
+  load_b(0, b);
+  // ranks of the children
+  int crank = 0;
+  if (tid < kNch * 3) {
+    const int c = tid / 3, k = tid % 3;
+    const int fi = child_of<3>(ci, a.lvl, c);
+    const int bk = k == 0 ? beta[0] : (k == 1 ? beta[1] : beta[2]);
+    crank = a.rank_f[((long long)fi * 3 + k) * a.nb + bk];
+  }
+  // every child's padded matrices, all loads in flight before any store:
+  // the first child's input, the ranks and the matrices take one memory
+  // round trip together
+  {
+    constexpr int kPer = kNch * 3 * kR * kC / 256;
+    float2 v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      const int c = e / (3 * kR * kC), k = (e / (kR * kC)) % 3, j = (e / kC) % kR, col = e % kC;
+      // the mode varies across lanes: select its sizes from the uniform
+      // arguments (indexing the argument arrays by it would read them from
+      // memory, one dependent load each)
+      const int Rk = k == 0 ? a.R[0] : (k == 1 ? a.R[1] : a.R[2]);
+      const int Ak = k == 0 ? a.A[0] : (k == 1 ? a.A[1] : a.A[2]);
+      const int bk = k == 0 ? beta[0] : (k == 1 ? beta[1] : beta[2]);
+      const long long ok = k == 0 ? a.mat_k_off[0] : (k == 1 ? a.mat_k_off[1] : a.mat_k_off[2]);
+      v[u] = make_float2(0.f, 0.f);
+      if (j < Rk && col < Ak) {
+        const int fi = child_of<3>(ci, a.lvl, c);
+        v[u] = mats[(long long)fi * a.mat_item_stride + ok + ((long long)bk * Rk + j) * Ak + col];
+      }
+    }
+    if (sg[0].c <= 0 || sg[1].c <= 0 || sg[2].c <= 0) return;  // no entries (uniform, before any barrier)
+    if (tid < kNch * 3) srk[tid / 3][tid % 3] = crank;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      float2 x = v[u];
+      if (a.conj) x.y = -x.y;
+      smat[tid + 256 * u] = x;
+    }
+  }
+
+  const int c0 = sg[0].c, c1 = sg[1].c, c2 = sg[2].c;
+  const int nt0 = (c0 + 3) / 4, nt1 = (c1 + 3) / 4, nt2 = (c2 + 3) / 4;
+  int col0[4], col1[4], col2[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    col0[t] = pcol(sg[0], 4 * t + qn);
+    col1[t] = pcol(sg[1], 4 * t + qn);
+    col2[t] = pcol(sg[2], 4 * t + qn);
+  }
+  CAcc acc[4][4];  // [slice s: a0 = 4 s + w][tile t: a2 = 4 t + row]
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) czero4(acc[s][t]);
+  __syncthreads();  // ranks and matrices
+
+  for (int c = 0; c < kNch; ++c) {
+    const int r0 = srk[c][0], r1 = srk[c][1], r2 = srk[c][2];
+    // ---- mode 0: sbuf1[a0][j1][j2][q] = sum_j0 M0[j0][a0] fine(j0, j1, j2, q)
+    {
+      const float2* M0 = smat + (c * 3 + 0) * kR * kC;
+      const int p = 16 * w + blk;
+      if (16 * w < R1 * R2 && (16 * w) / R2 < r1) {
+        CAcc d[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) czero4(d[t]);
+        switch (nt0) {
+          case 1: tiles_reg<1>(d, b, M0, col0, r0); break;
+          case 2: tiles_reg<2>(d, b, M0, col0, r0); break;
+          case 3: tiles_reg<3>(d, b, M0, col0, r0); break;
+          default: tiles_reg<4>(d, b, M0, col0, r0); break;
+        }
+        const int j1 = p / R2, j2 = p % R2;
+        if (p < R1 * R2 && j1 < r1 && j2 < r2) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int a0 = 4 * t + v;
+              if (a0 < c0) sbuf1[((a0 * kR + j1) * kR + j2) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
+            }
+        }
+      }
+      if (c + 1 < kNch) load_b(c + 1, b);  // next child's input, in flight during modes 1 and 2
+    }
+    __syncthreads();
+    // ---- modes 1 and 2, one a_0 row at a time per wave (rows w, w + 4, ..):
+    // the row's mode-1 result goes to this wave's own LDS, so no workgroup
+    // barrier separates the two modes
+    const float2* M1 = smat + (c * 3 + 1) * kR * kC;
+    const float2* M2 = smat + (c * 3 + 2) * kR * kC;
+    float2* t1 = sbuf2 + w * kR * kC * kQ;  // [j2][a1][q] of this wave's row
+    if (r1 > 0 && r2 > 0) {  // a child of rank 0 adds nothing
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int a0 = 4 * s + w;
+        if (a0 < c0) {
+          // t1[j2][a1][q] = sum_j1 M1[j1][a1] sbuf1[a0][j1][j2][q], j2 = blk
+          CAcc d[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) czero4(d[t]);
+          tiles_lds_n(nt1, d, sbuf1 + (a0 * kR * kR + min(blk, r2 - 1)) * kQ + qn, kR * kQ, M1, col1, r1);
+          if (blk < r2) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int a1 = 4 * t + v;
+                if (a1 < c1) t1[(blk * kC + a1) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
+              }
+          }
+          // acc[s] += sum_j2 M2[j2][a2] t1[j2][a1][q], a1 = blk (the same wave
+          // wrote t1: its LDS operations complete in order)
+          tiles_lds_n(nt2, acc[s], t1 + min(blk, c1 - 1) * kQ + qn, kC * kQ, M2, col2, r2);
+        }
+      }
+    }
+    __syncthreads();  // sbuf1 is rewritten by the next child
+  }
+
+  // the block's true entries, once
+  CoarseAddr<3> ca;
+  ca.init(a, ci, beta, q0);
+  if (blk < c1 && qn < Qa) {
+    const long long rowb = ca.base + sg[1].pos(blk) * ca.stride[1] + qn;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int a0 = 4 * s + w;
+      if (a0 < c0) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int a2 = 4 * t + v;
+            if (a2 < c2)
+              coarse[rowb + sg[0].pos(a0) * ca.stride[0] + sg[2].pos(a2) * ca.stride[2]] =
+                  make_float2(acc[s][t].re[v], acc[s][t].im[v]);
+          }
+      }
+    }
+  }
+}
+
+tb_status launch_fanin_m4(const StageArgs& a, int d, int n_items, const void* in, void* out,
+                          const void* mats, hipStream_t stream) {
+  if (d != 3) return fail(TB_ERR_UNSUPPORTED, "the matrix-core fan-in is for d = 3");
+  if (a.coarse_global || a.rank_c == nullptr)
+    return fail(TB_ERR_UNSUPPORTED, "the matrix-core fan-in runs the transfer levels only");
+  for (int k = 0; k < 3; ++k)
+    if (a.R[k] > kR || a.A[k] > kC)
+      return fail(TB_ERR_UNSUPPORTED, "matrix-core fan-in: ranks above 8 or coarse blocks above 16");
+  StageArgs b = a;
+  b.nsplit = 1;
+  b.chunk = a.A[0];
+  b.aff_blocks = 0;
+  const long long nwg = (long long)n_items * a.nblk * ((a.nrhs + kQ - 1) / kQ);
+  if (nwg < 1 || nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many workgroups for one launch");
+  stage_fanin_m4<<<dim3((unsigned)nwg), 256, 0, stream>>>(b, (const float2*)in, (float2*)out,
+                                                          (const float2*)mats);
+  TB_HIP_TRY(hipGetLastError());
+  return TB_OK;
+}
+
+}  // namespace tb

@@ -137,6 +137,38 @@ def test_register_fiber_stages_match_oracle(name, tmp_path):
     assert "c64" in ran
 
 
+@pytest.mark.parametrize("name", [k for k, v in CASES.items() if v[1] == 3 and v[2] >= 16])
+def test_matrix_core_fanin_matches_oracle(name, tmp_path):
+    # every fan-in transfer launch (target side forward, source side adjoint)
+    # on the 4 x 4 matrix-core fan-in: four right-hand sides per workgroup,
+    # a ragged last group, and fewer right-hand sides than one group.  A plan
+    # whose ranks exceed 8 is rejected with TB_ERR_UNSUPPORTED; one within
+    # them must run it on every such slot
+    torch = torch_gpu()
+    import paper_2411_03029_amd as tb
+    op = oracle_plan(name)
+    plan = gpu_plan(name, tmp_path)
+    n, d = op.n, op.d
+    slots = [s for s, st in enumerate(plan.launch_slots()) if st in ("tgt_transfer", "src_transfer_adj")]
+    fits = plan.info()["r_max"] <= 8
+    for nrhs in (4, 7, 2):
+        for s in slots:
+            plan.set_launch(nrhs, s, dtype="c64", transfer_mfma=2)
+        f = inputs.rhs_batch(n, d, nrhs, config=95)
+        x = to_dev(f, torch.complex64)
+        say(f"[gpu] matrix-core fan-in {name} nrhs={nrhs} slots={slots}")
+        try:
+            u = to_host(plan.apply(x, dtype="c64"))
+            v = to_host(plan.apply_adjoint(x, dtype="c64"))
+            torch.cuda.synchronize()
+        except tb.TBError as e:
+            assert e.status == 2 and not fits, str(e)
+            continue
+        assert slots, "no fan-in transfer level"
+        assert_parity(u, bf.apply(op, f), 2e-5, f"forward nrhs={nrhs}")
+        assert_parity(v, bf.apply_adjoint(op, f), 2e-5, f"adjoint nrhs={nrhs}")
+
+
 LEAF16 = {"fourier2_n64_leaf16": (kernels.FOURIER, 2, 64, 1e-6, 16),
           "helm3_n32_leaf16": (kernels.HELMHOLTZ, 3, 32, 1e-4, 16)}
 
