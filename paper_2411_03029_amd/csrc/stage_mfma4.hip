@@ -229,14 +229,12 @@ __global__ void __launch_bounds__(256, 2)
           default: tiles_reg<4>(d, b, M0, col0, r0); break;
         }
         const int j1 = p / R2, j2 = p % R2;
-        if (p < R1 * R2 && j1 < r1 && j2 < r2) {
+        if (p < R1 * R2 && j1 < r1 && j2 < r2) {  // rows past c0 land in unread padding
 #pragma unroll
           for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int a0 = 4 * t + v;
-              if (a0 < c0) sbuf1[((a0 * kR + j1) * kR + j2) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
-            }
+            for (int v = 0; v < 4; ++v)
+              sbuf1[(((4 * t + v) * kR + j1) * kR + j2) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
         }
       }
       if (c + 1 < kNch) load_b(c + 1, b);  // next child's input, in flight during modes 1 and 2
@@ -258,14 +256,11 @@ __global__ void __launch_bounds__(256, 2)
 #pragma unroll
           for (int t = 0; t < 4; ++t) czero4(d[t]);
           tiles_lds_n(nt1, d, sbuf1 + (a0 * kR * kR + min(blk, r2 - 1)) * kQ + qn, kR * kQ, M1, col1, r1);
-          if (blk < r2) {
+          if (blk < r2) {  // rows past c1 land in unread padding
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const int a1 = 4 * t + v;
-                if (a1 < c1) t1[(blk * kC + a1) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
-              }
+              for (int v = 0; v < 4; ++v) t1[(blk * kC + 4 * t + v) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
           }
           // acc[s] += sum_j2 M2[j2][a2] t1[j2][a1][q], a1 = blk (the same wave
           // wrote t1: its LDS operations complete in order)
