@@ -198,11 +198,14 @@ __global__ void __launch_bounds__(256, 2)
 
   const int c0 = sg[0].c, c1 = sg[1].c, c2 = sg[2].c;
   const int nt0 = (c0 + 3) / 4, nt1 = (c1 + 3) / 4, nt2 = (c2 + 3) / 4;
-  int col0[4], col1[4], col2[4];
+  // mode 1 pairs tiles of a1 across the two halves of an instruction's
+  // blocks: block blk holds position j2h = blk % 8 of tile 2 tp + th
+  const int th = blk >> 3, j2h = blk & 7;
+  int col0[4], col1p[4], col2[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     col0[t] = pcol(sg[0], 4 * t + qn);
-    col1[t] = pcol(sg[1], 4 * t + qn);
+    col1p[t] = t < 2 ? pcol(sg[1], 4 * (2 * t + th) + qn) : 0;
     col2[t] = pcol(sg[2], 4 * t + qn);
   }
   CAcc acc[4][4];  // [slice s: a0 = 4 s + w][tile t: a2 = 4 t + row]
@@ -251,16 +254,20 @@ __global__ void __launch_bounds__(256, 2)
       for (int s = 0; s < 4; ++s) {
         const int a0 = 4 * s + w;
         if (a0 < c0) {
-          // t1[j2][a1][q] = sum_j1 M1[j1][a1] sbuf1[a0][j1][j2][q], j2 = blk
+          // t1[j2][a1][q] = sum_j1 M1[j1][a1] sbuf1[a0][j1][j2][q]: a row has at
+          // most 8 positions j2, so blocks 0-7 and 8-15 of an instruction take
+          // two different tiles of a1 (the matrix operand is per block)
           CAcc d[4];
 #pragma unroll
           for (int t = 0; t < 4; ++t) czero4(d[t]);
-          tiles_lds_n(nt1, d, sbuf1 + (a0 * kR * kR + min(blk, r2 - 1)) * kQ + qn, kR * kQ, M1, col1, r1);
-          if (blk < r2) {  // rows past c1 land in unread padding
+          tiles_lds_n((nt1 + 1) / 2, d, sbuf1 + (a0 * kR * kR + min(j2h, r2 - 1)) * kQ + qn, kR * kQ, M1,
+                      col1p, r1);
+          if (j2h < r2) {  // rows past c1 land in unread padding
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+            for (int tp = 0; tp < 2; ++tp)
 #pragma unroll
-              for (int v = 0; v < 4; ++v) t1[(blk * kC + 4 * t + v) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
+              for (int v = 0; v < 4; ++v)
+                t1[(j2h * kC + 4 * (2 * tp + th) + v) * kQ + qn] = make_float2(d[tp].re[v], d[tp].im[v]);
           }
           // acc[s] += sum_j2 M2[j2][a2] t1[j2][a1][q], a1 = blk (the same wave
           // wrote t1: its LDS operations complete in order)
