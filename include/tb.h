@@ -276,11 +276,12 @@ typedef struct {
                              2 = children in turn, first mode first, the coarse slice summed
                              in LDS (8 outputs per thread) */
   int transfer_mfma;      /* transfer levels (not the leaves), FP32 / BF16 applies: 1 = mode
-                             products on the matrix cores, one block per workgroup; 2 = fan-in
-                             levels with d = 3: the children in turn on 4 x 4 matrix-core
-                             blocks, four right-hand sides per workgroup, the coarse block
-                             accumulated in registers (fine ranks up to 8, coarse blocks up
-                             to 16 per mode) */
+                             products on the matrix cores, one block per workgroup; 2 = d = 3
+                             levels on 4 x 4 matrix-core blocks, four right-hand sides per
+                             workgroup (fine ranks up to 8, coarse blocks up to 16 per mode):
+                             fan-ins take the children in turn and accumulate the coarse
+                             block in registers, fan-outs take one fine block per workgroup
+                             of eight waves */
   int rhs_per_thread;     /* fan-out / fan-in kernels: 1 or 4 right-hand sides per thread
                              (4 needs a right-hand-side tile of 4 or 8) */
   int flat_stage;         /* transfer stages and leaves: 1 = flat staging (FP32 applies), one

@@ -3498,12 +3498,12 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
                                    limit);
     }
   }
-  if (cfg.mfma == 2) {  // fan-in on 4 x 4 matrix-core blocks, d = 3
+  if (cfg.mfma == 2) {  // transfer levels on 4 x 4 matrix-core blocks, d = 3
     if constexpr (sizeof(T) != 4) {
-      return fail(TB_ERR_UNSUPPORTED, "the matrix-core fan-in is FP32 only");
+      return fail(TB_ERR_UNSUPPORTED, "the 4 x 4 matrix-core transfers are FP32 only");
     } else {
-      if (fanout) return fail(TB_ERR_UNSUPPORTED, "the 4 x 4 matrix-core form is a fan-in");
-      return launch_fanin_m4(a, p.d, n_items, in, out, mats, stream);
+      return fanout ? launch_fanout_m4(a, p.d, n_items, in, out, mats, stream)
+                    : launch_fanin_m4(a, p.d, n_items, in, out, mats, stream);
     }
   }
   if (cfg.mfma == 1) return launch_stage_xmfma<T>(p, a, fanout, n_items, in, out, mats, stream, cfg);
@@ -4171,7 +4171,7 @@ static std::vector<LaunchCfg> stage_candidates(long long nrhs, bool fanout, bool
       out.push_back(c);
     }
   }
-  if (fp32 && !fanout && nrhs >= 2) {  // fan-in on 4 x 4 matrix-core blocks (d = 3 transfers)
+  if (fp32 && nrhs >= 2) {  // 4 x 4 matrix-core blocks (d = 3 transfer levels)
     LaunchCfg c;
     c.mfma = 2;
     out.push_back(c);

@@ -275,6 +275,10 @@ tb_status launch_leaf_wave(bool fp64, const StageArgs& a, int d, bool fanout, in
 // up to 8 and coarse blocks up to 16 per mode, transfer levels only.
 tb_status launch_fanin_m4(const StageArgs& a, int d, int n_items, const void* in, void* out,
                           const void* mats, hipStream_t stream);
+// The fan-out counterpart: one fine block and four right-hand sides per
+// workgroup of eight waves.
+tb_status launch_fanout_m4(const StageArgs& a, int d, int n_items, const void* in, void* out,
+                           const void* mats, hipStream_t stream);
 
 // Generic apply for any number of modes (apply_generic.hip): per-workgroup
 // scratch in global memory, FP64 (fp64) or FP32.

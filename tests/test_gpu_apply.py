@@ -138,25 +138,30 @@ def test_register_fiber_stages_match_oracle(name, tmp_path):
 
 
 @pytest.mark.parametrize("name", [k for k, v in CASES.items() if v[1] == 3 and v[2] >= 16])
-def test_matrix_core_fanin_matches_oracle(name, tmp_path):
-    # every fan-in transfer launch (target side forward, source side adjoint)
-    # on the 4 x 4 matrix-core fan-in: four right-hand sides per workgroup,
-    # a ragged last group, and fewer right-hand sides than one group.  A plan
-    # whose ranks exceed 8 is rejected with TB_ERR_UNSUPPORTED; one within
-    # them must run it on every such slot
+@pytest.mark.parametrize("side", ["fanin", "fanout", "both"])
+def test_matrix_core_transfers_match_oracle(name, side, tmp_path):
+    # the transfer launches on the 4 x 4 matrix-core forms: the fan-ins
+    # (target side forward, source side adjoint), the fan-outs (source side
+    # forward, target side adjoint) or all of them; four right-hand sides per
+    # workgroup, a ragged last group, and fewer right-hand sides than one
+    # group.  A plan whose ranks exceed 8 is rejected with
+    # TB_ERR_UNSUPPORTED; one within them must run it on every such slot
     torch = torch_gpu()
     import paper_2411_03029_amd as tb
     op = oracle_plan(name)
     plan = gpu_plan(name, tmp_path)
     n, d = op.n, op.d
-    slots = [s for s, st in enumerate(plan.launch_slots()) if st in ("tgt_transfer", "src_transfer_adj")]
+    stages = {"fanin": ("tgt_transfer", "src_transfer_adj"),
+              "fanout": ("src_transfer", "tgt_transfer_adj")}
+    want = stages["fanin"] + stages["fanout"] if side == "both" else stages[side]
+    slots = [s for s, st in enumerate(plan.launch_slots()) if st in want]
     fits = plan.info()["r_max"] <= 8
     for nrhs in (4, 7, 2):
         for s in slots:
             plan.set_launch(nrhs, s, dtype="c64", transfer_mfma=2)
         f = inputs.rhs_batch(n, d, nrhs, config=95)
         x = to_dev(f, torch.complex64)
-        say(f"[gpu] matrix-core fan-in {name} nrhs={nrhs} slots={slots}")
+        say(f"[gpu] matrix-core transfers {name} {side} nrhs={nrhs} slots={slots}")
         try:
             u = to_host(plan.apply(x, dtype="c64"))
             v = to_host(plan.apply_adjoint(x, dtype="c64"))
@@ -164,7 +169,7 @@ def test_matrix_core_fanin_matches_oracle(name, tmp_path):
         except tb.TBError as e:
             assert e.status == 2 and not fits, str(e)
             continue
-        assert slots, "no fan-in transfer level"
+        assert slots, "no transfer level"
         assert_parity(u, bf.apply(op, f), 2e-5, f"forward nrhs={nrhs}")
         assert_parity(v, bf.apply_adjoint(op, f), 2e-5, f"adjoint nrhs={nrhs}")
 

@@ -100,7 +100,7 @@ def _candidates(stage, nrhs, dtype):
                 out.append(dict(rhs_tile=qt, fanin_in_turn=2, outputs_per_thread=8, rhs_per_thread=4))
         if dtype != "c128":
             out.append(dict(rhs_tile=qt, transfer_mfma=1))
-    if dtype != "c128" and not fanout and nrhs >= 2:   # fan-in on 4 x 4 matrix-core blocks
+    if dtype != "c128" and nrhs >= 2:   # 4 x 4 matrix-core blocks (d = 3 transfer levels)
         out.append(dict(transfer_mfma=2))
     if dtype != "c128":   # flat staging, one right-hand side per workgroup
         out += [dict(flat_stage=1), dict(flat_stage=1, whole_blocks=1)]
