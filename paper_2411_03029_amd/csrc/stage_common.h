@@ -276,7 +276,7 @@ tb_status launch_leaf_wave(bool fp64, const StageArgs& a, int d, bool fanout, in
 tb_status launch_fanin_m4(const StageArgs& a, int d, int n_items, const void* in, void* out,
                           const void* mats, hipStream_t stream);
 // The fan-out counterpart: one fine block and four right-hand sides per
-// workgroup of eight waves.
+// workgroup of four waves, in two halves of its first mode.
 tb_status launch_fanout_m4(const StageArgs& a, int d, int n_items, const void* in, void* out,
                            const void* mats, hipStream_t stream);
 

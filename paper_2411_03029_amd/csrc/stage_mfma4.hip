@@ -335,18 +335,22 @@ tb_status launch_fanin_m4(const StageArgs& a, int d, int n_items, const void* in
 // fine(a_0, a_1, a_2, q) = sum_j M0[a_0][j_0] M1[a_1][j_1] M2[a_2][j_2]
 //                          coarse(j_0, j_1, j_2, q)
 // (source side of the forward apply; conj(M) on the target side of the
-// adjoint).  One workgroup of eight waves takes one fine block and four
-// right-hand sides.  Mode 0 reads the coarse block from global memory
-// (16 positions (j_1, j_2) per instruction, two tiles of a_0) into LDS;
-// then wave w carries row a_0 = w through mode 1 (positions j_2, two tiles
-// of a_1) into LDS of its own and mode 2 (positions a_1, the two tiles of
-// a_2 in the two halves of the blocks), which writes the fine block.
-__global__ void __launch_bounds__(512)
+// adjoint).  One workgroup of four waves takes one fine block and four
+// right-hand sides, in two halves of four a_0 rows each.  Per half, mode 0
+// reads the coarse block from global memory (16 positions (j_1, j_2) per
+// instruction, the half's tile of a_0; each wave's next group of positions
+// in flight while it multiplies the current one) into LDS; then wave w
+// carries row a_0 = 4 h + w through mode 1 (positions j_2, two tiles of a_1)
+// into LDS of its own and mode 2 (positions a_1, the two tiles of a_2 in the
+// two halves of the blocks), which writes the fine block.  Holding one half
+// of the mode-0 output (32 KB) lets three workgroups share a CU; the coarse
+// block is read once per half, the second time mostly from L2.
+__global__ void __launch_bounds__(256, 3)
     stage_fanout_m4(StageArgs a, const float2* __restrict__ coarse, float2* __restrict__ fine,
                     const float2* __restrict__ mats) {
   __shared__ float2 smt[3 * kC * kR];            // [mode][padded coarse position][row a]
-  __shared__ float2 st0[kR * kC * kC * kQ];      // mode 0 output [a0][j1][j2][q], compact j
-  __shared__ float2 st1[8 * kC * kR * kQ];       // mode 1 output of row a0 = w: [w][j2][a1][q]
+  __shared__ float2 st0[4 * kC * kC * kQ];       // mode 0 output of a half [a0 - 4h][j1][j2][q], compact j
+  __shared__ float2 st1[4 * kC * kR * kQ];       // mode 1 output of row a0 = 4h + w: [w][j2][a1][q]
 
   const StageBid sb = stage_bid(a, kQ);
   const int fi = sb.item_blk / a.nblk;
@@ -363,99 +367,110 @@ __global__ void __launch_bounds__(512)
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int blk = lane >> 2, qn = lane & 3;
   const int qc = min(qn, Qa - 1);
-  // the matrices, transposed, at their padded coarse positions
-  float2 mv = make_float2(0.f, 0.f);
-  if (tid < 3 * kC * kR) {
-    const int k = tid / (kC * kR), p = (tid / kR) % kC, row = tid % kR;
-    const int Rk = k == 0 ? a.R[0] : (k == 1 ? a.R[1] : a.R[2]);
-    const int Ak = k == 0 ? a.A[0] : (k == 1 ? a.A[1] : a.A[2]);
-    const int bk = k == 0 ? beta[0] : (k == 1 ? beta[1] : beta[2]);
-    const long long ok = k == 0 ? a.mat_k_off[0] : (k == 1 ? a.mat_k_off[1] : a.mat_k_off[2]);
-    if (row < Rk && p < Ak) mv = mats[(long long)fi * a.mat_item_stride + ok + ((long long)bk * Rk + row) * Ak + p];
-    if (a.conj) mv.y = -mv.y;
+  // the matrices, transposed, at their padded coarse positions (384 entries)
+  float2 mv[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + 256 * u;
+    mv[u] = make_float2(0.f, 0.f);
+    if (e < 3 * kC * kR) {
+      const int k = e / (kC * kR), p = (e / kR) % kC, row = e % kR;
+      const int Rk = k == 0 ? a.R[0] : (k == 1 ? a.R[1] : a.R[2]);
+      const int Ak = k == 0 ? a.A[0] : (k == 1 ? a.A[1] : a.A[2]);
+      const int bk = k == 0 ? beta[0] : (k == 1 ? beta[1] : beta[2]);
+      const long long ok = k == 0 ? a.mat_k_off[0] : (k == 1 ? a.mat_k_off[1] : a.mat_k_off[2]);
+      if (row < Rk && p < Ak) mv[u] = mats[(long long)fi * a.mat_item_stride + ok + ((long long)bk * Rk + row) * Ak + p];
+      if (a.conj) mv[u].y = -mv[u].y;
+    }
   }
   const int c0 = sg[0].c, c1 = sg[1].c, c2 = sg[2].c;
   if (c0 <= 0 || c1 <= 0 || c2 <= 0 || r[0] <= 0 || r[1] <= 0 || r[2] <= 0) return;  // uniform
-  if (tid < 3 * kC * kR) smt[tid] = mv;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+    if (tid + 256 * u < 3 * kC * kR) smt[tid + 256 * u] = mv[u];
   CoarseAddr<3> ca;
   ca.init(a, citem, beta, q0);
   long long fs[3];
   const long long fb = fine_base<3>(a, fi, beta, q0, fs);
   const int row[4] = {qn, 4 + qn, 0, 0};
+  const int P = c1 * c2, ng = (P + 15) / 16;
+  // this lane's mode-0 input for group g of positions (j1, j2)
+  auto load_grp = [&](int g, float2 (&b)[kC]) {
+    const int pc = min(16 * g + blk, P - 1);
+    const int j1 = pc / c2, j2 = pc % c2;
+    const float2* src = coarse + ca.base + sg[1].pos(j1) * ca.stride[1] + sg[2].pos(j2) * ca.stride[2] + qc;
+#pragma unroll
+    for (int k = 0; k < kC; ++k) b[k] = src[sg[0].pos(min(k, c0 - 1)) * ca.stride[0]];
+  };
+  float2 b[kC];
+  if (w < ng) load_grp(w, b);
   __syncthreads();  // matrices
 
-  // ---- mode 0: st0[a0][j1][j2][q] = sum_j0 M0[a0][j0] coarse(j0, j1, j2, q)
-  {
-    const int P = c1 * c2, ng = (P + 15) / 16;
-    for (int g = w; g < ng; g += 8) {
-      const int p = 16 * g + blk, pc = min(p, P - 1);
-      const int j1 = pc / c2, j2 = pc % c2;
-      const float2* src = coarse + ca.base + sg[1].pos(j1) * ca.stride[1] + sg[2].pos(j2) * ca.stride[2] + qc;
-      float2 b[kC];
+  const int nh = r[0] > 4 ? 2 : 1;
+  for (int h = 0; h < nh; ++h) {
+    // ---- mode 0, rows a0 = 4 h + v: st0[v][j1][j2][q] = sum_j0 M0[a0][j0] coarse(j0, j1, j2, q)
+    for (int g = w; g < ng; g += 4) {
+      float2 cur[kC];
 #pragma unroll
-      for (int k = 0; k < kC; ++k) b[k] = src[sg[0].pos(min(k, c0 - 1)) * ca.stride[0]];
-      CAcc d[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) czero4(d[t]);
+      for (int k = 0; k < kC; ++k) cur[k] = b[k];
+      // the next group of this wave (the first group again for the second half)
+      const int gn = g + 4 < ng ? g + 4 : (h + 1 < nh ? w : -1);
+      if (gn >= 0) load_grp(gn, b);
+      CAcc d;
+      czero4(d);
 #pragma unroll
       for (int k = 0; k < kC; ++k) {
         if (k < c0) {
-          const float2* Mk = smt + sg[0].pos(k) * kR;
-          float2 m[2];
-#pragma unroll
-          for (int t = 0; t < 2; ++t) m[t] = Mk[row[t]];
-#pragma unroll
-          for (int t = 0; t < 2; ++t) d[t].re = mf(m[t].x, b[k].x, d[t].re);
-#pragma unroll
-          for (int t = 0; t < 2; ++t) d[t].im = mf(m[t].x, b[k].y, d[t].im);
-#pragma unroll
-          for (int t = 0; t < 2; ++t) d[t].re = mf(-m[t].y, b[k].y, d[t].re);
-#pragma unroll
-          for (int t = 0; t < 2; ++t) d[t].im = mf(m[t].y, b[k].x, d[t].im);
+          const float2 m = smt[sg[0].pos(k) * kR + row[h]];
+          d.re = mf(m.x, cur[k].x, d.re);
+          d.im = mf(m.x, cur[k].y, d.im);
+          d.re = mf(-m.y, cur[k].y, d.re);
+          d.im = mf(m.y, cur[k].x, d.im);
         }
       }
+      const int p = 16 * g + blk;
       if (p < P) {  // rows past r0 land in unread padding
+        const int j1 = p / c2, j2 = p % c2;
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            st0[(((4 * t + v) * kC + j1) * kC + j2) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
+        for (int v = 0; v < 4; ++v) st0[((v * kC + j1) * kC + j2) * kQ + qn] = make_float2(d.re[v], d.im[v]);
       }
     }
-  }
-  __syncthreads();
-  if (w >= r[0]) return;  // no barrier follows
-  const int a0 = w;
-  float2* t1 = st1 + w * kC * kR * kQ;  // [j2][a1][q]
-  // ---- mode 1: t1[j2][a1][q] = sum_j1 M1[a1][j1] st0[a0][j1][j2][q], j2 = blk
-  {
-    CAcc d[4];
+    __syncthreads();
+    const int a0 = 4 * h + w;
+    if (a0 < r[0]) {
+      float2* t1 = st1 + w * kC * kR * kQ;  // [j2][a1][q]
+      // ---- mode 1: t1[j2][a1][q] = sum_j1 M1[a1][j1] st0[w][j1][j2][q], j2 = blk
+      {
+        CAcc d[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) czero4(d[t]);
-    seg_tiles<2>(d, st0 + (a0 * kC * kC + min(blk, c2 - 1)) * kQ + qn, kC * kQ, smt + kC * kR, row, sg[1]);
-    if (blk < c2) {
+        for (int t = 0; t < 4; ++t) czero4(d[t]);
+        seg_tiles<2>(d, st0 + (w * kC * kC + min(blk, c2 - 1)) * kQ + qn, kC * kQ, smt + kC * kR, row, sg[1]);
+        if (blk < c2) {
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+          for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) t1[(blk * kR + 4 * t + v) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
+            for (int v = 0; v < 4; ++v) t1[(blk * kR + 4 * t + v) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
+        }
+      }
+      // ---- mode 2: fine[a0][a1][a2][q] = sum_j2 M2[a2][j2] t1[j2][a1][q]; the
+      // block holds a1 = blk % 8 and rows a2 of tile blk / 8 (the same wave
+      // wrote t1: its LDS operations complete in order)
+      {
+        const int a1 = blk & 7, th = blk >> 3;
+        const int rowh[4] = {4 * th + qn, 0, 0, 0};
+        CAcc d[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) czero4(d[t]);
+        seg_tiles<1>(d, t1 + min(a1, r[1] - 1) * kQ + qn, kR * kQ, smt + 2 * kC * kR, rowh, sg[2]);
+        if (a1 < r[1] && qn < Qa) {
+          float2* dst = fine + fb + a0 * fs[0] + a1 * fs[1] + qn;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (4 * th + v < r[2]) dst[(4 * th + v) * fs[2]] = make_float2(d[0].re[v], d[0].im[v]);
+        }
+      }
     }
-  }
-  // ---- mode 2: fine[a0][a1][a2][q] = sum_j2 M2[a2][j2] t1[j2][a1][q]; the
-  // block holds a1 = blk % 8 and rows a2 of tile blk / 8 (the same wave
-  // wrote t1: its LDS operations complete in order)
-  {
-    const int a1 = blk & 7, th = blk >> 3;
-    const int rowh[4] = {4 * th + qn, 0, 0, 0};
-    CAcc d[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) czero4(d[t]);
-    seg_tiles<1>(d, t1 + min(a1, r[1] - 1) * kQ + qn, kR * kQ, smt + 2 * kC * kR, rowh, sg[2]);
-    if (a1 < r[1] && qn < Qa) {
-      float2* dst = fine + fb + a0 * fs[0] + a1 * fs[1] + qn;
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (4 * th + v < r[2]) dst[(4 * th + v) * fs[2]] = make_float2(d[0].re[v], d[0].im[v]);
-    }
+    if (h + 1 < nh) __syncthreads();  // st0 is rewritten by the second half
   }
 }
 
@@ -472,7 +487,7 @@ tb_status launch_fanout_m4(const StageArgs& a, int d, int n_items, const void* i
   b.chunk = a.R[0];
   const long long nwg = (long long)n_items * a.nblk * ((a.nrhs + kQ - 1) / kQ);
   if (nwg < 1 || nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many workgroups for one launch");
-  stage_fanout_m4<<<dim3((unsigned)nwg), 512, 0, stream>>>(b, (const float2*)in, (float2*)out,
+  stage_fanout_m4<<<dim3((unsigned)nwg), 256, 0, stream>>>(b, (const float2*)in, (float2*)out,
                                                            (const float2*)mats);
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;
