@@ -1,33 +1,42 @@
-// Fan-in transfer stage on the matrix cores, d = 3, FP32 (Algorithm 2 step
-// 3: the 2^d children's tensors carried into their parent block, target side
-// of the forward apply; with M^H, the source side of the adjoint).
+// Transfer stages on the matrix cores, d = 3, FP32, four right-hand sides
+// per workgroup (Algorithm 2 steps 1 and 3 at the transfer levels, and the
+// same stages of the adjoint).
+//
+// Every mode product runs on v_mfma_f32_4x4x1f32: one instruction forms 16
+// independent 4 x 4 outer products, each of four matrix entries (four rows
+// of the output mode) with one input entry of the four right-hand sides.  A
+// block of the instruction is one position of the two modes not being
+// contracted, so the contracted mode needs no padding (K = 1) and the output
+// mode is padded only to a multiple of four; where a mode has at most 8
+// positions, the two halves of the blocks take two different tiles of rows
+// (the matrix operand is per block).  A complex product is four real
+// instructions.
+//
+// Fan-in (the 2^d children's tensors carried into their parent block: the
+// target side of the forward apply; with M^H, the source side of the
+// adjoint):
 //
 //   coarse(a_0, a_1, a_2, q) = sum_children sum_j M0_c[j_0][a_0] M1_c[j_1][a_1]
 //                              M2_c[j_2][a_2] fine_c(j_0, j_1, j_2, q)
 //
-// One workgroup of four waves takes one coarse block and four right-hand
-// sides.  Every mode product runs on v_mfma_f32_4x4x1f32: one instruction
-// forms 16 independent 4 x 4 outer products, each of four entries of one
-// matrix column (four rows of the output mode) with one input entry of the
-// four right-hand sides.  A block of the instruction is one position of the
-// two modes not being contracted, so the contracted mode needs no padding
-// (K = 1) and the output mode is padded only to a multiple of four.  A
-// complex product is four real instructions.
-//
-// The children are taken in turn.  Per child: mode 0 reads its input from
-// global memory into registers (issued one child ahead, so the loads overlap
-// the previous child's products) and writes LDS; then each wave takes its
-// a_0 rows (w, w + 4, ..) one at a time through mode 1, into LDS of its own,
-// and mode 2, into accumulators that stay in registers for the whole block
+// One workgroup of four waves takes one coarse block.  The children are
+// taken in turn.  Per child: mode 0 reads its input from global memory into
+// registers (issued one child ahead, so the loads overlap the previous
+// child's products) and writes LDS; then each wave takes its a_0 rows
+// (w, w + 4, ..) one at a time through mode 1, into LDS of its own, and
+// mode 2, into accumulators that stay in registers for the whole block
 // (16 x 16 x 16 entries of four right-hand sides over 256 lanes: 32 complex
-// values per lane).  Two workgroup barriers per child.  The
-// matrices of all eight children come into LDS at the start, in the same
-// memory round trip as the ranks: they are staged at their padded columns,
-// so their addresses do not depend on any rank.
+// values per lane).  Two workgroup barriers per child.  The matrices of all
+// eight children come into LDS at the start, in the same memory round trip
+// as the ranks and the first child's input: they are staged at their padded
+// columns, so their addresses do not depend on any rank.
+//
+// Fan-out (source side of the forward apply; target side of the adjoint
+// with conj(M)): described above stage_fanout_m4.
 //
 // Limits (the host rejects other blocks): fine ranks up to 8 per mode,
-// coarse blocks up to 16 per mode, coarse output an intermediate level (not
-// the caller's array).
+// coarse blocks up to 16 per mode, transfer levels only (not the leaves,
+// whose coarse side is the caller's array).
 #include <hip/hip_runtime.h>
 
 #include "stage_common.h"
