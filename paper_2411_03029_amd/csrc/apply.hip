@@ -3502,8 +3502,9 @@ static tb_status launch_stage(const Plan& p, StageArgs a, bool fanout, int n_ite
     if constexpr (sizeof(T) != 4) {
       return fail(TB_ERR_UNSUPPORTED, "the 4 x 4 matrix-core transfers are FP32 only");
     } else {
-      return fanout ? launch_fanout_m4(a, p.d, n_items, in, out, mats, stream)
-                    : launch_fanin_m4(a, p.d, n_items, in, out, mats, stream);
+      if (fanout) return launch_fanout_m4(a, p.d, n_items, in, out, mats, stream);
+      return a.coarse_global ? launch_leaf_fanin_m4(a, p.d, n_items, in, out, mats, stream)
+                             : launch_fanin_m4(a, p.d, n_items, in, out, mats, stream);
     }
   }
   if (cfg.mfma == 1) return launch_stage_xmfma<T>(p, a, fanout, n_items, in, out, mats, stream, cfg);

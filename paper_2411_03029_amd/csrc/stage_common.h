@@ -279,6 +279,10 @@ tb_status launch_fanin_m4(const StageArgs& a, int d, int n_items, const void* in
 // workgroup of four waves, in two halves of its first mode.
 tb_status launch_fanout_m4(const StageArgs& a, int d, int n_items, const void* in, void* out,
                            const void* mats, hipStream_t stream);
+// The leaf fan-in (target leaf, source leaf of the adjoint), leaf size 8:
+// one leaf box and four right-hand sides per workgroup.
+tb_status launch_leaf_fanin_m4(const StageArgs& a, int d, int n_items, const void* in, void* out,
+                               const void* mats, hipStream_t stream);
 
 // Generic apply for any number of modes (apply_generic.hip): per-workgroup
 // scratch in global memory, FP64 (fp64) or FP32.

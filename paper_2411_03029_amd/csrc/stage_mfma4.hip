@@ -32,11 +32,11 @@
 // columns, so their addresses do not depend on any rank.
 //
 // Fan-out (source side of the forward apply; target side of the adjoint
-// with conj(M)): described above stage_fanout_m4.
+// with conj(M)) and the leaf fan-in: described above stage_fanout_m4 and
+// leaf_fanin_m4.
 //
 // Limits (the host rejects other blocks): fine ranks up to 8 per mode,
-// coarse blocks up to 16 per mode, transfer levels only (not the leaves,
-// whose coarse side is the caller's array).
+// coarse blocks up to 16 per mode; the leaf form, leaf size 8.
 #include <hip/hip_runtime.h>
 
 #include "stage_common.h"
@@ -498,6 +498,149 @@ tb_status launch_fanout_m4(const StageArgs& a, int d, int n_items, const void* i
   if (nwg < 1 || nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many workgroups for one launch");
   stage_fanout_m4<<<dim3((unsigned)nwg), 256, 0, stream>>>(b, (const float2*)in, (float2*)out,
                                                            (const float2*)mats);
+  TB_HIP_TRY(hipGetLastError());
+  return TB_OK;
+}
+
+// --------------------------------------------------------- leaf fan-in --
+// box(p_0, p_1, p_2, q) = sum_a M0[a_0][p_0] M1[a_1][p_1] M2[a_2][p_2] fine(a, q)
+// (the target leaf of the forward apply; the source leaf of the adjoint
+// with conj(M)), leaf size 8, the box in the caller's array.  One workgroup
+// of four waves takes one leaf box and four right-hand sides.  The padded
+// fine block, the padded matrices and the ranks come in one memory round
+// trip.  Mode 0 (positions (a_1, a_2), both tiles of p_0) writes LDS; then
+// wave w carries rows p_0 = w and w + 4 through mode 1 (positions a_2, the
+// two tiles of p_1 in the two halves of the blocks) into LDS of its own and
+// mode 2 (positions p_1, the two tiles of p_2 likewise), whose four outputs
+// per lane are four consecutive points of one box row.
+constexpr int kL = 8;  // leaf size
+
+__global__ void __launch_bounds__(256)
+    leaf_fanin_m4(StageArgs a, const float2* __restrict__ fine, float2* __restrict__ box,
+                  const float2* __restrict__ mats) {
+  __shared__ float2 smat[3 * kR * kL];            // [mode][row a][point p]
+  __shared__ float2 st0[kL * kR * kR * kQ];       // mode 0 output [p0][a1][a2][q]
+  __shared__ float2 st1[4 * kL * kR * kQ];        // mode 1 output of one row p0 per wave [w][p1][a2][q]
+
+  const StageBid sb = stage_bid(a, kQ);
+  const int fi = sb.item_blk / a.nblk;
+  int beta[3];
+  unflatten_blk<3>(sb.item_blk % a.nblk, a.nb, beta);
+  int r[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) r[k] = a.rank_f[((long long)fi * 3 + k) * a.nb + beta[k]];
+  const int q0 = sb.q0;
+  const int Qa = min(kQ, a.nrhs - q0);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int blk = lane >> 2, qn = lane & 3;
+  const int qc = min(qn, Qa - 1);
+  const int R0 = a.R[0], R1 = a.R[1], R2 = a.R[2];
+  long long fs[3];
+  const long long fb = fine_base<3>(a, fi, beta, q0, fs);
+  // this lane's mode-0 input: rows a0 < kR at position 16 w + blk of the
+  // padded (a1, a2) grid
+  float2 b[kR];
+  {
+    const int p = min(16 * w + blk, R1 * R2 - 1);
+    const float2* src = fine + fb + (p / R2) * fs[1] + (p % R2) * fs[2] + qc;
+#pragma unroll
+    for (int k = 0; k < kR; ++k) b[k] = src[min(k, R0 - 1) * fs[0]];
+  }
+  float2 mv = make_float2(0.f, 0.f);
+  if (tid < 3 * kR * kL) {
+    const int k = tid / (kR * kL), row = (tid / kL) % kR, pt = tid % kL;
+    const int Rk = k == 0 ? a.R[0] : (k == 1 ? a.R[1] : a.R[2]);
+    const int bk = k == 0 ? beta[0] : (k == 1 ? beta[1] : beta[2]);
+    const long long ok = k == 0 ? a.mat_k_off[0] : (k == 1 ? a.mat_k_off[1] : a.mat_k_off[2]);
+    if (row < Rk) mv = mats[(long long)fi * a.mat_item_stride + ok + ((long long)bk * Rk + row) * kL + pt];
+    if (a.conj) mv.y = -mv.y;
+  }
+  if (r[0] <= 0 || r[1] <= 0 || r[2] <= 0) return;  // uniform, before any barrier
+  if (tid < 3 * kR * kL) smat[tid] = mv;
+  CoarseAddr<3> ca;
+  ca.init(a, fi, beta, q0);  // the box of item fi in the caller's array
+  __syncthreads();  // matrices
+
+  // ---- mode 0: st0[p0][a1][a2][q] = sum_a0 M0[a0][p0] fine(a0, a1, a2, q)
+  if (16 * w < R1 * R2 && (16 * w) / R2 < r[1]) {
+    CAcc d[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) czero4(d[t]);
+#pragma unroll
+    for (int k = 0; k < kR; ++k) {
+      if (k < r[0]) {
+        float2 m[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) m[t] = smat[k * kL + 4 * t + qn];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) d[t].re = mf(m[t].x, b[k].x, d[t].re);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) d[t].im = mf(m[t].x, b[k].y, d[t].im);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) d[t].re = mf(-m[t].y, b[k].y, d[t].re);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) d[t].im = mf(m[t].y, b[k].x, d[t].im);
+      }
+    }
+    const int p = 16 * w + blk, a1 = p / R2, a2 = p % R2;
+    if (p < R1 * R2 && a1 < r[1] && a2 < r[2]) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          st0[(((4 * t + v) * kR + a1) * kR + a2) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
+    }
+  }
+  __syncthreads();
+  const int th = blk >> 3, ph = blk & 7;  // tile half, position within the half
+  const int rowh[4] = {4 * th + qn, 0, 0, 0};
+  float2* t1 = st1 + w * kL * kR * kQ;  // [p1][a2][q]
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const int p0 = w + 4 * s2;
+    // ---- mode 1: t1[p1][a2][q] = sum_a1 M1[a1][p1] st0[p0][a1][a2][q], a2 = ph
+    {
+      CAcc d[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) czero4(d[t]);
+      tiles_lds<1, kL>(d, st0 + (p0 * kR * kR + min(ph, r[2] - 1)) * kQ + qn, kR * kQ, smat + kR * kL, rowh,
+                       r[1]);
+      if (ph < r[2]) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) t1[((4 * th + v) * kR + ph) * kQ + qn] = make_float2(d[0].re[v], d[0].im[v]);
+      }
+    }
+    // ---- mode 2: box[p0][p1][p2][q] = sum_a2 M2[a2][p2] t1[p1][a2][q], p1 = ph
+    // (the same wave wrote t1: its LDS operations complete in order)
+    {
+      CAcc d[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) czero4(d[t]);
+      tiles_lds<1, kL>(d, t1 + ph * kR * kQ + qn, kQ, smat + 2 * kR * kL, rowh, r[2]);
+      if (qn < Qa) {
+        float2* dst = box + ca.base + p0 * ca.stride[0] + ph * ca.stride[1] + qn * ca.qstride;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(4 * th + v) * ca.stride[2]] = make_float2(d[0].re[v], d[0].im[v]);
+      }
+    }
+  }
+}
+
+tb_status launch_leaf_fanin_m4(const StageArgs& a, int d, int n_items, const void* in, void* out,
+                               const void* mats, hipStream_t stream) {
+  if (d != 3) return fail(TB_ERR_UNSUPPORTED, "the matrix-core leaf fan-in is for d = 3");
+  if (!a.coarse_global) return fail(TB_ERR_UNSUPPORTED, "the matrix-core leaf fan-in runs the leaves only");
+  for (int k = 0; k < 3; ++k)
+    if (a.A[k] != kL || a.R[k] > kR)
+      return fail(TB_ERR_UNSUPPORTED, "matrix-core leaf fan-in: leaf size 8 and ranks up to 8 only");
+  StageArgs b = a;
+  b.nsplit = 1;
+  b.chunk = a.A[0];
+  b.aff_blocks = 0;
+  const long long nwg = (long long)n_items * a.nblk * ((a.nrhs + kQ - 1) / kQ);
+  if (nwg < 1 || nwg >= (1LL << 31)) return fail(TB_ERR_UNSUPPORTED, "too many workgroups for one launch");
+  leaf_fanin_m4<<<dim3((unsigned)nwg), 256, 0, stream>>>(b, (const float2*)in, (float2*)out,
+                                                        (const float2*)mats);
   TB_HIP_TRY(hipGetLastError());
   return TB_OK;
 }

@@ -138,24 +138,27 @@ def test_register_fiber_stages_match_oracle(name, tmp_path):
 
 
 @pytest.mark.parametrize("name", [k for k, v in CASES.items() if v[1] == 3 and v[2] >= 16])
-@pytest.mark.parametrize("side", ["fanin", "fanout", "both"])
+@pytest.mark.parametrize("side", ["fanin", "fanout", "both", "leaf"])
 def test_matrix_core_transfers_match_oracle(name, side, tmp_path):
     # the transfer launches on the 4 x 4 matrix-core forms: the fan-ins
     # (target side forward, source side adjoint), the fan-outs (source side
-    # forward, target side adjoint) or all of them; four right-hand sides per
-    # workgroup, a ragged last group, and fewer right-hand sides than one
-    # group.  A plan whose ranks exceed 8 is rejected with
-    # TB_ERR_UNSUPPORTED; one within them must run it on every such slot
+    # forward, target side adjoint), all of them, or the fan-in leaves
+    # (target leaf, source leaf of the adjoint; leaf size 8); four right-hand
+    # sides per workgroup, a ragged last group, and fewer right-hand sides
+    # than one group.  A plan whose ranks exceed 8 (or, for the leaves, whose
+    # leaf size is not 8) is rejected with TB_ERR_UNSUPPORTED; one within
+    # them must run it on every such slot
     torch = torch_gpu()
     import paper_2411_03029_amd as tb
     op = oracle_plan(name)
     plan = gpu_plan(name, tmp_path)
     n, d = op.n, op.d
     stages = {"fanin": ("tgt_transfer", "src_transfer_adj"),
-              "fanout": ("src_transfer", "tgt_transfer_adj")}
+              "fanout": ("src_transfer", "tgt_transfer_adj"),
+              "leaf": ("tgt_leaf", "src_leaf_adj")}
     want = stages["fanin"] + stages["fanout"] if side == "both" else stages[side]
     slots = [s for s, st in enumerate(plan.launch_slots()) if st in want]
-    fits = plan.info()["r_max"] <= 8
+    fits = plan.info()["r_max"] <= 8 and (side != "leaf" or op.leaf == 8)
     for nrhs in (4, 7, 2):
         for s in slots:
             plan.set_launch(nrhs, s, dtype="c64", transfer_mfma=2)
