@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(256, 2)
     col1p[t] = t < 2 ? pcol(sg[1], 4 * (2 * t + th) + qn) : 0;
     col2[t] = pcol(sg[2], 4 * t + qn);
   }
-  CAcc acc[4][4];  // [slice s: a0 = 4 s + w][tile t: a2 = 4 t + row]
+  CAcc acc[4][4];  // [row s: a0 = 4 s + w][tile t: a2 = 4 t + row]
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
