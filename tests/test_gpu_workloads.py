@@ -11,7 +11,9 @@
    target rows (forward) and source columns (adjoint).
 3. The Helmholtz cubes at n = 128 with 64 right-hand sides (tol 1e-4,
    complex FP32, matrix-core cores), forward and adjoint, against the exact
-   FFT convolution on the first and the last right-hand side.
+   FFT convolution on the first and the last right-hand side; and the same
+   with the transfer levels and fan-in leaves forced onto the 4 x 4
+   matrix-core forms.
 
 Approximation bounds follow the target of the FP32 apply: relative error at
 most tol + 1e-5 against the exact operator.
@@ -127,5 +129,51 @@ def test_helmholtz128_64rhs_against_fft_convolution():
     for q in (0, nrhs - 1):
         eu = relerr(to_host(u[q]), dense.apply_exact(op, f[q])[0])
         ev = relerr(to_host(v[q]), dense.adjoint_exact(op, f[q])[0])
+        say(f"[gpu]   rhs {q}: forward {eu:.2e} adjoint {ev:.2e}")
+        assert eu <= tol + 1e-5 and ev <= tol + 1e-5
+
+
+def test_helmholtz128_64rhs_matrix_core_stages():
+    # the same workload with its transfer levels and fan-in leaves forced
+    # onto the 4 x 4 matrix-core forms (ranks 3..8, leaf 8): the transfers
+    # give the vector forms' bits (the same products in the same order), and
+    # with the matrix-core leaves too the apply meets the same bound against
+    # FFT convolution
+    torch = torch_gpu()
+    import paper_2411_03029_amd as tb
+    n, tol, nrhs = 128, 1e-4, 64
+    op = Operator(kernels.HELMHOLTZ, 3, n, omega=kernels.helmholtz_omega(n))
+    say("[gpu] construct helmholtz n=128 tol=1e-4 (matrix-core stages)")
+    plan = tb.construct("helmholtz", 3, n, tol, store=("c64",))
+    f = inputs.rhs_batch(n, 3, nrhs, config=5)
+    x = to_dev(f, torch.complex64)
+    slots = plan.launch_slots()
+    fanin = ("tgt_transfer", "src_transfer_adj")
+    fanout = ("src_transfer", "tgt_transfer_adj")
+    leaves = ("tgt_leaf", "src_leaf_adj")
+
+    def run(cfgs):
+        for s, st in enumerate(slots):
+            for names, cfg in cfgs:
+                if st in names:
+                    plan.set_launch(nrhs, s, dtype="c64", **cfg)
+        u, v = plan.apply(x), plan.apply_adjoint(x)
+        torch.cuda.synchronize()
+        return u, v
+
+    say("[gpu]   vector transfers and leaves")
+    u0, v0 = run([(fanin, dict(rhs_tile=4, fanin_in_turn=2, outputs_per_thread=8)),
+                  (fanout, dict(outputs_per_thread=8, rhs_tile=2)),
+                  (leaves, dict(fanin_in_turn=1, rhs_tile=8))])
+    say("[gpu]   matrix-core transfers")
+    u1, v1 = run([(fanin + fanout, dict(transfer_mfma=2))])
+    assert torch.equal(u0, u1) and torch.equal(v0, v1)
+    say("[gpu]   matrix-core transfers and fan-in leaves")
+    u2, v2 = run([(leaves, dict(transfer_mfma=2))])
+    for a, b in ((u2, u1), (v2, v1)):
+        assert float((a - b).abs().max() / b.abs().max()) <= 1e-5
+    for q in (0, nrhs - 1):
+        eu = relerr(to_host(u2[q]), dense.apply_exact(op, f[q])[0])
+        ev = relerr(to_host(v2[q]), dense.adjoint_exact(op, f[q])[0])
         say(f"[gpu]   rhs {q}: forward {eu:.2e} adjoint {ev:.2e}")
         assert eu <= tol + 1e-5 and ev <= tol + 1e-5
