@@ -19,17 +19,20 @@
 //   coarse(a_0, a_1, a_2, q) = sum_children sum_j M0_c[j_0][a_0] M1_c[j_1][a_1]
 //                              M2_c[j_2][a_2] fine_c(j_0, j_1, j_2, q)
 //
-// One workgroup of four waves takes one coarse block.  The children are
-// taken in turn.  Per child: mode 0 reads its input from global memory into
+// One workgroup of four waves takes one coarse block, in groups of four a_0
+// rows; wave w accumulates row a_0 = 4 s + w of group s over all children,
+// in registers (16 x 16 entries of four right-hand sides: 8 complex values
+// per lane).  Per group, the children are taken in turn: mode 0 (the
+// group's tile of a_0) reads the child's input from global memory into
 // registers (issued one child ahead, so the loads overlap the previous
-// child's products) and writes LDS; then each wave takes its a_0 rows
-// (w, w + 4, ..) one at a time through mode 1, into LDS of its own, and
-// mode 2, into accumulators that stay in registers for the whole block
-// (16 x 16 x 16 entries of four right-hand sides over 256 lanes: 32 complex
-// values per lane).  Two workgroup barriers per child.  The matrices of all
-// eight children come into LDS at the start, in the same memory round trip
-// as the ranks and the first child's input: they are staged at their padded
-// columns, so their addresses do not depend on any rank.
+// child's products) and writes LDS; then each wave takes its row through
+// mode 1, into LDS of its own, and mode 2, into its accumulators.  Two
+// workgroup barriers per child and group.  Holding one row per wave keeps
+// the registers (145) and LDS (49 KB) within three workgroups per CU; each
+// child's input is read once per group, mostly from L2.  The matrices of
+// all eight children come into LDS at the start, in the same memory round
+// trip as the ranks and the first child's input: they are staged at their
+// padded columns, so their addresses do not depend on any rank.
 //
 // Fan-out (source side of the forward apply; target side of the adjoint
 // with conj(M)) and the leaf fan-in: described above stage_fanout_m4 and
@@ -138,11 +141,11 @@ __device__ __forceinline__ void tiles_reg(CAcc (&d)[4], const float2 (&b)[kR], c
 
 }  // namespace
 
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(256, 3)
     stage_fanin_m4(StageArgs a, const float2* __restrict__ fine, float2* __restrict__ coarse,
                    const float2* __restrict__ mats) {
   __shared__ float2 smat[kNch * 3 * kR * kC];  // [child][mode][row j][padded column]
-  __shared__ float2 sbuf1[kC * kR * kR * kQ];  // mode 0 output [a0][j1][j2][q]
+  __shared__ float2 sbuf1[4 * kR * kR * kQ];   // mode 0 output of a group of four a0 rows [a0 - 4s][j1][j2][q]
   __shared__ float2 sbuf2[4 * kR * kC * kQ];   // mode 1 output of one a_0 row per wave [w][j2][a1][q]
   __shared__ int srk[kNch][3];
 
@@ -216,106 +219,89 @@ __global__ void __launch_bounds__(256, 2)
   }
 
   const int c0 = sg[0].c, c1 = sg[1].c, c2 = sg[2].c;
-  const int nt0 = (c0 + 3) / 4, nt1 = (c1 + 3) / 4, nt2 = (c2 + 3) / 4;
+  const int nt1 = (c1 + 3) / 4, nt2 = (c2 + 3) / 4;
   // mode 1 pairs tiles of a1 across the two halves of an instruction's
   // blocks: block blk holds position j2h = blk % 8 of tile 2 tp + th
   const int th = blk >> 3, j2h = blk & 7;
-  int col0[4], col1p[4], col2[4];
+  int col1p[4], col2[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    col0[t] = pcol(sg[0], 4 * t + qn);
     col1p[t] = t < 2 ? pcol(sg[1], 4 * (2 * t + th) + qn) : 0;
     col2[t] = pcol(sg[2], 4 * t + qn);
   }
-  CAcc acc[4][4];  // [row s: a0 = 4 s + w][tile t: a2 = 4 t + row]
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) czero4(acc[s][t]);
+  CoarseAddr<3> ca;
+  ca.init(a, ci, beta, q0);
   __syncthreads();  // ranks and matrices
 
-  for (int c = 0; c < kNch; ++c) {
-    const int r0 = srk[c][0], r1 = srk[c][1], r2 = srk[c][2];
-    // ---- mode 0: sbuf1[a0][j1][j2][q] = sum_j0 M0[j0][a0] fine(j0, j1, j2, q)
-    {
-      const float2* M0 = smat + (c * 3 + 0) * kR * kC;
-      const int p = 16 * w + blk;
-      if (16 * w < R1 * R2 && (16 * w) / R2 < r1) {
+  // row groups s of four a0 rows, outermost: wave w accumulates row
+  // a0 = 4 s + w over all children, so the accumulators hold one row
+  const int ngrp = (c0 + 3) / 4;
+  for (int s = 0; s < ngrp; ++s) {
+    CAcc acc[4];  // [tile t: a2 = 4 t + row]
+#pragma unroll
+    for (int t = 0; t < 4; ++t) czero4(acc[t]);
+    int col0s[4] = {pcol(sg[0], 4 * s + qn), 0, 0, 0};
+    const int a0 = 4 * s + w;
+    for (int c = 0; c < kNch; ++c) {
+      const int r0 = srk[c][0], r1 = srk[c][1], r2 = srk[c][2];
+      // ---- mode 0, rows of group s: sbuf1[a0 - 4s][j1][j2][q] = sum_j0 M0[j0][a0] fine(j0, j1, j2, q)
+      {
+        const float2* M0 = smat + (c * 3 + 0) * kR * kC;
+        const int p = 16 * w + blk;
+        if (16 * w < R1 * R2 && (16 * w) / R2 < r1) {
+          CAcc d[4];
+          czero4(d[0]);
+          tiles_reg<1>(d, b, M0, col0s, r0);
+          const int j1 = p / R2, j2 = p % R2;
+          if (p < R1 * R2 && j1 < r1 && j2 < r2) {  // rows past c0 land in unread padding
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              sbuf1[((v * kR + j1) * kR + j2) * kQ + qn] = make_float2(d[0].re[v], d[0].im[v]);
+          }
+        }
+        // the next (group, child) input, in flight during modes 1 and 2
+        if (c + 1 < kNch)
+          load_b(c + 1, b);
+        else if (s + 1 < ngrp)
+          load_b(0, b);
+      }
+      __syncthreads();
+      // ---- modes 1 and 2 for row a0 of this wave
+      if (a0 < c0 && r1 > 0 && r2 > 0) {  // a child of rank 0 adds nothing
+        const float2* M1 = smat + (c * 3 + 1) * kR * kC;
+        const float2* M2 = smat + (c * 3 + 2) * kR * kC;
+        float2* t1 = sbuf2 + w * kR * kC * kQ;  // [j2][a1][q] of this wave's row
+        // t1[j2][a1][q] = sum_j1 M1[j1][a1] sbuf1[w][j1][j2][q]: a row has at
+        // most 8 positions j2, so blocks 0-7 and 8-15 of an instruction take
+        // two different tiles of a1 (the matrix operand is per block)
         CAcc d[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) czero4(d[t]);
-        switch (nt0) {
-          case 1: tiles_reg<1>(d, b, M0, col0, r0); break;
-          case 2: tiles_reg<2>(d, b, M0, col0, r0); break;
-          case 3: tiles_reg<3>(d, b, M0, col0, r0); break;
-          default: tiles_reg<4>(d, b, M0, col0, r0); break;
-        }
-        const int j1 = p / R2, j2 = p % R2;
-        if (p < R1 * R2 && j1 < r1 && j2 < r2) {  // rows past c0 land in unread padding
+        tiles_lds_n((nt1 + 1) / 2, d, sbuf1 + (w * kR * kR + min(j2h, r2 - 1)) * kQ + qn, kR * kQ, M1, col1p,
+                    r1);
+        if (j2h < r2) {  // rows past c1 land in unread padding
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
+          for (int tp = 0; tp < 2; ++tp)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              sbuf1[(((4 * t + v) * kR + j1) * kR + j2) * kQ + qn] = make_float2(d[t].re[v], d[t].im[v]);
+              t1[(j2h * kC + 4 * (2 * tp + th) + v) * kQ + qn] = make_float2(d[tp].re[v], d[tp].im[v]);
         }
+        // acc += sum_j2 M2[j2][a2] t1[j2][a1][q], a1 = blk (the same wave
+        // wrote t1: its LDS operations complete in order)
+        tiles_lds_n(nt2, acc, t1 + min(blk, c1 - 1) * kQ + qn, kC * kQ, M2, col2, r2);
       }
-      if (c + 1 < kNch) load_b(c + 1, b);  // next child's input, in flight during modes 1 and 2
+      __syncthreads();  // sbuf1 is rewritten by the next child
     }
-    __syncthreads();
-    // ---- modes 1 and 2, one a_0 row at a time per wave (rows w, w + 4, ..):
-    // the row's mode-1 result goes to this wave's own LDS, so no workgroup
-    // barrier separates the two modes
-    const float2* M1 = smat + (c * 3 + 1) * kR * kC;
-    const float2* M2 = smat + (c * 3 + 2) * kR * kC;
-    float2* t1 = sbuf2 + w * kR * kC * kQ;  // [j2][a1][q] of this wave's row
-    if (r1 > 0 && r2 > 0) {  // a child of rank 0 adds nothing
+    // row a0 of the block's true entries
+    if (a0 < c0 && blk < c1 && qn < Qa) {
+      float2* dst = coarse + ca.base + sg[0].pos(a0) * ca.stride[0] + sg[1].pos(blk) * ca.stride[1] + qn;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int a0 = 4 * s + w;
-        if (a0 < c0) {
-          // t1[j2][a1][q] = sum_j1 M1[j1][a1] sbuf1[a0][j1][j2][q]: a row has at
-          // most 8 positions j2, so blocks 0-7 and 8-15 of an instruction take
-          // two different tiles of a1 (the matrix operand is per block)
-          CAcc d[4];
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int t = 0; t < 4; ++t) czero4(d[t]);
-          tiles_lds_n((nt1 + 1) / 2, d, sbuf1 + (a0 * kR * kR + min(j2h, r2 - 1)) * kQ + qn, kR * kQ, M1,
-                      col1p, r1);
-          if (j2h < r2) {  // rows past c1 land in unread padding
-#pragma unroll
-            for (int tp = 0; tp < 2; ++tp)
-#pragma unroll
-              for (int v = 0; v < 4; ++v)
-                t1[(j2h * kC + 4 * (2 * tp + th) + v) * kQ + qn] = make_float2(d[tp].re[v], d[tp].im[v]);
-          }
-          // acc[s] += sum_j2 M2[j2][a2] t1[j2][a1][q], a1 = blk (the same wave
-          // wrote t1: its LDS operations complete in order)
-          tiles_lds_n(nt2, acc[s], t1 + min(blk, c1 - 1) * kQ + qn, kC * kQ, M2, col2, r2);
+        for (int v = 0; v < 4; ++v) {
+          const int a2 = 4 * t + v;
+          if (a2 < c2) dst[sg[2].pos(a2) * ca.stride[2]] = make_float2(acc[t].re[v], acc[t].im[v]);
         }
-      }
-    }
-    __syncthreads();  // sbuf1 is rewritten by the next child
-  }
-
-  // the block's true entries, once
-  CoarseAddr<3> ca;
-  ca.init(a, ci, beta, q0);
-  if (blk < c1 && qn < Qa) {
-    const long long rowb = ca.base + sg[1].pos(blk) * ca.stride[1] + qn;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int a0 = 4 * s + w;
-      if (a0 < c0) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int a2 = 4 * t + v;
-            if (a2 < c2)
-              coarse[rowb + sg[0].pos(a0) * ca.stride[0] + sg[2].pos(a2) * ca.stride[2]] =
-                  make_float2(acc[s][t].re[v], acc[s][t].im[v]);
-          }
-      }
     }
   }
 }
