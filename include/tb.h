@@ -280,10 +280,10 @@ typedef struct {
                              levels on 4 x 4 matrix-core blocks, four right-hand sides per
                              workgroup (fine ranks up to 8, coarse blocks up to 16 per mode):
                              fan-ins take the children in turn and accumulate the coarse
-                             block in registers, a group of rows at a time, fan-outs take one
-                             fine block per workgroup
-                             in two halves of its first mode; also the fan-in leaves (target
-                             leaf, source leaf of the adjoint) with leaf size 8 */
+                             block in registers, a group of rows at a time; fan-outs take one
+                             fine block per workgroup in two halves of its first mode; also
+                             the fan-in leaves (target leaf, source leaf of the adjoint) with
+                             leaf size 8 */
   int rhs_per_thread;     /* fan-out / fan-in kernels: 1 or 4 right-hand sides per thread
                              (4 needs a right-hand-side tile of 4 or 8) */
   int flat_stage;         /* transfer stages and leaves: 1 = flat staging (FP32 applies), one
